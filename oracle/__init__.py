@@ -1,0 +1,216 @@
+"""CPU oracle for per-pixel weighted reservoir sampling (arXiv 2510.03964).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` import this package.  The product package
+never imports it, and this package never imports the product package.
+
+The arithmetic lives in ``fwrs_oracle.c`` (plain C, one IEEE binary32 operation
+at a time for everything that decides a slot, binary64 for the resolve); this
+module only marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+BIAS_NONE = 0
+BIAS_BERNOULLI = 1
+
+_lib = None
+
+
+class Params(C.Structure):
+    """Mirror of ``fwrs_oracle_params`` (fwrs_oracle.h)."""
+
+    _fields_ = [
+        ("seed", C.c_uint32),
+        ("stream_id", C.c_uint32),
+        ("fov_deg", C.c_float),
+        ("fovea_radius_px", C.c_float),
+        ("bias_mode", C.c_uint32),
+        ("r_m", C.c_float),
+        ("a_k", C.c_float),
+        ("r2k", C.c_float),
+        ("rek", C.c_float),
+    ]
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def lib(path: str | None = None):
+    """Load (building if needed) the oracle shared library."""
+    global _lib
+    if path is not None:
+        return _bind(C.CDLL(path))
+    if _lib is None:
+        override = os.environ.get("FWRS_ORACLE_LIB")   # a variant built by the mutation tests
+        if override:
+            _lib = _bind(C.CDLL(override))
+            return _lib
+        p = _build.LIB
+        if not os.path.exists(p) or os.path.getmtime(p) < os.path.getmtime(_build.SRC):
+            _build.build(force=True)
+        _lib = _bind(C.CDLL(p))
+    return _lib
+
+
+def _bind(L):
+    vp = C.c_void_p
+    L.fwrs_oracle_default_params.argtypes = [C.c_int, C.POINTER(Params)]
+    L.fwrs_oracle_create.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(Params)]
+    L.fwrs_oracle_create.restype = vp
+    L.fwrs_oracle_destroy.argtypes = [vp]
+    L.fwrs_oracle_push.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint8), C.c_float, C.c_float]
+    L.fwrs_oracle_resolve.argtypes = [vp, C.POINTER(C.c_double)]
+    L.fwrs_oracle_frame_index.argtypes = [vp]
+    L.fwrs_oracle_frame_index.restype = C.c_uint32
+    L.fwrs_oracle_constants.argtypes = [vp, C.POINTER(C.c_float)]
+    L.fwrs_oracle_state.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint32), C.POINTER(C.c_float),
+                                    C.POINTER(C.c_uint32), C.POINTER(C.c_float)]
+    L.fwrs_oracle_philox_many.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                          C.POINTER(C.c_uint32), C.c_size_t]
+    L.fwrs_oracle_exp2p_many.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_size_t]
+    L.fwrs_oracle_density_many.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_size_t]
+    L.fwrs_oracle_eccentricity.argtypes = [vp, C.c_int, C.c_int, C.c_float, C.c_float]
+    L.fwrs_oracle_eccentricity.restype = C.c_float
+    L.fwrs_oracle_weight.argtypes = [vp, C.c_int, C.c_int, C.c_uint8, C.c_float, C.c_float]
+    L.fwrs_oracle_weight.restype = C.c_float
+    L.fwrs_oracle_weight_image.argtypes = [vp, C.POINTER(C.c_uint8), C.c_float, C.c_float,
+                                           C.POINTER(C.c_float)]
+    L.fwrs_oracle_trials.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(Params), C.c_int, C.c_int,
+                                     C.c_uint32, C.c_int, C.c_int, C.POINTER(C.c_float),
+                                     C.POINTER(C.c_uint8), C.POINTER(C.c_float), C.POINTER(C.c_uint32),
+                                     C.POINTER(C.c_float)]
+    L.fwrs_oracle_trials.restype = C.c_int
+    return L
+
+
+def default_params(width: int, **overrides) -> Params:
+    p = Params()
+    lib().fwrs_oracle_default_params(int(width), C.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+@dataclass
+class State:
+    wsum: np.ndarray   # [H, W] float32
+    cnt: np.ndarray    # [H, W] uint32
+    wt: np.ndarray     # [k, H, W] float32
+    idx: np.ndarray    # [k, H, W] uint32
+    col: np.ndarray    # [k, 3, H, W] float32
+
+
+class Oracle:
+    """One pixel-stream context of the oracle (a width x height image, k slots)."""
+
+    def __init__(self, width: int, height: int, k: int, params: Params | None = None, library=None):
+        self._L = library or lib()
+        self.width, self.height, self.k = int(width), int(height), int(k)
+        self.params = params if params is not None else default_params(width)
+        h = self._L.fwrs_oracle_create(self.width, self.height, self.k, C.byref(self.params))
+        if not h:
+            raise ValueError(f"oracle create failed for {width}x{height} k={k}")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.fwrs_oracle_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    @property
+    def t(self) -> int:
+        return int(self._L.fwrs_oracle_frame_index(self._h))
+
+    def push(self, color: np.ndarray, level: np.ndarray, gx: float, gy: float) -> None:
+        color = np.ascontiguousarray(color, dtype=np.float32)
+        level = np.ascontiguousarray(level, dtype=np.uint8)
+        assert color.shape == (self.height, self.width, 3) and level.shape == (self.height, self.width)
+        self._L.fwrs_oracle_push(self._h, _ptr(color, C.c_float), _ptr(level, C.c_uint8),
+                                 C.c_float(gx), C.c_float(gy))
+
+    def resolve(self) -> np.ndarray:
+        out = np.empty((self.height, self.width, 3), dtype=np.float64)
+        self._L.fwrs_oracle_resolve(self._h, _ptr(out, C.c_double))
+        return out
+
+    def state(self) -> State:
+        H, W, k = self.height, self.width, self.k
+        s = State(np.empty((H, W), np.float32), np.empty((H, W), np.uint32), np.empty((k, H, W), np.float32),
+                  np.empty((k, H, W), np.uint32), np.empty((k, 3, H, W), np.float32))
+        self._L.fwrs_oracle_state(self._h, _ptr(s.wsum, C.c_float), _ptr(s.cnt, C.c_uint32),
+                                  _ptr(s.wt, C.c_float), _ptr(s.idx, C.c_uint32), _ptr(s.col, C.c_float))
+        return s
+
+    def constants(self) -> dict:
+        out = np.empty(9, np.float32)
+        self._L.fwrs_oracle_constants(self._h, _ptr(out, C.c_float))
+        names = ["A", "B", "IR2", "IRM", "C", "ppd", "iPPD", "rf", "Drf"]
+        return {n: np.float32(v) for n, v in zip(names, out)}
+
+    def density(self, e: np.ndarray) -> np.ndarray:
+        e = np.ascontiguousarray(e, dtype=np.float32)
+        out = np.empty_like(e)
+        self._L.fwrs_oracle_density_many(self._h, _ptr(e, C.c_float), _ptr(out, C.c_float), e.size)
+        return out
+
+    def eccentricity(self, x: int, y: int, gx: float, gy: float) -> np.float32:
+        return np.float32(self._L.fwrs_oracle_eccentricity(self._h, int(x), int(y), C.c_float(gx), C.c_float(gy)))
+
+    def weight(self, x: int, y: int, level: int, gx: float, gy: float) -> np.float32:
+        return np.float32(self._L.fwrs_oracle_weight(self._h, int(x), int(y), int(level),
+                                                     C.c_float(gx), C.c_float(gy)))
+
+    def weight_image(self, level: np.ndarray, gx: float, gy: float) -> np.ndarray:
+        level = np.ascontiguousarray(level, dtype=np.uint8)
+        out = np.empty((self.height, self.width), np.float32)
+        self._L.fwrs_oracle_weight_image(self._h, _ptr(level, C.c_uint8), C.c_float(gx), C.c_float(gy),
+                                         _ptr(out, C.c_float))
+        return out
+
+
+def philox(keys: np.ndarray, ctrs: np.ndarray) -> np.ndarray:
+    """Philox4x32-10 blocks: keys [n, 2] uint32, counters [n, 4] uint32 -> [n, 4] uint32."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint32)
+    ctrs = np.ascontiguousarray(ctrs, dtype=np.uint32)
+    n = ctrs.shape[0]
+    out = np.empty((n, 4), np.uint32)
+    lib().fwrs_oracle_philox_many(_ptr(keys, C.c_uint32), _ptr(ctrs, C.c_uint32), _ptr(out, C.c_uint32), n)
+    return out
+
+
+def exp2p(y: np.ndarray) -> np.ndarray:
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    out = np.empty_like(y)
+    lib().fwrs_oracle_exp2p_many(_ptr(y, C.c_float), _ptr(out, C.c_float), y.size)
+    return out
+
+
+def trials(width: int, height: int, k: int, params: Params, px: int, py: int, seed0: int, n_trials: int,
+           rgb: np.ndarray, lev: np.ndarray, gaze: np.ndarray, library=None):
+    """Final slot frame indices [n_trials, k] (and final w_sum [n_trials]) of the single stream at
+    pixel (px, py), repeated with Philox seeds seed0, seed0 + 1, ..."""
+    L = library or lib()
+    rgb = np.ascontiguousarray(rgb, dtype=np.float32).reshape(-1, 3)
+    lev = np.ascontiguousarray(lev, dtype=np.uint8).reshape(-1)
+    gaze = np.ascontiguousarray(gaze, dtype=np.float32).reshape(-1, 2)
+    n_frames = lev.size
+    assert rgb.shape[0] == n_frames and gaze.shape[0] == n_frames
+    idx = np.empty((n_trials, k), np.uint32)
+    wsum = np.empty(n_trials, np.float32)
+    rc = L.fwrs_oracle_trials(width, height, k, C.byref(params), px, py, seed0, n_trials, n_frames,
+                              _ptr(rgb, C.c_float), _ptr(lev, C.c_uint8), _ptr(gaze, C.c_float),
+                              _ptr(idx, C.c_uint32), _ptr(wsum, C.c_float))
+    if rc != 0:
+        raise ValueError(f"oracle trials failed ({rc})")
+    return idx, wsum

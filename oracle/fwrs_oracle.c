@@ -1,0 +1,392 @@
+/*
+ * CPU oracle for per-pixel weighted reservoir sampling on foveated frames.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  The product path never
+ * links, imports or calls it; it shares no code, header, constant or table
+ * with the GPU library.
+ *
+ * Paper: "Enhancing Foveated Rendering with Weighted Reservoir Sampling"
+ * (MIG '25, arXiv 2510.03964).  Section / equation / algorithm numbers below
+ * are the paper's:
+ *   Sec. 3.1, Eq. 1      A-Chao selection probability w_i / sum_{j<=i} w_j
+ *   Sec. 3.1, Alg. 1     A-Chao update of an n = 1 reservoir
+ *   Sec. 3.2, Alg. 2     Combine Reservoirs (keep R1 iff rand*(W1+W2) <= W1)
+ *   Sec. 4.1             one independent stream per pixel; one new candidate
+ *                        per frame; combine temporal reservoir R1 with R2 =
+ *                        the new candidate
+ *   Sec. 4.1, Eq. 3      Watson retinal density d(e)
+ *   Sec. 4.1, Eq. 4      weight w(e) = 1 inside the fovea, d(e)/d(r_f) outside
+ *   Sec. 4.2, Eq. 5, 6   Bernoulli survival bias applied to R1.w_sum before
+ *                        the combine
+ *
+ * Precision.  Every quantity that decides which sample a slot keeps (the
+ * weight, the biased weight sum, the uniform variate and the comparison) is
+ * evaluated in IEEE binary32, round-to-nearest-even, one operation at a time
+ * (build with -ffp-contract=off -fno-fast-math).  The decision is an integer
+ * result, so it is taken in the precision the GPU kernel uses.  The resolve
+ * (the weighted mean of the slots) has a plain definition and is evaluated in
+ * binary64.
+ *
+ * Readings of the paper that this file fixes (the paper does not state them):
+ *   - k slots per pixel are k independent n = 1 A-Chao reservoirs that see the
+ *     same candidate stream and share w_sum; each slot draws its own variate.
+ *     At k = 1 this is exactly the paper's reservoir.
+ *   - rand is uniform on (0, 1] with 24 bits: u = ((bits >> 8) + 1) * 2^-24,
+ *     so an empty reservoir always takes its first candidate.
+ *   - rand comes from Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11),
+ *     key = (seed, stream_id), counter = (pixel, frame, block, 0); slot j
+ *     uses word j % 4 of block j / 4.
+ *   - eccentricity e (degrees) = pixel-centre distance to the gaze point
+ *     divided by ppd = width / fov_deg; r_f = fovea_radius_px / ppd.
+ *   - r_m (not printed in the paper) defaults to 41.03 degrees.
+ *   - level 0 ("rendered at full fidelity") has weight 1.
+ *   - the stored w_sum after a frame is biased W1 + w (Alg. 2 sums the
+ *     biased R1.w_sum and R2.w_sum).
+ *   - resolve: out = sum_j wt_j * col_j / sum_j wt_j over the slots, with the
+ *     render-time weights; 0 before the first frame.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "fwrs_oracle.h"
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, as defined by Salmon et al., SC'11: a 4-word counter and a  */
+/* 2-word key; each round multiplies words 0 and 2 by fixed odd constants,    */
+/* takes the high and low halves of the 64-bit products, xors the high halves */
+/* with the other two words and the round key, and permutes; the key is       */
+/* advanced by the two Weyl constants between rounds.                         */
+/* ------------------------------------------------------------------------ */
+#define PHILOX_MUL_A 0xD2511F53u
+#define PHILOX_MUL_B 0xCD9E8D57u
+#define PHILOX_WEYL_A 0x9E3779B9u
+#define PHILOX_WEYL_B 0xBB67AE85u
+
+void fwrs_oracle_philox(const uint32_t key_in[2], const uint32_t ctr_in[4], uint32_t out[4])
+{
+    uint32_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_WEYL_A;
+            k1 += PHILOX_WEYL_B;
+        }
+        uint64_t pa = (uint64_t)PHILOX_MUL_A * (uint64_t)x0;
+        uint64_t pb = (uint64_t)PHILOX_MUL_B * (uint64_t)x2;
+        uint32_t hi_a = (uint32_t)(pa >> 32), lo_a = (uint32_t)pa;
+        uint32_t hi_b = (uint32_t)(pb >> 32), lo_b = (uint32_t)pb;
+        uint32_t y0 = hi_b ^ x1 ^ k0;
+        uint32_t y1 = lo_b;
+        uint32_t y2 = hi_a ^ x3 ^ k1;
+        uint32_t y3 = lo_a;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2^y for y <= 0: exact range reduction y = n + f with n = rint(y) and       */
+/* |f| <= 1/2, then the degree-7 Taylor polynomial of 2^f = exp(f ln 2) in    */
+/* Horner form (one multiply and one add per step), then scaling by 2^n.      */
+/* Coefficient i is the binary32 rounding of (ln 2)^i / i!.                   */
+/* ------------------------------------------------------------------------ */
+static float exp2_coef[8];
+
+static void init_exp2_coef(void)
+{
+    /* (ln 2)^i / i! accumulated in binary64, then rounded once to binary32. */
+    const double ln2 = 0.69314718055994530942;
+    double c = 1.0;
+    for (int i = 0; i < 8; ++i) {
+        if (i > 0) c = c * ln2 / (double)i;
+        exp2_coef[i] = (float)c;
+    }
+}
+
+float fwrs_oracle_exp2p(float y)
+{
+    if (exp2_coef[0] != 1.0f) init_exp2_coef();
+    float n = rintf(y);
+    float f = y - n;
+    float p = exp2_coef[7];
+    for (int i = 6; i >= 0; --i) {
+        p = p * f;
+        p = p + exp2_coef[i];
+    }
+    return ldexpf(p, (int)n);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eq. 3 multiplied through by (1 + e/r_2k)^2; the 2 d_c(0) factor cancels in */
+/* Eq. 4 and is dropped:                                                      */
+/*   d(e) ~ num(e) / den(e),                                                  */
+/*   num(e) = a_k + (1 - a_k) exp(-e / r_ek) (1 + e/r_2k)^2,                  */
+/*   den(e) = (1 + e/r_2k)^2 (1 + e/r_m).                                     */
+/* exp(-e / r_ek) = 2^(-e log2(e) / r_ek).                                    */
+/* ------------------------------------------------------------------------ */
+static void density_terms(const fwrs_oracle* o, float e, float* num, float* den)
+{
+    float t1 = 1.0f + e * o->IRM;
+    float t2 = 1.0f + e * o->IR2;
+    float T = t2 * t2;
+    float E = fwrs_oracle_exp2p(-(e * o->C));
+    *num = o->A + (o->B * E) * T;
+    *den = T * t1;
+}
+
+float fwrs_oracle_density(const fwrs_oracle* o, float e)
+{
+    float num, den;
+    density_terms(o, e, &num, &den);
+    return num / den;
+}
+
+float fwrs_oracle_eccentricity(const fwrs_oracle* o, int x, int y, float gx, float gy)
+{
+    float dx = ((float)x + 0.5f) - gx;
+    float dy = ((float)y + 0.5f) - gy;
+    return sqrtf(dx * dx + dy * dy) * o->iPPD;
+}
+
+/* Eq. 4, with level 0 (a pixel rendered at full fidelity this frame) scored 1. */
+float fwrs_oracle_weight(const fwrs_oracle* o, int x, int y, uint8_t level, float gx, float gy)
+{
+    float e = fwrs_oracle_eccentricity(o, x, y, gx, gy);
+    if (level == 0 || e <= o->rf) return 1.0f;
+    float num, den;
+    density_terms(o, e, &num, &den);
+    return fminf(1.0f, num / (den * o->Drf));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Context                                                                    */
+/* ------------------------------------------------------------------------ */
+void fwrs_oracle_default_params(int width, fwrs_oracle_params* p)
+{
+    p->seed = 0;
+    p->stream_id = 0;
+    p->fov_deg = 70.0f;
+    p->fovea_radius_px = 0.05f * (float)width;
+    p->bias_mode = FWRS_ORACLE_BIAS_BERNOULLI;
+    p->r_m = 41.03f;       /* not printed in the paper; Watson (2014) */
+    p->a_k = 0.9851f;      /* Sec. 4.1, parameters of Eq. 3 */
+    p->r2k = 1.058f;
+    p->rek = 22.14f;
+}
+
+static void derive_constants(fwrs_oracle* o)
+{
+    const fwrs_oracle_params* p = &o->prm;
+    o->A = p->a_k;
+    o->B = 1.0f - p->a_k;
+    o->IR2 = 1.0f / p->r2k;
+    o->IRM = 1.0f / p->r_m;
+    o->C = 1.44269504088896341f / p->rek;   /* log2(e) / r_ek */
+    o->ppd = (float)o->width / p->fov_deg;
+    o->iPPD = 1.0f / o->ppd;
+    o->rf = p->fovea_radius_px * o->iPPD;
+    float num, den;
+    density_terms(o, o->rf, &num, &den);
+    o->Drf = num / den;
+}
+
+fwrs_oracle* fwrs_oracle_create(int width, int height, int k, const fwrs_oracle_params* p)
+{
+    if (width <= 0 || height <= 0 || k < 1 || k > 16) return NULL;
+    fwrs_oracle* o = (fwrs_oracle*)calloc(1, sizeof(fwrs_oracle));
+    if (!o) return NULL;
+    o->width = width;
+    o->height = height;
+    o->k = k;
+    if (p) o->prm = *p; else fwrs_oracle_default_params(width, &o->prm);
+    size_t n = (size_t)width * (size_t)height;
+    o->wsum = (float*)calloc(n, sizeof(float));
+    o->cnt = (uint32_t*)calloc(n, sizeof(uint32_t));
+    o->wt = (float*)calloc(n * (size_t)k, sizeof(float));
+    o->idx = (uint32_t*)malloc(n * (size_t)k * sizeof(uint32_t));
+    o->col = (float*)calloc(n * (size_t)k * 3, sizeof(float));
+    if (!o->wsum || !o->cnt || !o->wt || !o->idx || !o->col) {
+        fwrs_oracle_destroy(o);
+        return NULL;
+    }
+    for (size_t i = 0; i < n * (size_t)k; ++i) o->idx[i] = 0xFFFFFFFFu;   /* empty slot */
+    derive_constants(o);
+    return o;
+}
+
+void fwrs_oracle_destroy(fwrs_oracle* o)
+{
+    if (!o) return;
+    free(o->wsum); free(o->cnt); free(o->wt); free(o->idx); free(o->col);
+    free(o);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One frame of one pixel stream (Sec. 4.1, 4.2):                             */
+/*   R2 = {x_new, w} (Eq. 4);                                                 */
+/*   bias R1.w_sum by the survival probability of Eq. 5 (Eq. 6), BERNOULLI;   */
+/*   combine per Alg. 2, independently in every slot;                         */
+/*   R_out.w_sum = biased R1.w_sum + w, R_out.m = R1.m + 1.                   */
+/* The pixel's state lives at stride `n` (pixels per plane) from wsum/cnt.    */
+/* ------------------------------------------------------------------------ */
+static void update_pixel(const fwrs_oracle* o, int x, int y, uint32_t p, uint32_t t,
+                         const float rgb[3], uint8_t level, float gx, float gy,
+                         float* wsum, uint32_t* cnt, float* wt, uint32_t* idx, float* col, size_t n)
+{
+    const int k = o->k;
+    float w = fwrs_oracle_weight(o, x, y, level, gx, gy);
+    float W1 = *wsum;
+    float W1b = W1;
+    if (o->prm.bias_mode == FWRS_ORACLE_BIAS_BERNOULLI) {
+        float total = W1 + w;          /* R1.w_sum + R2.w_sum */
+        float q = w / total;           /* chance that R2 replaces R1, Eq. 5 */
+        float survive = 1.0f - q;      /* Eq. 5 */
+        W1b = W1 * survive;            /* Eq. 6 */
+    }
+    float s = W1b + w;                 /* Alg. 2: R_out.w_sum */
+
+    uint32_t key[2] = {o->prm.seed, o->prm.stream_id};
+    uint32_t words[4];
+    int have_block = -1;
+    for (int j = 0; j < k; ++j) {
+        int b = j / 4;
+        if (b != have_block) {
+            uint32_t ctr[4] = {p, t, (uint32_t)b, 0u};
+            fwrs_oracle_philox(key, ctr, words);
+            have_block = b;
+        }
+        float u = (float)((words[j % 4] >> 8) + 1u) * 0x1p-24f;   /* rand in (0, 1] */
+        /* Alg. 2 keeps R1 when rand * (W1 + W2) <= W1; otherwise R2 wins. */
+        if (u * s > W1b) {
+            col[((size_t)j * 3 + 0) * n] = rgb[0];
+            col[((size_t)j * 3 + 1) * n] = rgb[1];
+            col[((size_t)j * 3 + 2) * n] = rgb[2];
+            wt[(size_t)j * n] = w;
+            idx[(size_t)j * n] = t;
+        }
+    }
+    *wsum = s;
+    *cnt = *cnt + 1u;
+}
+
+void fwrs_oracle_push(fwrs_oracle* o, const float* color, const uint8_t* level, float gx, float gy)
+{
+    const size_t n = (size_t)o->width * (size_t)o->height;
+    for (int y = 0; y < o->height; ++y) {
+        for (int x = 0; x < o->width; ++x) {
+            size_t p = (size_t)y * (size_t)o->width + (size_t)x;
+            update_pixel(o, x, y, (uint32_t)p, o->t, color + 3 * p, level[p], gx, gy,
+                         o->wsum + p, o->cnt + p, o->wt + p, o->idx + p, o->col + p, n);
+        }
+    }
+    o->t += 1u;
+}
+
+/* Weighted combination of the k slots (the k-slot resolve; at k = 1 it is the
+ * paper's output R_out.x).  Binary64 from the stored binary32 values. */
+void fwrs_oracle_resolve(const fwrs_oracle* o, double* out)
+{
+    const size_t n = (size_t)o->width * (size_t)o->height;
+    for (size_t p = 0; p < n; ++p) {
+        if (o->cnt[p] == 0) {
+            out[3 * p + 0] = 0.0; out[3 * p + 1] = 0.0; out[3 * p + 2] = 0.0;
+            continue;
+        }
+        double total = 0.0;
+        for (int j = 0; j < o->k; ++j) total += (double)o->wt[(size_t)j * n + p];
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int j = 0; j < o->k; ++j)
+                acc += (double)o->wt[(size_t)j * n + p] * (double)o->col[((size_t)j * 3 + c) * n + p];
+            out[3 * p + c] = acc / total;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Accessors and vector helpers for the tests.                                */
+/* ------------------------------------------------------------------------ */
+uint32_t fwrs_oracle_frame_index(const fwrs_oracle* o) { return o->t; }
+
+void fwrs_oracle_constants(const fwrs_oracle* o, float out[9])
+{
+    out[0] = o->A; out[1] = o->B; out[2] = o->IR2; out[3] = o->IRM; out[4] = o->C;
+    out[5] = o->ppd; out[6] = o->iPPD; out[7] = o->rf; out[8] = o->Drf;
+}
+
+void fwrs_oracle_state(const fwrs_oracle* o, float* wsum, uint32_t* cnt, float* wt, uint32_t* idx, float* col)
+{
+    const size_t n = (size_t)o->width * (size_t)o->height;
+    const size_t k = (size_t)o->k;
+    if (wsum) memcpy(wsum, o->wsum, n * sizeof(float));
+    if (cnt) memcpy(cnt, o->cnt, n * sizeof(uint32_t));
+    if (wt) memcpy(wt, o->wt, n * k * sizeof(float));
+    if (idx) memcpy(idx, o->idx, n * k * sizeof(uint32_t));
+    if (col) memcpy(col, o->col, n * k * 3 * sizeof(float));
+}
+
+void fwrs_oracle_philox_many(const uint32_t* keys, const uint32_t* ctrs, uint32_t* out, size_t count)
+{
+    for (size_t i = 0; i < count; ++i) fwrs_oracle_philox(keys + 2 * i, ctrs + 4 * i, out + 4 * i);
+}
+
+void fwrs_oracle_exp2p_many(const float* y, float* out, size_t count)
+{
+    for (size_t i = 0; i < count; ++i) out[i] = fwrs_oracle_exp2p(y[i]);
+}
+
+void fwrs_oracle_density_many(const fwrs_oracle* o, const float* e, float* out, size_t count)
+{
+    for (size_t i = 0; i < count; ++i) out[i] = fwrs_oracle_density(o, e[i]);
+}
+
+void fwrs_oracle_weight_image(const fwrs_oracle* o, const uint8_t* level, float gx, float gy, float* out)
+{
+    for (int y = 0; y < o->height; ++y)
+        for (int x = 0; x < o->width; ++x) {
+            size_t p = (size_t)y * (size_t)o->width + (size_t)x;
+            out[p] = fwrs_oracle_weight(o, x, y, level[p], gx, gy);
+        }
+}
+
+/* Many independent runs of the single stream at pixel (px, py) of a
+ * width x height context, differing only in the Philox seed (seed0 + trial).
+ * Frame f supplies colour rgb[3f..3f+2], level lev[f] and gaze gaze[2f..2f+1].
+ * Writes the final frame index of every slot to idx_out[trial * k + j] and the
+ * final w_sum to wsum_out[trial] (if not NULL). */
+int fwrs_oracle_trials(int width, int height, int k, const fwrs_oracle_params* p, int px, int py,
+                       uint32_t seed0, int n_trials, int n_frames, const float* rgb, const uint8_t* lev,
+                       const float* gaze, uint32_t* idx_out, float* wsum_out)
+{
+    if (px < 0 || py < 0 || px >= width || py >= height) return 1;
+    fwrs_oracle* o = fwrs_oracle_create(1, 1, k, p);   /* scratch holder for one pixel's state */
+    if (!o) return 2;
+    /* The per-pixel math uses the full context's geometry. */
+    o->width = width;
+    o->height = height;
+    derive_constants(o);
+    const uint32_t pix = (uint32_t)((size_t)py * (size_t)width + (size_t)px);
+    for (int trial = 0; trial < n_trials; ++trial) {
+        o->prm.seed = seed0 + (uint32_t)trial;
+        o->wsum[0] = 0.0f;
+        o->cnt[0] = 0u;
+        for (int j = 0; j < k; ++j) {
+            o->wt[j] = 0.0f;
+            o->idx[j] = 0xFFFFFFFFu;
+            o->col[3 * j + 0] = o->col[3 * j + 1] = o->col[3 * j + 2] = 0.0f;
+        }
+        for (int f = 0; f < n_frames; ++f)
+            update_pixel(o, px, py, pix, (uint32_t)f, rgb + 3 * f, lev[f], gaze[2 * f], gaze[2 * f + 1],
+                         o->wsum, o->cnt, o->wt, o->idx, o->col, 1);
+        for (int j = 0; j < k; ++j) idx_out[(size_t)trial * (size_t)k + (size_t)j] = o->idx[j];
+        if (wsum_out) wsum_out[trial] = o->wsum[0];
+    }
+    o->width = 1;
+    o->height = 1;
+    fwrs_oracle_destroy(o);
+    return 0;
+}

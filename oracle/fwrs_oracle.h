@@ -1,0 +1,76 @@
+/*
+ * CPU oracle for per-pixel weighted reservoir sampling on foveated frames
+ * (arXiv 2510.03964, Sec. 3.1, 3.2, 4.1, 4.2).  TEST INFRASTRUCTURE ONLY:
+ * loaded by the tests, the smoke check and the benchmark's CPU baseline, never
+ * by the product path.  Shares nothing with the GPU library.
+ *
+ * Layout of the oracle's own state, N = width * height, p = y * width + x:
+ *   wsum[p]              binary32, the reservoir's w_sum (Alg. 2)
+ *   cnt[p]               uint32, candidates seen (Alg. 2's m)
+ *   wt[j * N + p]        binary32, render-time weight of the sample in slot j
+ *   idx[j * N + p]       uint32, frame index of the sample in slot j
+ *                        (0xFFFFFFFF while empty)
+ *   col[(j*3 + c)*N + p] binary32, channel c of the sample in slot j
+ * Frames are [H][W][3] binary32 (HWC) with a [H][W] uint8 level map.
+ */
+#ifndef FWRS_ORACLE_H
+#define FWRS_ORACLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FWRS_ORACLE_BIAS_NONE 0u
+#define FWRS_ORACLE_BIAS_BERNOULLI 1u
+
+typedef struct fwrs_oracle_params {
+    uint32_t seed;            /* Philox key word 0 */
+    uint32_t stream_id;       /* Philox key word 1 */
+    float fov_deg;            /* horizontal field of view covered by `width` pixels */
+    float fovea_radius_px;    /* r_f in pixels */
+    uint32_t bias_mode;       /* FWRS_ORACLE_BIAS_* */
+    float r_m, a_k, r2k, rek; /* Eq. 3 parameters */
+} fwrs_oracle_params;
+
+typedef struct fwrs_oracle {
+    int width, height, k;
+    fwrs_oracle_params prm;
+    uint32_t t;
+    float A, B, IR2, IRM, C, ppd, iPPD, rf, Drf;
+    float* wsum;
+    uint32_t* cnt;
+    float* wt;
+    uint32_t* idx;
+    float* col;
+} fwrs_oracle;
+
+void fwrs_oracle_default_params(int width, fwrs_oracle_params* p);
+fwrs_oracle* fwrs_oracle_create(int width, int height, int k, const fwrs_oracle_params* p);
+void fwrs_oracle_destroy(fwrs_oracle* o);
+void fwrs_oracle_push(fwrs_oracle* o, const float* color, const uint8_t* level, float gx, float gy);
+void fwrs_oracle_resolve(const fwrs_oracle* o, double* out);
+uint32_t fwrs_oracle_frame_index(const fwrs_oracle* o);
+void fwrs_oracle_constants(const fwrs_oracle* o, float out[9]);
+void fwrs_oracle_state(const fwrs_oracle* o, float* wsum, uint32_t* cnt, float* wt, uint32_t* idx, float* col);
+
+void fwrs_oracle_philox(const uint32_t key[2], const uint32_t ctr[4], uint32_t out[4]);
+void fwrs_oracle_philox_many(const uint32_t* keys, const uint32_t* ctrs, uint32_t* out, size_t count);
+float fwrs_oracle_exp2p(float y);
+void fwrs_oracle_exp2p_many(const float* y, float* out, size_t count);
+float fwrs_oracle_density(const fwrs_oracle* o, float e);
+void fwrs_oracle_density_many(const fwrs_oracle* o, const float* e, float* out, size_t count);
+float fwrs_oracle_eccentricity(const fwrs_oracle* o, int x, int y, float gx, float gy);
+float fwrs_oracle_weight(const fwrs_oracle* o, int x, int y, uint8_t level, float gx, float gy);
+void fwrs_oracle_weight_image(const fwrs_oracle* o, const uint8_t* level, float gx, float gy, float* out);
+int fwrs_oracle_trials(int width, int height, int k, const fwrs_oracle_params* p, int px, int py,
+                       uint32_t seed0, int n_trials, int n_frames, const float* rgb, const uint8_t* lev,
+                       const float* gaze, uint32_t* idx_out, float* wsum_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

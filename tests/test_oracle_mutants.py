@@ -1,0 +1,71 @@
+"""The oracle's pins detect plausible mistakes (CPU only).
+
+Each case plants one mistake in a copy of the oracle's C source (a dropped
+term, a wrong sign, a wrong index, a transposed operand ...), builds it, and
+runs the pin suite against the mutant through FWRS_ORACLE_LIB.  The suite must
+fail for every mutant.  The product library is not involved.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+sys.path.insert(0, ROOT)
+
+from oracle import build as oracle_build  # noqa: E402
+
+MUTANTS = {
+    "philox_hi_lo_swapped": ("uint32_t y1 = lo_b;", "uint32_t y1 = hi_b;"),
+    "philox_key_not_bumped": ("k1 += PHILOX_WEYL_B;", "k1 += 0u;"),
+    "exp2_sign_of_f": ("p = p * f;", "p = p * -f;"),
+    "density_drops_r_m_term": ("*den = T * t1;", "*den = T;"),
+    "density_exponent_sign": ("-(e * o->C)", "(e * o->C)"),
+    "weight_fovea_test_inverted": ("if (level == 0 || e <= o->rf) return 1.0f;",
+                                   "if (level == 0 || e >= o->rf) return 1.0f;"),
+    "weight_level_ignored": ("if (level == 0 || e <= o->rf)", "if (e <= o->rf)"),
+    "bias_survival_not_complemented": ("float survive = 1.0f - q;", "float survive = q;"),
+    "bias_dropped": ("W1b = W1 * survive;", "W1b = W1 * 1.0f;"),
+    "combine_direction": ("if (u * s > W1b) {", "if (u * s < W1b) {"),
+    "index_off_by_one": ("idx[(size_t)j * n] = t;", "idx[(size_t)j * n] = t + 1u;"),
+    "slots_share_one_word": ("words[j % 4] >> 8", "words[0] >> 8"),
+    "counter_pixel_frame_swapped": ("uint32_t ctr[4] = {p, t, (uint32_t)b, 0u};",
+                                    "uint32_t ctr[4] = {t, p, (uint32_t)b, 0u};"),
+    "uniform_not_offset": ("((words[j % 4] >> 8) + 1u)", "((words[j % 4] >> 8) + 0u)"),
+    "stored_wsum_unbiased": ("*wsum = s;", "*wsum = W1 + w;"),
+    "count_not_incremented": ("*cnt = *cnt + 1u;", "*cnt = *cnt;"),
+    "colour_channels_mixed": ("col[((size_t)j * 3 + 1) * n] = rgb[1];", "col[((size_t)j * 3 + 1) * n] = rgb[0];"),
+    "stored_weight_is_wsum": ("wt[(size_t)j * n] = w;", "wt[(size_t)j * n] = s;"),
+    "resolve_unnormalised": ("out[3 * p + c] = acc / total;", "out[3 * p + c] = acc;"),
+    "resolve_wrong_slot_weight": ("acc += (double)o->wt[(size_t)j * n + p] *", "acc += (double)o->wt[p] *"),
+}
+
+
+def _run_mutant(name, tmpdir):
+    old, new = MUTANTS[name]
+    src = open(oracle_build.SRC).read()
+    assert src.count(old) == 1, f"{name}: pattern must occur exactly once"
+    mpath = os.path.join(tmpdir, f"{name}.c")
+    with open(mpath, "w") as f:
+        f.write(src.replace(old, new))
+    lib = os.path.join(tmpdir, f"lib_{name}.so")
+    hdr_dir = os.path.dirname(oracle_build.SRC)
+    subprocess.run(["gcc", *oracle_build.CFLAGS, "-I", hdr_dir, "-o", lib, mpath, "-lm"], check=True,
+                   capture_output=True)
+    env = dict(os.environ, FWRS_ORACLE_LIB=lib, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(HERE, "test_oracle_pins.py")], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=600)
+    return name, r.returncode, r.stdout[-400:]
+
+
+def test_every_planted_mistake_fails_a_pin(tmp_path):
+    with cf.ThreadPoolExecutor(max_workers=6) as ex:
+        results = list(ex.map(lambda n: _run_mutant(n, str(tmp_path)), sorted(MUTANTS)))
+    survivors = [(n, out) for (n, rc, out) in results if rc == 0]
+    assert not survivors, f"mutants not caught by any pin: {[n for n, _ in survivors]}"
