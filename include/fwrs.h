@@ -1,0 +1,250 @@
+/*
+ * fwrs.h -- C ABI of the foveated weighted-reservoir-sampling library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method is the per-pixel weighted reservoir sampling of "Enhancing
+ * Foveated Rendering with Weighted Reservoir Sampling" (MIG '25, arXiv
+ * 2510.03964).  The problem statement (Sec. 4): every frame, each pixel is
+ * handed a freshly rendered sample at some foveation level, and the question
+ * is whether to keep that sample for display.  Each pixel location is an
+ * independent stream (Sec. 4.1); the new sample is scored with the retinal
+ * density weight of Eq. 3-4; the reservoir's running weight sum is biased by
+ * the Bernoulli survival probability of Eq. 5-6 (Sec. 4.2); then the temporal
+ * reservoir and the new sample are combined by Alg. 2 (Sec. 3.2).  This
+ * library keeps k such n = 1 reservoirs ("slots") per pixel that see the same
+ * candidates and w_sum and draw independent variates; k = 1 is exactly the
+ * paper's reservoir.  The displayed colour is the combination of the slots
+ * weighted by each kept sample's render-time weight (at k = 1: the kept sample,
+ * R_out.x).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Images are row-major, pixel p = y * width + x.  `color` and `out` are
+ *    [height][width][3] float32 (RGB, HWC); `level_map` is [height][width]
+ *    uint8 with 0 = rendered at full resolution this frame, 1 and 2 = reduced.
+ *  - Every buffer argument named color, level_map, out or arena is a DEVICE
+ *    pointer on the context's device; `host` arguments are host pointers.
+ *    Buffers are owned by the caller and must stay valid until the work
+ *    enqueued on the context's stream has completed (stream-ordered use).
+ *  - Gaze (gaze_x, gaze_y) is in continuous pixel coordinates of the same
+ *    image (pixel centres are at x + 0.5, y + 0.5).
+ *  - Calls that enqueue GPU work return as soon as it is enqueued.  An
+ *    asynchronous failure is reported by fwrs_sync (FWRS_E_HIP).
+ *  - Every call returns a status (FWRS_OK on success) except fwrs_state_bytes
+ *    and fwrs_strerror.  On FWRS_E_ARG nothing was enqueued and the context is
+ *    unchanged.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *
+ * Randomness: slot j of pixel p at frame t (t = 0, 1, ... counts the frames
+ * pushed into the context) draws word j % 4 of the Philox4x32-10 block with
+ * key (seed, stream_id) and counter (p, t, j / 4, 0) and reads it as
+ * u = ((word >> 8) + 1) * 2^-24 in (0, 1].  Results therefore do not depend on
+ * how frames are batched, on the launch configuration or on the device.
+ *
+ * Arithmetic: the weight, the biased weight sum and the keep/replace test are
+ * IEEE binary32 operations in a fixed order, without contraction into fused
+ * multiply-adds; the decisions (and so the kept frame indices and counts) are
+ * reproducible bit for bit.  The resolve is a binary32 weighted mean.
+ */
+#ifndef FWRS_H
+#define FWRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define FWRS_OK 0
+#define FWRS_E_ARG 1     /* invalid argument; nothing enqueued */
+#define FWRS_E_NOMEM 2   /* device or host allocation failed */
+#define FWRS_E_HIP 3     /* a HIP runtime call failed (possibly asynchronously) */
+#define FWRS_E_STATE 4   /* call not valid in the object's current state */
+
+/* ---- temporal bias modes (Sec. 4.2) ------------------------------------- */
+#define FWRS_BIAS_NONE 0u       /* plain Alg. 2: R1.w_sum is not biased */
+#define FWRS_BIAS_BERNOULLI 1u  /* Eq. 6: R1.w_sum *= 1 - w / (R1.w_sum + w) */
+
+/* Largest slot count per pixel. */
+#define FWRS_MAX_K 16
+
+/* Method parameters.
+ *   seed, stream_id   Philox key words.
+ *   fov_deg           horizontal field of view spanned by `width` pixels; the
+ *                     eccentricity of a pixel is its distance to the gaze in
+ *                     pixels divided by ppd = width / fov_deg (degrees).
+ *   fovea_radius_px   r_f in pixels; inside it the weight is 1 (Eq. 4).
+ *   bias_mode         FWRS_BIAS_*.
+ *   r_m, a_k, r2k, rek  parameters of the retinal density d(e) of Eq. 3
+ *                     (Sec. 4.1 prints a_k = 0.9851, r_2,k = 1.058,
+ *                     r_e,k = 22.14; r_m is not printed, default 41.03).
+ */
+typedef struct fwrs_params {
+    uint32_t seed;
+    uint32_t stream_id;
+    float fov_deg;
+    float fovea_radius_px;
+    uint32_t bias_mode;
+    float r_m;
+    float a_k;
+    float r2k;
+    float rek;
+} fwrs_params;
+
+typedef struct fwrs_ctx fwrs_ctx;
+
+/* Device-side view of a context's reservoir store (structure of arrays).
+ * Every plane holds `pitch` elements (pitch >= width * height, a multiple of
+ * 64); element p of a plane belongs to pixel p.
+ *   wsum[p]                 float32  w_sum of the pixel's reservoir (Alg. 2)
+ *   cnt[p]                  uint32   candidates seen, Alg. 2's m
+ *   wt[j * pitch + p]       float32  render-time weight of slot j's sample
+ *   idx[j * pitch + p]      uint32   frame index of slot j's sample
+ *                                    (0xFFFFFFFF while empty)
+ *   col[(j*3+c) * pitch + p] float32 channel c of slot j's sample
+ * The pointers are owned by the context (or by the caller's arena). */
+typedef struct fwrs_state_view {
+    int width, height, k;
+    uint32_t frame_index;   /* frames pushed so far */
+    size_t pitch;
+    float* wsum;
+    uint32_t* cnt;
+    float* wt;
+    uint32_t* idx;
+    float* col;
+} fwrs_state_view;
+
+/* Fills `p` with the defaults for an image `width` pixels wide: seed 0,
+ * stream 0, fov 70 degrees, fovea radius 5% of the width, BERNOULLI bias and
+ * the Eq. 3 parameters above.  FWRS_E_ARG if width <= 0 or p is NULL. */
+int fwrs_default_params(int width, fwrs_params* p);
+
+/* Device bytes of the reservoir store for a width x height image with k
+ * slots: 4 * pitch * (2 + 5k) plus a small statistics area, where pitch is
+ * width * height rounded up to 64.  Use it for admission control and to size
+ * a caller-provided arena.  Returns 0 for invalid sizes. */
+size_t fwrs_state_bytes(int width, int height, int k);
+
+/* Host bytes written by fwrs_download_state: width * height * (8 + 20k). */
+size_t fwrs_state_host_bytes(int width, int height, int k);
+
+/* Creates a context with fwrs_default_params(width) on the null stream of the
+ * current device.  The library allocates the reservoir store and clears it
+ * to the empty state (w_sum = 0, m = 0, wt = 0, col = 0, idx = 0xFFFFFFFF).
+ * FWRS_E_ARG: width or height <= 0, width * height >= 2^31, k outside
+ * [1, FWRS_MAX_K], out NULL.  FWRS_E_NOMEM: allocation failed. */
+int fwrs_create(int width, int height, int k, fwrs_ctx** out);
+
+/* As fwrs_create with explicit parameters, a borrowed HIP stream (hipStream_t,
+ * NULL = null stream) and an optional caller-owned device arena of
+ * `arena_bytes` >= fwrs_state_bytes(width, height, k) bytes, aligned to 256
+ * bytes, that the library uses for the store and never frees.  With arena ==
+ * NULL the library allocates.  The arena is cleared on the stream.
+ * FWRS_E_ARG also for: params NULL, fov_deg or fovea_radius_px not finite and
+ * > 0, bias_mode unknown, a_k outside (0, 1], r_m, r2k or rek not finite and
+ * > 0, arena too small or misaligned. */
+int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void* hip_stream, void* arena,
+                   size_t arena_bytes, fwrs_ctx** out);
+
+/* Waits for the context's stream, then frees library-owned memory.  A NULL
+ * context is accepted. */
+int fwrs_destroy(fwrs_ctx* ctx);
+
+/* Changes the stream later calls enqueue on (borrowed, NULL = null stream). */
+int fwrs_set_stream(fwrs_ctx* ctx, void* hip_stream);
+
+/* Enqueues a clear of the store to the empty state and sets the frame index
+ * to 0. */
+int fwrs_reset(fwrs_ctx* ctx);
+
+/* One frame of the method for every pixel (Sec. 4.1-4.2): weight w from the
+ * eccentricity to (gaze_x, gaze_y) (Eq. 3-4; level 0 scores 1), bias of the
+ * pixel's w_sum by Eq. 6 (BERNOULLI), then Alg. 2 per slot: the slot takes
+ * (color, w, frame index) when u * (W1' + w) > W1', and w_sum <- W1' + w,
+ * m <- m + 1.  Then the frame index advances by 1.
+ * FWRS_E_ARG: NULL pointers, non-finite gaze.  Level values above 2 are
+ * treated like 2 (reduced resolution).  FWRS_E_STATE: 2^32 - 1 frames pushed. */
+int fwrs_push_frame(fwrs_ctx* ctx, const float* color, const uint8_t* level_map, float gaze_x, float gaze_y);
+
+/* Enqueues the resolve into `out` ([height][width][3] float32): for each
+ * pixel sum_j wt_j * col_j / sum_j wt_j over its slots; 0 before any frame. */
+int fwrs_resolve(fwrs_ctx* ctx, float* out);
+
+/* fwrs_push_frame followed by fwrs_resolve in one pass over memory; the
+ * results are bit-identical to the two calls. */
+int fwrs_push_frame_resolve(fwrs_ctx* ctx, const float* color, const uint8_t* level_map, float gaze_x,
+                            float gaze_y, float* out);
+
+/* Frames pushed so far (host-side counter; no synchronisation). */
+int fwrs_frame_index(const fwrs_ctx* ctx, uint32_t* frame_index);
+
+/* Device pointers and layout of the store (no synchronisation). */
+int fwrs_get_state(const fwrs_ctx* ctx, fwrs_state_view* view);
+
+/* Synchronises the stream and copies the store to host memory, packed
+ * without padding in the order wsum[N], cnt[N], wt[k][N], idx[k][N],
+ * col[k][3][N] (N = width * height).  `host_bytes` must equal
+ * fwrs_state_host_bytes(...). */
+int fwrs_download_state(fwrs_ctx* ctx, void* host, size_t host_bytes);
+
+/* Synchronises the stream and returns the number of slot replacements (takes)
+ * and pixel updates since creation or the last reset.  The average number of
+ * slots replaced per pixel update is slot_takes / pixel_updates. */
+int fwrs_get_stats(fwrs_ctx* ctx, uint64_t* slot_takes, uint64_t* pixel_updates);
+
+/* Selects the thread-block tile: tile_x quads (4 horizontal pixels each) by
+ * tile_y rows, tile_x * tile_y in {64, 128, 256}, both powers of two.  It only
+ * changes the launch shape, never the results. */
+int fwrs_set_tile(fwrs_ctx* ctx, int tile_x, int tile_y);
+
+/* Waits for the context's stream; reports asynchronous HIP failures. */
+int fwrs_sync(fwrs_ctx* ctx);
+
+/* Text for a status code (static storage). */
+const char* fwrs_strerror(int status);
+
+/* ---- batched form --------------------------------------------------------
+ * One tick advances several contexts -- any mix of sizes and slot counts, on
+ * the same device -- by one frame each with a single persistent kernel launch.
+ * Each entry is the argument list of fwrs_push_frame_resolve; the results are
+ * bit-identical to calling it once per entry.  A context may appear at most
+ * once per tick.  Contexts' own streams are not used: the tick runs on the
+ * engine's stream, and the caller orders it after any other work on those
+ * contexts. */
+typedef struct fwrs_frame {
+    fwrs_ctx* ctx;
+    const float* color;
+    const uint8_t* level_map;
+    float gaze_x;
+    float gaze_y;
+    float* out;
+} fwrs_frame;
+
+typedef struct fwrs_engine fwrs_engine;
+
+/* Creates a tick engine for up to `max_frames` entries per tick on a
+ * borrowed HIP stream.  With use_graph != 0 each tick replays a captured HIP
+ * graph (descriptor upload + persistent kernel) instead of issuing the two
+ * operations.  The engine owns a device descriptor table and two pinned host
+ * staging buffers. */
+int fwrs_engine_create(void* hip_stream, int max_frames, int use_graph, fwrs_engine** out);
+
+/* Enqueues one tick.  FWRS_E_ARG: n outside [0, max_frames], a NULL field, a
+ * context repeated, contexts on another device. */
+int fwrs_engine_tick(fwrs_engine* eng, const fwrs_frame* frames, int n);
+
+/* Selects the tile shape the engine uses for contexts whose width * height is
+ * at least `min_pixels` (class table of up to 8 entries, largest threshold
+ * first wins); same constraints as fwrs_set_tile.  Results never change. */
+int fwrs_engine_set_tile(fwrs_engine* eng, long long min_pixels, int tile_x, int tile_y);
+
+/* Waits for the engine's stream, then frees the engine. */
+int fwrs_engine_destroy(fwrs_engine* eng);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FWRS_H */

@@ -68,6 +68,9 @@ def _bind(L):
     L.fwrs_oracle_create.restype = vp
     L.fwrs_oracle_destroy.argtypes = [vp]
     L.fwrs_oracle_push.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint8), C.c_float, C.c_float]
+    L.fwrs_oracle_push_rows.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint8), C.c_float, C.c_float,
+                                        C.c_int, C.c_int]
+    L.fwrs_oracle_advance.argtypes = [vp]
     L.fwrs_oracle_resolve.argtypes = [vp, C.POINTER(C.c_double)]
     L.fwrs_oracle_frame_index.argtypes = [vp]
     L.fwrs_oracle_frame_index.restype = C.c_uint32
@@ -138,6 +141,17 @@ class Oracle:
         assert color.shape == (self.height, self.width, 3) and level.shape == (self.height, self.width)
         self._L.fwrs_oracle_push(self._h, _ptr(color, C.c_float), _ptr(level, C.c_uint8),
                                  C.c_float(gx), C.c_float(gy))
+
+    def push_rows(self, color: np.ndarray, level: np.ndarray, gx: float, gy: float, y0: int, y1: int) -> None:
+        """Update only rows [y0, y1) of the frame (the frame index does not advance; call advance())."""
+        color = np.ascontiguousarray(color, dtype=np.float32)
+        level = np.ascontiguousarray(level, dtype=np.uint8)
+        assert color.shape == (self.height, self.width, 3) and level.shape == (self.height, self.width)
+        self._L.fwrs_oracle_push_rows(self._h, _ptr(color, C.c_float), _ptr(level, C.c_uint8),
+                                      C.c_float(gx), C.c_float(gy), int(y0), int(y1))
+
+    def advance(self) -> None:
+        self._L.fwrs_oracle_advance(self._h)
 
     def resolve(self) -> np.ndarray:
         out = np.empty((self.height, self.width, 3), dtype=np.float64)

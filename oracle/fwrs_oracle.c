@@ -273,6 +273,23 @@ static void update_pixel(const fwrs_oracle* o, int x, int y, uint32_t p, uint32_
     *cnt = *cnt + 1u;
 }
 
+/* Rows y0 <= y < y1 of one frame; the frame index does not advance.  Lets a
+ * test follow a band of a large image without updating the rest. */
+void fwrs_oracle_push_rows(fwrs_oracle* o, const float* color, const uint8_t* level, float gx, float gy, int y0,
+                           int y1)
+{
+    const size_t n = (size_t)o->width * (size_t)o->height;
+    for (int y = y0; y < y1 && y < o->height; ++y) {
+        for (int x = 0; x < o->width; ++x) {
+            size_t p = (size_t)y * (size_t)o->width + (size_t)x;
+            update_pixel(o, x, y, (uint32_t)p, o->t, color + 3 * p, level[p], gx, gy,
+                         o->wsum + p, o->cnt + p, o->wt + p, o->idx + p, o->col + p, n);
+        }
+    }
+}
+
+void fwrs_oracle_advance(fwrs_oracle* o) { o->t += 1u; }
+
 void fwrs_oracle_push(fwrs_oracle* o, const float* color, const uint8_t* level, float gx, float gy)
 {
     const size_t n = (size_t)o->width * (size_t)o->height;

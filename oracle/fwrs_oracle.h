@@ -51,6 +51,9 @@ void fwrs_oracle_default_params(int width, fwrs_oracle_params* p);
 fwrs_oracle* fwrs_oracle_create(int width, int height, int k, const fwrs_oracle_params* p);
 void fwrs_oracle_destroy(fwrs_oracle* o);
 void fwrs_oracle_push(fwrs_oracle* o, const float* color, const uint8_t* level, float gx, float gy);
+void fwrs_oracle_push_rows(fwrs_oracle* o, const float* color, const uint8_t* level, float gx, float gy, int y0,
+                           int y1);
+void fwrs_oracle_advance(fwrs_oracle* o);
 void fwrs_oracle_resolve(const fwrs_oracle* o, double* out);
 uint32_t fwrs_oracle_frame_index(const fwrs_oracle* o);
 void fwrs_oracle_constants(const fwrs_oracle* o, float out[9]);

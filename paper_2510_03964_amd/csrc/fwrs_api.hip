@@ -1,0 +1,620 @@
+// C ABI of the weighted-reservoir-sampling library (include/fwrs.h):
+// contexts with a structure-of-arrays reservoir store in HBM, argument
+// validation, single-frame launches on a borrowed stream, state access, and
+// the batched tick engine (persistent kernel, optionally replayed as a HIP
+// graph).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/fwrs.h"
+#include "fwrs_device.hpp"
+#include "fwrs_internal.hpp"
+
+using fwrs::FrameDesc;
+
+namespace {
+
+constexpr size_t kPitchAlign = 64;   // elements; planes start on 256-byte boundaries
+constexpr size_t kStatBytes = sizeof(unsigned long long) * fwrs::kStatSlots;
+constexpr int kDefaultTileX = 64, kDefaultTileY = 4;
+
+size_t pitch_for(int width, int height)
+{
+    const size_t n = (size_t)width * (size_t)height;
+    return (n + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
+}
+
+bool sizes_ok(int width, int height, int k)
+{
+    if (width <= 0 || height <= 0 || k < 1 || k > FWRS_MAX_K) return false;
+    // pixel indices are 32-bit in the kernels and in the Philox counter
+    return (long long)width * (long long)height < (1ll << 31);
+}
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
+
+bool params_ok(const fwrs_params* p)
+{
+    if (!p) return false;
+    if (!finite_pos(p->fov_deg) || !finite_pos(p->fovea_radius_px)) return false;
+    if (p->bias_mode != FWRS_BIAS_NONE && p->bias_mode != FWRS_BIAS_BERNOULLI) return false;
+    if (!(p->a_k > 0.0f && p->a_k <= 1.0f)) return false;
+    return finite_pos(p->r_m) && finite_pos(p->r2k) && finite_pos(p->rek);
+}
+
+// Per-context constants, derived with the same binary32 functions the kernels use.
+fwrs::Consts derive(const fwrs_params& p, int width)
+{
+    fwrs::Consts c{};
+    c.A = p.a_k;
+    c.B = 1.0f - p.a_k;
+    c.IR2 = 1.0f / p.r2k;
+    c.IRM = 1.0f / p.r_m;
+    c.C = 1.44269504088896341f / p.rek;
+    c.ppd = (float)width / p.fov_deg;
+    c.iPPD = 1.0f / c.ppd;
+    c.rf = p.fovea_radius_px * c.iPPD;
+    float num, den;
+    fwrs::density_terms(c, c.rf, num, den);
+    c.Drf = num / den;
+    return c;
+}
+
+int log2_exact(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return (1 << l) == v ? l : -1;
+}
+
+bool tile_ok(int tx, int ty)
+{
+    const int lx = log2_exact(tx), ly = log2_exact(ty);
+    if (lx < 0 || ly < 0) return false;
+    return lx + ly >= 6 && lx + ly <= 8;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard()
+    {
+        if (ok && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct fwrs_ctx {
+    int width = 0, height = 0, k = 0, device = 0;
+    fwrs_params prm{};
+    fwrs::Consts c{};
+    hipStream_t stream = nullptr;
+    void* arena = nullptr;
+    bool owns_arena = false;
+    size_t pitch = 0;
+    float* wsum = nullptr;
+    uint32_t* cnt = nullptr;
+    float* wt = nullptr;
+    float* col = nullptr;
+    uint32_t* idx = nullptr;
+    unsigned long long* stats = nullptr;
+    uint32_t t = 0;
+    uint64_t pixel_updates = 0;
+    int tile_x = kDefaultTileX, tile_y = kDefaultTileY;
+};
+
+namespace {
+
+int clear_store(fwrs_ctx* x)
+{
+    const size_t P = x->pitch, k = (size_t)x->k;
+    // wsum, cnt, wt and col are contiguous and start out zero; idx starts empty.
+    if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->wsum), P * (2 + 4 * k), 0u, x->stream) != hipSuccess)
+        return FWRS_E_HIP;
+    if (fwrs::launch_fill_u32(x->idx, P * k, 0xFFFFFFFFu, x->stream) != hipSuccess) return FWRS_E_HIP;
+    if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->stats), kStatBytes / 4, 0u, x->stream) != hipSuccess)
+        return FWRS_E_HIP;
+    x->t = 0;
+    x->pixel_updates = 0;
+    return FWRS_OK;
+}
+
+void fill_geometry(FrameDesc& d, int width, int height, int tx, int ty)
+{
+    d.tile_x_log2 = (uint32_t)log2_exact(tx);
+    d.tile_y_log2 = (uint32_t)log2_exact(ty);
+    const uint32_t tile_w = (uint32_t)tx * fwrs::kQuad;
+    d.tiles_x = ((uint32_t)width + tile_w - 1) / tile_w;
+    const uint32_t tiles_y = ((uint32_t)height + (uint32_t)ty - 1) / (uint32_t)ty;
+    const uint32_t tiles_per_item = (uint32_t)fwrs::kBlock / (uint32_t)(tx * ty);
+    d.items = (d.tiles_x * tiles_y + tiles_per_item - 1) / tiles_per_item;
+}
+
+bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+FrameDesc make_desc(const fwrs_ctx* x, const float* color, const uint8_t* level, float gx, float gy, float* out,
+                    int tx, int ty)
+{
+    FrameDesc d{};
+    d.color = color;
+    d.level = level;
+    d.out = out;
+    d.wsum = x->wsum;
+    d.cnt = x->cnt;
+    d.wt = x->wt;
+    d.idx = x->idx;
+    d.col = x->col;
+    d.stats = x->stats;
+    d.width = (uint32_t)x->width;
+    d.height = (uint32_t)x->height;
+    d.pitch = (uint32_t)x->pitch;
+    d.t = x->t;
+    d.gx = gx;
+    d.gy = gy;
+    d.c = x->c;
+    d.seed = x->prm.seed;
+    d.stream_id = x->prm.stream_id;
+    d.bias = x->prm.bias_mode;
+    d.k = (uint32_t)x->k;
+    fill_geometry(d, x->width, x->height, tx, ty);
+    d.item_begin = 0;
+    d.vec_ok = (x->width % 4 == 0) && aligned(color, 16) && aligned(out, 16) && aligned(level, 4) ? 1u : 0u;
+    return d;
+}
+
+bool gaze_ok(float gx, float gy) { return std::isfinite(gx) && std::isfinite(gy); }
+
+int run_frame(fwrs_ctx* x, const float* color, const uint8_t* level, float gx, float gy, float* out, int op)
+{
+    DeviceGuard g(x->device);
+    if (!g.ok) return FWRS_E_HIP;
+    FrameDesc d = make_desc(x, color, level, gx, gy, out, x->tile_x, x->tile_y);
+    if (fwrs::launch_frame(d, op, x->stream) != hipSuccess) return FWRS_E_HIP;
+    if (op & 1) {
+        x->t += 1u;
+        x->pixel_updates += (uint64_t)x->width * (uint64_t)x->height;
+    }
+    return FWRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwrs_default_params(int width, fwrs_params* p)
+{
+    if (width <= 0 || !p) return FWRS_E_ARG;
+    p->seed = 0;
+    p->stream_id = 0;
+    p->fov_deg = 70.0f;
+    p->fovea_radius_px = 0.05f * (float)width;
+    p->bias_mode = FWRS_BIAS_BERNOULLI;
+    p->r_m = 41.03f;
+    p->a_k = 0.9851f;
+    p->r2k = 1.058f;
+    p->rek = 22.14f;
+    return FWRS_OK;
+}
+
+size_t fwrs_state_bytes(int width, int height, int k)
+{
+    if (!sizes_ok(width, height, k)) return 0;
+    return 4 * pitch_for(width, height) * (2 + 5 * (size_t)k) + kStatBytes;
+}
+
+size_t fwrs_state_host_bytes(int width, int height, int k)
+{
+    if (!sizes_ok(width, height, k)) return 0;
+    return (size_t)width * (size_t)height * (8 + 20 * (size_t)k);
+}
+
+int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void* hip_stream, void* arena,
+                   size_t arena_bytes, fwrs_ctx** out)
+{
+    if (!out || !sizes_ok(width, height, k) || !params_ok(params)) return FWRS_E_ARG;
+    *out = nullptr;
+    const size_t need = fwrs_state_bytes(width, height, k);
+    if (arena && (arena_bytes < need || !aligned(arena, 256))) return FWRS_E_ARG;
+    fwrs_ctx* x = new (std::nothrow) fwrs_ctx();
+    if (!x) return FWRS_E_NOMEM;
+    if (hipGetDevice(&x->device) != hipSuccess) { delete x; return FWRS_E_HIP; }
+    x->width = width;
+    x->height = height;
+    x->k = k;
+    x->prm = *params;
+    x->c = derive(*params, width);
+    x->stream = (hipStream_t)hip_stream;
+    x->pitch = pitch_for(width, height);
+    if (arena) {
+        x->arena = arena;
+    } else {
+        if (hipMalloc(&x->arena, need) != hipSuccess) {
+            (void)hipGetLastError();
+            delete x;
+            return FWRS_E_NOMEM;
+        }
+        x->owns_arena = true;
+    }
+    const size_t P = x->pitch, kk = (size_t)k;
+    float* base = static_cast<float*>(x->arena);
+    x->wsum = base;
+    x->cnt = reinterpret_cast<uint32_t*>(base + P);
+    x->wt = base + 2 * P;
+    x->col = base + (2 + kk) * P;
+    x->idx = reinterpret_cast<uint32_t*>(base + (2 + 4 * kk) * P);
+    x->stats = reinterpret_cast<unsigned long long*>(base + (2 + 5 * kk) * P);
+    const int rc = clear_store(x);
+    if (rc != FWRS_OK) {
+        if (x->owns_arena) (void)hipFree(x->arena);
+        delete x;
+        return rc;
+    }
+    *out = x;
+    return FWRS_OK;
+}
+
+int fwrs_create(int width, int height, int k, fwrs_ctx** out)
+{
+    fwrs_params p;
+    if (fwrs_default_params(width, &p) != FWRS_OK) return FWRS_E_ARG;
+    return fwrs_create_ex(width, height, k, &p, nullptr, nullptr, 0, out);
+}
+
+int fwrs_destroy(fwrs_ctx* x)
+{
+    if (!x) return FWRS_OK;
+    int rc = FWRS_OK;
+    {
+        DeviceGuard g(x->device);
+        if (hipStreamSynchronize(x->stream) != hipSuccess) rc = FWRS_E_HIP;
+        if (x->owns_arena && hipFree(x->arena) != hipSuccess) rc = FWRS_E_HIP;
+    }
+    delete x;
+    return rc;
+}
+
+int fwrs_set_stream(fwrs_ctx* x, void* hip_stream)
+{
+    if (!x) return FWRS_E_ARG;
+    x->stream = (hipStream_t)hip_stream;
+    return FWRS_OK;
+}
+
+int fwrs_reset(fwrs_ctx* x)
+{
+    if (!x) return FWRS_E_ARG;
+    DeviceGuard g(x->device);
+    if (!g.ok) return FWRS_E_HIP;
+    return clear_store(x);
+}
+
+int fwrs_push_frame(fwrs_ctx* x, const float* color, const uint8_t* level_map, float gaze_x, float gaze_y)
+{
+    if (!x || !color || !level_map || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
+    if (x->t == 0xFFFFFFFFu) return FWRS_E_STATE;
+    return run_frame(x, color, level_map, gaze_x, gaze_y, nullptr, 1);
+}
+
+int fwrs_resolve(fwrs_ctx* x, float* out)
+{
+    if (!x || !out) return FWRS_E_ARG;
+    return run_frame(x, nullptr, nullptr, 0.0f, 0.0f, out, 2);
+}
+
+int fwrs_push_frame_resolve(fwrs_ctx* x, const float* color, const uint8_t* level_map, float gaze_x, float gaze_y,
+                            float* out)
+{
+    if (!x || !color || !level_map || !out || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
+    if (x->t == 0xFFFFFFFFu) return FWRS_E_STATE;
+    return run_frame(x, color, level_map, gaze_x, gaze_y, out, 3);
+}
+
+int fwrs_frame_index(const fwrs_ctx* x, uint32_t* frame_index)
+{
+    if (!x || !frame_index) return FWRS_E_ARG;
+    *frame_index = x->t;
+    return FWRS_OK;
+}
+
+int fwrs_get_state(const fwrs_ctx* x, fwrs_state_view* v)
+{
+    if (!x || !v) return FWRS_E_ARG;
+    v->width = x->width;
+    v->height = x->height;
+    v->k = x->k;
+    v->frame_index = x->t;
+    v->pitch = x->pitch;
+    v->wsum = x->wsum;
+    v->cnt = x->cnt;
+    v->wt = x->wt;
+    v->idx = x->idx;
+    v->col = x->col;
+    return FWRS_OK;
+}
+
+int fwrs_download_state(fwrs_ctx* x, void* host, size_t host_bytes)
+{
+    if (!x || !host || host_bytes != fwrs_state_host_bytes(x->width, x->height, x->k)) return FWRS_E_ARG;
+    DeviceGuard g(x->device);
+    if (!g.ok) return FWRS_E_HIP;
+    const size_t N = (size_t)x->width * (size_t)x->height, P = x->pitch, k = (size_t)x->k;
+    char* h = static_cast<char*>(host);
+    auto copy_planes = [&](const void* src, size_t planes) -> bool {
+        for (size_t i = 0; i < planes; ++i) {
+            const char* s = static_cast<const char*>(src) + i * P * 4;
+            if (hipMemcpyAsync(h, s, N * 4, hipMemcpyDeviceToHost, x->stream) != hipSuccess) return false;
+            h += N * 4;
+        }
+        return true;
+    };
+    if (!copy_planes(x->wsum, 1) || !copy_planes(x->cnt, 1) || !copy_planes(x->wt, k) || !copy_planes(x->idx, k) ||
+        !copy_planes(x->col, 3 * k))
+        return FWRS_E_HIP;
+    return hipStreamSynchronize(x->stream) == hipSuccess ? FWRS_OK : FWRS_E_HIP;
+}
+
+int fwrs_get_stats(fwrs_ctx* x, uint64_t* slot_takes, uint64_t* pixel_updates)
+{
+    if (!x) return FWRS_E_ARG;
+    DeviceGuard g(x->device);
+    if (!g.ok) return FWRS_E_HIP;
+    std::vector<unsigned long long> h(fwrs::kStatSlots);
+    if (hipMemcpyAsync(h.data(), x->stats, kStatBytes, hipMemcpyDeviceToHost, x->stream) != hipSuccess)
+        return FWRS_E_HIP;
+    if (hipStreamSynchronize(x->stream) != hipSuccess) return FWRS_E_HIP;
+    uint64_t s = 0;
+    for (unsigned long long v : h) s += v;
+    if (slot_takes) *slot_takes = s;
+    if (pixel_updates) *pixel_updates = x->pixel_updates;
+    return FWRS_OK;
+}
+
+int fwrs_set_tile(fwrs_ctx* x, int tile_x, int tile_y)
+{
+    if (!x || !tile_ok(tile_x, tile_y)) return FWRS_E_ARG;
+    x->tile_x = tile_x;
+    x->tile_y = tile_y;
+    return FWRS_OK;
+}
+
+int fwrs_sync(fwrs_ctx* x)
+{
+    if (!x) return FWRS_E_ARG;
+    DeviceGuard g(x->device);
+    if (!g.ok) return FWRS_E_HIP;
+    if (hipStreamSynchronize(x->stream) != hipSuccess) return FWRS_E_HIP;
+    return hipGetLastError() == hipSuccess ? FWRS_OK : FWRS_E_HIP;
+}
+
+const char* fwrs_strerror(int status)
+{
+    switch (status) {
+        case FWRS_OK: return "ok";
+        case FWRS_E_ARG: return "invalid argument";
+        case FWRS_E_NOMEM: return "out of memory";
+        case FWRS_E_HIP: return "HIP runtime error";
+        case FWRS_E_STATE: return "invalid state";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched tick engine
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TileClass {
+    long long min_pixels;
+    int tx, ty;
+};
+
+constexpr size_t kHdrBytes = 256;   // header (frame count, total items) padded so the table is aligned
+
+}  // namespace
+
+struct fwrs_engine {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int max_frames = 0;
+    int use_graph = 0;
+    uint32_t grid = 0;
+    size_t table_bytes = 0;
+    void* d_buf = nullptr;          // header + descriptor table
+    void* h_stage[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int cur = 0;
+    std::vector<TileClass> classes;
+};
+
+namespace {
+
+void engine_free(fwrs_engine* e)
+{
+    for (int b = 0; b < 2; ++b) {
+        if (e->exec[b]) (void)hipGraphExecDestroy(e->exec[b]);
+        if (e->graph[b]) (void)hipGraphDestroy(e->graph[b]);
+        if (e->done[b]) (void)hipEventDestroy(e->done[b]);
+        if (e->h_stage[b]) (void)hipHostFree(e->h_stage[b]);
+    }
+    if (e->d_buf) (void)hipFree(e->d_buf);
+    delete e;
+}
+
+void engine_tile(const fwrs_engine* e, long long pixels, int& tx, int& ty)
+{
+    tx = kDefaultTileX;
+    ty = kDefaultTileY;
+    long long best = -1;
+    for (const TileClass& c : e->classes)
+        if (pixels >= c.min_pixels && c.min_pixels > best) {
+            best = c.min_pixels;
+            tx = c.tx;
+            ty = c.ty;
+        }
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwrs_engine_create(void* hip_stream, int max_frames, int use_graph, fwrs_engine** out)
+{
+    if (!out || max_frames <= 0 || max_frames > 4096) return FWRS_E_ARG;
+    *out = nullptr;
+    fwrs_engine* e = new (std::nothrow) fwrs_engine();
+    if (!e) return FWRS_E_NOMEM;
+    e->stream = (hipStream_t)hip_stream;
+    e->max_frames = max_frames;
+    e->use_graph = use_graph ? 1 : 0;
+    if (hipGetDevice(&e->device) != hipSuccess) { delete e; return FWRS_E_HIP; }
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, e->device) != hipSuccess ||
+        fwrs::tick_occupancy(&per_cu) != hipSuccess) {
+        delete e;
+        return FWRS_E_HIP;
+    }
+    if (per_cu < 1) per_cu = 1;
+    e->grid = (uint32_t)(cus * per_cu);
+    e->table_bytes = kHdrBytes + sizeof(FrameDesc) * (size_t)max_frames;
+    if (hipMalloc(&e->d_buf, e->table_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        engine_free(e);
+        return FWRS_E_NOMEM;
+    }
+    for (int b = 0; b < 2; ++b) {
+        if (hipHostMalloc(&e->h_stage[b], e->table_bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            engine_free(e);
+            return FWRS_E_NOMEM;
+        }
+        std::memset(e->h_stage[b], 0, e->table_bytes);
+        if (hipEventCreateWithFlags(&e->done[b], hipEventDisableTiming) != hipSuccess) {
+            engine_free(e);
+            return FWRS_E_HIP;
+        }
+    }
+    if (e->use_graph) {
+        const FrameDesc* descs = reinterpret_cast<const FrameDesc*>(static_cast<char*>(e->d_buf) + kHdrBytes);
+        const uint32_t* hdr = static_cast<const uint32_t*>(e->d_buf);
+        for (int b = 0; b < 2; ++b) {
+            hipGraphNode_t copy = nullptr, kern = nullptr;
+            bool ok = hipGraphCreate(&e->graph[b], 0) == hipSuccess &&
+                      hipGraphAddMemcpyNode1D(&copy, e->graph[b], nullptr, 0, e->d_buf, e->h_stage[b],
+                                              e->table_bytes, hipMemcpyHostToDevice) == hipSuccess;
+            if (ok) {
+                void* args[2] = {(void*)&descs, (void*)&hdr};
+                hipKernelNodeParams kp{};
+                kp.func = fwrs::tick_kernel_entry();
+                kp.gridDim = dim3(e->grid);
+                kp.blockDim = dim3(fwrs::kBlock);
+                kp.sharedMemBytes = 0;
+                kp.kernelParams = args;
+                kp.extra = nullptr;
+                ok = hipGraphAddKernelNode(&kern, e->graph[b], &copy, 1, &kp) == hipSuccess &&
+                     hipGraphInstantiate(&e->exec[b], e->graph[b], nullptr, nullptr, 0) == hipSuccess;
+            }
+            if (!ok) {
+                engine_free(e);
+                return FWRS_E_HIP;
+            }
+        }
+    }
+    *out = e;
+    return FWRS_OK;
+}
+
+int fwrs_engine_set_tile(fwrs_engine* e, long long min_pixels, int tile_x, int tile_y)
+{
+    if (!e || min_pixels < 0 || !tile_ok(tile_x, tile_y)) return FWRS_E_ARG;
+    for (TileClass& c : e->classes)
+        if (c.min_pixels == min_pixels) {
+            c.tx = tile_x;
+            c.ty = tile_y;
+            return FWRS_OK;
+        }
+    if (e->classes.size() >= 8) return FWRS_E_ARG;
+    e->classes.push_back(TileClass{min_pixels, tile_x, tile_y});
+    return FWRS_OK;
+}
+
+int fwrs_engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n)
+{
+    if (!e || n < 0 || n > e->max_frames || (n > 0 && !frames)) return FWRS_E_ARG;
+    for (int i = 0; i < n; ++i) {
+        const fwrs_frame& f = frames[i];
+        if (!f.ctx || !f.color || !f.level_map || !f.out || !gaze_ok(f.gaze_x, f.gaze_y)) return FWRS_E_ARG;
+        if (f.ctx->device != e->device) return FWRS_E_ARG;
+        if (f.ctx->t == 0xFFFFFFFFu) return FWRS_E_STATE;
+        for (int j = 0; j < i; ++j)
+            if (frames[j].ctx == f.ctx) return FWRS_E_ARG;
+    }
+    DeviceGuard g(e->device);
+    if (!g.ok) return FWRS_E_HIP;
+    const int b = e->cur;
+    // The staging buffer was last read by the tick issued two calls ago.
+    if (hipEventSynchronize(e->done[b]) != hipSuccess) return FWRS_E_HIP;
+    char* stage = static_cast<char*>(e->h_stage[b]);
+    FrameDesc* descs = reinterpret_cast<FrameDesc*>(stage + kHdrBytes);
+    uint32_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        const fwrs_frame& f = frames[i];
+        int tx, ty;
+        engine_tile(e, (long long)f.ctx->width * f.ctx->height, tx, ty);
+        FrameDesc d = make_desc(f.ctx, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, tx, ty);
+        d.item_begin = total;
+        total += d.items;
+        descs[i] = d;
+    }
+    uint32_t* hdr = reinterpret_cast<uint32_t*>(stage);
+    hdr[0] = (uint32_t)n;
+    hdr[1] = total;
+    hipError_t err;
+    if (e->use_graph) {
+        err = hipGraphLaunch(e->exec[b], e->stream);
+    } else {
+        const size_t bytes = kHdrBytes + sizeof(FrameDesc) * (size_t)n;
+        err = hipMemcpyAsync(e->d_buf, stage, bytes, hipMemcpyHostToDevice, e->stream);
+        if (err == hipSuccess && total > 0) {
+            const FrameDesc* dd = reinterpret_cast<const FrameDesc*>(static_cast<char*>(e->d_buf) + kHdrBytes);
+            err = fwrs::launch_tick(dd, static_cast<const uint32_t*>(e->d_buf), e->grid, e->stream);
+        }
+    }
+    if (err != hipSuccess) return FWRS_E_HIP;
+    if (hipEventRecord(e->done[b], e->stream) != hipSuccess) return FWRS_E_HIP;
+    e->cur ^= 1;
+    for (int i = 0; i < n; ++i) {
+        frames[i].ctx->t += 1u;
+        frames[i].ctx->pixel_updates += (uint64_t)frames[i].ctx->width * (uint64_t)frames[i].ctx->height;
+    }
+    return FWRS_OK;
+}
+
+int fwrs_engine_destroy(fwrs_engine* e)
+{
+    if (!e) return FWRS_OK;
+    int rc = FWRS_OK;
+    {
+        DeviceGuard g(e->device);
+        if (hipStreamSynchronize(e->stream) != hipSuccess) rc = FWRS_E_HIP;
+        engine_free(e);
+    }
+    return rc;
+}
+
+}  // extern "C"

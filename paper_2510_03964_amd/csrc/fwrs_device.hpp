@@ -1,0 +1,148 @@
+// Device-side building blocks of the weighted-reservoir-sampling pass for
+// gfx950: the per-frame descriptor, the method constants, Philox4x32-10, the
+// base-2 exponential, the Eq. 3-4 weight and the Eq. 5-6 bias.
+//
+// Every binary32 operation here is written out in the order the method fixes
+// and the library is built with -ffp-contract=off and correctly rounded
+// division and square root, so the weight, the biased w_sum and the keep /
+// replace decisions are reproducible bit for bit on any IEEE binary32 target
+// (the same functions run on the host to derive the per-context constants).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fwrs {
+
+// Method constants derived once per context from its parameters (Sec. 4.1).
+struct Consts {
+    float A;     // a_k
+    float B;     // 1 - a_k
+    float IR2;   // 1 / r_2,k
+    float IRM;   // 1 / r_m
+    float C;     // log2(e) / r_e,k: exp(-e / r_e,k) = 2^(-e C)
+    float ppd;   // pixels per degree = width / fov_deg
+    float iPPD;  // 1 / ppd
+    float rf;    // foveal radius in degrees = fovea_radius_px / ppd
+    float Drf;   // density at r_f (normalisation of Eq. 4)
+};
+
+// Everything one frame of one context needs on the device.  Passed by value
+// to the single-frame kernels and stored in a device table for batched ticks.
+struct alignas(16) FrameDesc {
+    const float* color;         // [H][W][3] f32, the new candidates
+    const uint8_t* level;       // [H][W] u8 foveation level
+    float* out;                 // [H][W][3] f32 resolve target (may be null for push-only)
+    float* wsum;                // [pitch]
+    uint32_t* cnt;              // [pitch]
+    float* wt;                  // [k][pitch]
+    uint32_t* idx;              // [k][pitch]
+    float* col;                 // [k][3][pitch]
+    unsigned long long* stats;  // [kStatSlots] slot-take counters, or null
+    uint32_t width, height, pitch, t;
+    float gx, gy;
+    Consts c;
+    uint32_t seed, stream_id, bias, k;
+    uint32_t tile_x_log2, tile_y_log2, tiles_x, items;  // launch geometry
+    uint32_t item_begin;        // first work item of this frame in a batched tick
+    uint32_t vec_ok;            // width % 4 == 0 and 16-byte aligned buffers
+    uint32_t pad[2];
+};
+
+constexpr int kBlock = 256;             // threads per block
+constexpr int kQuad = 4;                // pixels per thread
+constexpr int kStatSlots = 1024;        // spread of the slot-take counters
+constexpr uint32_t kBiasNone = 0u;
+constexpr uint32_t kBiasBernoulli = 1u;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11).  Counter (x0..x3),
+// key (k0, k1); per round: (hi, lo) of M_A * x0 and M_B * x2, new words
+// (hi_B ^ x1 ^ k0, lo_B, hi_A ^ x3 ^ k1, lo_A); the key advances by the Weyl
+// constants between rounds.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPhiloxMulA = 0xD2511F53u;
+constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxWeylA = 0x9E3779B9u;
+constexpr uint32_t kPhiloxWeylB = 0xBB67AE85u;
+
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                                uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi_a = __umulhi(kPhiloxMulA, x0);
+        const uint32_t lo_a = kPhiloxMulA * x0;
+        const uint32_t hi_b = __umulhi(kPhiloxMulB, x2);
+        const uint32_t lo_b = kPhiloxMulB * x2;
+        x0 = hi_b ^ x1 ^ k0;
+        x1 = lo_b;
+        x2 = hi_a ^ x3 ^ k1;
+        x3 = lo_a;
+        k0 += kPhiloxWeylA;
+        k1 += kPhiloxWeylB;
+    }
+    return make_uint4(x0, x1, x2, x3);
+}
+
+// Variate in (0, 1] from the top 24 bits of a Philox word.
+__device__ __forceinline__ float unit_variate(uint32_t word)
+{
+    return (float)((word >> 8) + 1u) * 0x1p-24f;
+}
+
+// ---------------------------------------------------------------------------
+// 2^y for y <= 0: y = n + f, n = rint(y), |f| <= 1/2 (exact), degree-7 Taylor
+// polynomial of 2^f = exp(f ln 2) in Horner form, scaled by 2^n.  The
+// coefficients are the binary32 roundings of (ln 2)^i / i!.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ float exp2_neg(float y)
+{
+    const float n = rintf(y);
+    const float f = y - n;
+    float p = 0x1.ffcbfcp-17f;        // (ln 2)^7 / 7!
+    p = p * f; p = p + 0x1.430912p-13f;   // (ln 2)^6 / 6!
+    p = p * f; p = p + 0x1.5d87fep-10f;   // (ln 2)^5 / 5!
+    p = p * f; p = p + 0x1.3b2ab6p-7f;    // (ln 2)^4 / 4!
+    p = p * f; p = p + 0x1.c6b08ep-5f;    // (ln 2)^3 / 3!
+    p = p * f; p = p + 0x1.ebfbe0p-3f;    // (ln 2)^2 / 2!
+    p = p * f; p = p + 0x1.62e430p-1f;    // ln 2
+    p = p * f; p = p + 1.0f;
+    return ldexpf(p, (int)n);
+}
+
+// Eq. 3 multiplied through by (1 + e / r_2,k)^2, without the 2 d_c(0) factor
+// that cancels in Eq. 4:  d(e) ~ num / den with
+//   num = a_k + (1 - a_k) exp(-e / r_e,k) (1 + e / r_2,k)^2,
+//   den = (1 + e / r_2,k)^2 (1 + e / r_m).
+__host__ __device__ __forceinline__ void density_terms(const Consts& c, float e, float& num, float& den)
+{
+    const float t1 = 1.0f + e * c.IRM;
+    const float t2 = 1.0f + e * c.IR2;
+    const float T = t2 * t2;
+    const float E = exp2_neg(-(e * c.C));
+    num = c.A + (c.B * E) * T;
+    den = T * t1;
+}
+
+// Eq. 4 for a pixel whose centre lies `dist2` squared pixels from the gaze;
+// level 0 (full fidelity this frame) and e <= r_f score 1.
+__device__ __forceinline__ float weight_eq4(const Consts& c, float dist2, uint32_t level)
+{
+    const float e = sqrtf(dist2) * c.iPPD;
+    float num, den;
+    density_terms(c, e, num, den);
+    const float w = fminf(1.0f, num / (den * c.Drf));
+    return (level == 0u || e <= c.rf) ? 1.0f : w;
+}
+
+// Eq. 5-6: R1.w_sum scaled by the survival probability 1 - w / (R1.w_sum + w).
+__device__ __forceinline__ float bias_eq6(float W1, float w, uint32_t mode)
+{
+    const float total = W1 + w;
+    const float q = w / total;
+    const float survive = 1.0f - q;
+    return mode == kBiasBernoulli ? W1 * survive : W1;
+}
+
+}  // namespace fwrs

@@ -1,0 +1,342 @@
+"""Python binding of the C ABI in include/fwrs.h (ctypes; argument marshalling only).
+
+Torch tensors supply device memory (``data_ptr()``) and HIP streams
+(``torch.cuda.Stream.cuda_stream``); every step of the method runs in the HIP
+kernels of ``libfwrs.so``.  There is no fallback: if the library is missing or
+the GPU is absent the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfwrs.so")
+
+OK, E_ARG, E_NOMEM, E_HIP, E_STATE = 0, 1, 2, 3, 4
+BIAS_NONE, BIAS_BERNOULLI = 0, 1
+MAX_K = 16
+
+#: every symbol include/fwrs.h declares
+EXPORTS = (
+    "fwrs_default_params", "fwrs_state_bytes", "fwrs_state_host_bytes", "fwrs_create", "fwrs_create_ex",
+    "fwrs_destroy", "fwrs_set_stream", "fwrs_reset", "fwrs_push_frame", "fwrs_resolve",
+    "fwrs_push_frame_resolve", "fwrs_frame_index", "fwrs_get_state", "fwrs_download_state", "fwrs_get_stats",
+    "fwrs_set_tile", "fwrs_sync", "fwrs_strerror", "fwrs_engine_create", "fwrs_engine_tick",
+    "fwrs_engine_set_tile", "fwrs_engine_destroy",
+)
+
+
+class FwrsError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+        self.status = status
+
+
+class Params(C.Structure):
+    """``fwrs_params``."""
+
+    _fields_ = [
+        ("seed", C.c_uint32),
+        ("stream_id", C.c_uint32),
+        ("fov_deg", C.c_float),
+        ("fovea_radius_px", C.c_float),
+        ("bias_mode", C.c_uint32),
+        ("r_m", C.c_float),
+        ("a_k", C.c_float),
+        ("r2k", C.c_float),
+        ("rek", C.c_float),
+    ]
+
+
+class StateView(C.Structure):
+    """``fwrs_state_view``."""
+
+    _fields_ = [
+        ("width", C.c_int),
+        ("height", C.c_int),
+        ("k", C.c_int),
+        ("frame_index", C.c_uint32),
+        ("pitch", C.c_size_t),
+        ("wsum", C.c_void_p),
+        ("cnt", C.c_void_p),
+        ("wt", C.c_void_p),
+        ("idx", C.c_void_p),
+        ("col", C.c_void_p),
+    ]
+
+
+class Frame(C.Structure):
+    """``fwrs_frame``."""
+
+    _fields_ = [
+        ("ctx", C.c_void_p),
+        ("color", C.c_void_p),
+        ("level_map", C.c_void_p),
+        ("gaze_x", C.c_float),
+        ("gaze_y", C.c_float),
+        ("out", C.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libfwrs.so (built by ``paper_2510_03964_amd.build``).  Raises if absent."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise FileNotFoundError(f"{p} is missing: build it with `python -m paper_2510_03964_amd.build`")
+    L = C.CDLL(p)
+    vp, i, f, u32, sz = C.c_void_p, C.c_int, C.c_float, C.c_uint32, C.c_size_t
+    sig = {
+        "fwrs_default_params": (i, [i, C.POINTER(Params)]),
+        "fwrs_state_bytes": (sz, [i, i, i]),
+        "fwrs_state_host_bytes": (sz, [i, i, i]),
+        "fwrs_create": (i, [i, i, i, C.POINTER(vp)]),
+        "fwrs_create_ex": (i, [i, i, i, C.POINTER(Params), vp, vp, sz, C.POINTER(vp)]),
+        "fwrs_destroy": (i, [vp]),
+        "fwrs_set_stream": (i, [vp, vp]),
+        "fwrs_reset": (i, [vp]),
+        "fwrs_push_frame": (i, [vp, vp, vp, f, f]),
+        "fwrs_resolve": (i, [vp, vp]),
+        "fwrs_push_frame_resolve": (i, [vp, vp, vp, f, f, vp]),
+        "fwrs_frame_index": (i, [vp, C.POINTER(u32)]),
+        "fwrs_get_state": (i, [vp, C.POINTER(StateView)]),
+        "fwrs_download_state": (i, [vp, vp, sz]),
+        "fwrs_get_stats": (i, [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+        "fwrs_set_tile": (i, [vp, i, i]),
+        "fwrs_sync": (i, [vp]),
+        "fwrs_strerror": (C.c_char_p, [i]),
+        "fwrs_engine_create": (i, [vp, i, i, C.POINTER(vp)]),
+        "fwrs_engine_tick": (i, [vp, C.POINTER(Frame), i]),
+        "fwrs_engine_set_tile": (i, [vp, C.c_longlong, i, i]),
+        "fwrs_engine_destroy": (i, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    try:
+        return load().fwrs_strerror(int(status)).decode()
+    except FileNotFoundError:
+        return f"status {status}"
+
+
+def _check(status: int, what: str) -> None:
+    if status != OK:
+        raise FwrsError(status, what)
+
+
+def default_params(width: int, **overrides) -> Params:
+    p = Params()
+    _check(load().fwrs_default_params(int(width), C.byref(p)), "fwrs_default_params")
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def state_bytes(width: int, height: int, k: int) -> int:
+    return int(load().fwrs_state_bytes(int(width), int(height), int(k)))
+
+
+def state_host_bytes(width: int, height: int, k: int) -> int:
+    return int(load().fwrs_state_host_bytes(int(width), int(height), int(k)))
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream or None
+    return int(stream.cuda_stream) or None
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+@dataclass
+class HostState:
+    """A packed host copy of a context's reservoir store (see fwrs_download_state)."""
+
+    wsum: np.ndarray   # [H, W] f32
+    cnt: np.ndarray    # [H, W] u32
+    wt: np.ndarray     # [k, H, W] f32
+    idx: np.ndarray    # [k, H, W] u32
+    col: np.ndarray    # [k, 3, H, W] f32
+
+
+class Reservoir:
+    """A context: the k-slot reservoirs of every pixel of a width x height stream.
+
+    ``arena`` may be a caller-owned device tensor (uint8, at least
+    ``state_bytes(width, height, k)`` bytes, 256-byte aligned) that holds the
+    store; otherwise the library allocates it."""
+
+    def __init__(self, width: int, height: int, k: int, params: Params | None = None, stream=None, arena=None):
+        self._L = load()
+        self.width, self.height, self.k = int(width), int(height), int(k)
+        self.params = params if params is not None else default_params(width)
+        self._arena = arena
+        h = C.c_void_p()
+        ap = _ptr(arena) if arena is not None else None
+        ab = arena.numel() * arena.element_size() if arena is not None else 0
+        _check(self._L.fwrs_create_ex(self.width, self.height, self.k, C.byref(self.params), _stream_handle(stream),
+                                      ap, ab, C.byref(h)), "fwrs_create_ex")
+        self._h = h
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(self._L.fwrs_destroy(self._h), "fwrs_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_stream(self, stream) -> None:
+        _check(self._L.fwrs_set_stream(self._h, _stream_handle(stream)), "fwrs_set_stream")
+
+    def set_tile(self, tile_x: int, tile_y: int) -> None:
+        _check(self._L.fwrs_set_tile(self._h, int(tile_x), int(tile_y)), "fwrs_set_tile")
+
+    def reset(self) -> None:
+        _check(self._L.fwrs_reset(self._h), "fwrs_reset")
+
+    def _check_frame(self, color, level) -> None:
+        H, W = self.height, self.width
+        if tuple(color.shape) != (H, W, 3) or color.dtype.itemsize != 4 or not color.is_contiguous():
+            raise ValueError(f"color must be contiguous float32 [{H}, {W}, 3]")
+        if tuple(level.shape) != (H, W) or level.dtype.itemsize != 1 or not level.is_contiguous():
+            raise ValueError(f"level must be contiguous uint8 [{H}, {W}]")
+        if not (color.is_cuda and level.is_cuda):
+            raise ValueError("color and level must be device tensors")
+
+    def _check_out(self, out) -> None:
+        if tuple(out.shape) != (self.height, self.width, 3) or out.dtype.itemsize != 4 or not out.is_contiguous():
+            raise ValueError("out must be contiguous float32 [H, W, 3]")
+        if not out.is_cuda:
+            raise ValueError("out must be a device tensor")
+
+    def push(self, color, level, gaze_x: float, gaze_y: float) -> None:
+        self._check_frame(color, level)
+        _check(self._L.fwrs_push_frame(self._h, _ptr(color), _ptr(level), float(gaze_x), float(gaze_y)),
+               "fwrs_push_frame")
+
+    def resolve(self, out) -> None:
+        self._check_out(out)
+        _check(self._L.fwrs_resolve(self._h, _ptr(out)), "fwrs_resolve")
+
+    def step(self, color, level, gaze_x: float, gaze_y: float, out) -> None:
+        """fwrs_push_frame_resolve: one frame of update and resolve in one pass."""
+        self._check_frame(color, level)
+        self._check_out(out)
+        _check(self._L.fwrs_push_frame_resolve(self._h, _ptr(color), _ptr(level), float(gaze_x), float(gaze_y),
+                                               _ptr(out)), "fwrs_push_frame_resolve")
+
+    @property
+    def frame_index(self) -> int:
+        t = C.c_uint32()
+        _check(self._L.fwrs_frame_index(self._h, C.byref(t)), "fwrs_frame_index")
+        return int(t.value)
+
+    def state_view(self) -> StateView:
+        v = StateView()
+        _check(self._L.fwrs_get_state(self._h, C.byref(v)), "fwrs_get_state")
+        return v
+
+    def download(self) -> HostState:
+        H, W, k = self.height, self.width, self.k
+        N = H * W
+        buf = np.empty(state_host_bytes(W, H, k), np.uint8)
+        _check(self._L.fwrs_download_state(self._h, buf.ctypes.data, buf.nbytes), "fwrs_download_state")
+        o = 0
+
+        def take(dtype, count, shape):
+            nonlocal o
+            a = buf[o:o + 4 * count].view(dtype).reshape(shape)
+            o += 4 * count
+            return a
+
+        return HostState(take(np.float32, N, (H, W)), take(np.uint32, N, (H, W)), take(np.float32, k * N, (k, H, W)),
+                         take(np.uint32, k * N, (k, H, W)), take(np.float32, 3 * k * N, (k, 3, H, W)))
+
+    def stats(self) -> tuple[int, int]:
+        """(slot takes, pixel updates) since creation or reset."""
+        a, b = C.c_uint64(), C.c_uint64()
+        _check(self._L.fwrs_get_stats(self._h, C.byref(a), C.byref(b)), "fwrs_get_stats")
+        return int(a.value), int(b.value)
+
+    def sync(self) -> None:
+        _check(self._L.fwrs_sync(self._h), "fwrs_sync")
+
+
+class Engine:
+    """Batched ticks: one persistent launch advances many contexts by one frame."""
+
+    def __init__(self, max_frames: int, stream=None, use_graph: bool = False):
+        self._L = load()
+        h = C.c_void_p()
+        _check(self._L.fwrs_engine_create(_stream_handle(stream), int(max_frames), 1 if use_graph else 0,
+                                          C.byref(h)), "fwrs_engine_create")
+        self._h = h
+        self.max_frames = int(max_frames)
+        self._frames = (Frame * self.max_frames)()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(self._L.fwrs_engine_destroy(self._h), "fwrs_engine_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tile(self, min_pixels: int, tile_x: int, tile_y: int) -> None:
+        _check(self._L.fwrs_engine_set_tile(self._h, int(min_pixels), int(tile_x), int(tile_y)),
+               "fwrs_engine_set_tile")
+
+    def tick(self, entries) -> None:
+        """entries: iterable of (Reservoir, color, level, gaze_x, gaze_y, out)."""
+        n = 0
+        for (res, color, level, gx, gy, out) in entries:
+            if n >= self.max_frames:
+                raise ValueError("too many frames for this engine")
+            res._check_frame(color, level)
+            res._check_out(out)
+            fr = self._frames[n]
+            fr.ctx = res.handle
+            fr.color = _ptr(color)
+            fr.level_map = _ptr(level)
+            fr.gaze_x = float(gx)
+            fr.gaze_y = float(gy)
+            fr.out = _ptr(out)
+            n += 1
+        _check(self._L.fwrs_engine_tick(self._h, self._frames, n), "fwrs_engine_tick")

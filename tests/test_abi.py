@@ -1,0 +1,98 @@
+"""The C-ABI library loads and exports every symbol include/fwrs.h declares; host-side
+argument handling (no GPU work).  CPU only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2510_03964_amd import fwrs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fwrs.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(fwrs_[a-z_0-9]+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared_functions() == sorted(fwrs.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = fwrs.load()
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", fwrs.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = set(re.findall(r"\bT (fwrs_[a-z_0-9]+)", out.stdout))
+    assert set(_declared_functions()) <= exported
+    # the C ABI exposes no C++ or torch types
+    assert not re.search(r"\bT _Z\S*fwrs_", out.stdout)
+
+
+def test_library_is_gfx950_code():
+    out = subprocess.run(["strings", fwrs.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    assert "gfx950" in out
+
+
+def test_header_compiles_as_plain_c(tmp_path):
+    src = tmp_path / "t.c"
+    src.write_text('#include "fwrs.h"\nint main(void){ fwrs_params p; return fwrs_default_params(64, &p); }\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), "-c", str(src), "-o",
+                    str(tmp_path / "t.o")], check=True)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    src = tmp_path / "l.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "fwrs.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(fwrs_params), sizeof(fwrs_state_view),"
+        " sizeof(fwrs_frame), offsetof(fwrs_frame, out), offsetof(fwrs_state_view, col)); return 0;}\n")
+    exe = tmp_path / "l"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [C.sizeof(fwrs.Params), C.sizeof(fwrs.StateView), C.sizeof(fwrs.Frame),
+                   fwrs.Frame.out.offset, fwrs.StateView.col.offset]
+
+
+def test_default_params_and_sizes():
+    p = fwrs.default_params(3840)
+    assert p.fov_deg == 70.0 and p.fovea_radius_px == pytest.approx(192.0)
+    assert p.bias_mode == fwrs.BIAS_BERNOULLI
+    assert (p.a_k, p.r2k, p.rek) == (pytest.approx(0.9851), pytest.approx(1.058), pytest.approx(22.14))
+    N = 3840 * 2160
+    assert fwrs.state_bytes(3840, 2160, 4) == 4 * N * (2 + 20) + 8192      # N is a multiple of 64
+    assert fwrs.state_host_bytes(3840, 2160, 4) == N * (8 + 80)
+    assert fwrs.state_bytes(13, 7, 3) == 4 * 128 * (2 + 15) + 8192        # pitch rounded up to 64
+    for bad in [(0, 5, 4), (5, 0, 4), (5, 5, 0), (5, 5, 17), (65536, 65536, 1)]:
+        assert fwrs.state_bytes(*bad) == 0
+
+
+def test_invalid_arguments_are_rejected_before_any_gpu_work():
+    L = fwrs.load()
+    h = C.c_void_p()
+    p = fwrs.default_params(64)
+    assert L.fwrs_create(0, 10, 4, C.byref(h)) == fwrs.E_ARG
+    assert L.fwrs_create(10, 10, 17, C.byref(h)) == fwrs.E_ARG
+    assert L.fwrs_create(10, 10, 4, None) == fwrs.E_ARG
+    for field, value in [("fov_deg", 0.0), ("fovea_radius_px", float("nan")), ("bias_mode", 7), ("a_k", 1.5),
+                         ("r_m", -1.0), ("rek", float("inf"))]:
+        q = fwrs.default_params(64)
+        setattr(q, field, value)
+        assert L.fwrs_create_ex(64, 64, 4, C.byref(q), None, None, 0, C.byref(h)) == fwrs.E_ARG, field
+    # a caller arena that is too small or misaligned
+    assert L.fwrs_create_ex(64, 64, 4, C.byref(p), None, 256, 16, C.byref(h)) == fwrs.E_ARG
+    assert L.fwrs_create_ex(64, 64, 4, C.byref(p), None, 4100, 1 << 30, C.byref(h)) == fwrs.E_ARG
+    assert L.fwrs_push_frame(None, None, None, 0.0, 0.0) == fwrs.E_ARG
+    assert L.fwrs_resolve(None, None) == fwrs.E_ARG
+    assert L.fwrs_destroy(None) == fwrs.OK
+    assert L.fwrs_engine_destroy(None) == fwrs.OK
+    assert L.fwrs_engine_create(None, 0, 0, C.byref(h)) == fwrs.E_ARG
+    assert fwrs.strerror(fwrs.E_ARG) == "invalid argument"
+    assert fwrs.strerror(99) == "unknown status"

@@ -1,0 +1,311 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, element by element.
+
+Bar: slot frame indices, counts, weights, weight sums and kept colours are
+bit-exact (they are decided or copied values); the resolved colour is within
+1e-5 of the oracle's binary64 resolve (a binary32 weighted mean of at most 16
+values in [0, 1] rounds to within a few 1e-7).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_03964_amd import fwrs, synth
+
+pytestmark = pytest.mark.gpu
+COLOR_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fwrs.load()
+    return torch.device("cuda:0")
+
+
+def _params(spec, bias=fwrs.BIAS_BERNOULLI, seed=synth.PHILOX_SEED):
+    p = fwrs.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=seed,
+                            stream_id=spec.stream_id, bias_mode=bias)
+    q = oracle.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=seed,
+                              stream_id=spec.stream_id, bias_mode=bias)
+    return p, q
+
+
+def _compare_state(st, so, where=""):
+    np.testing.assert_array_equal(st.cnt, so.cnt, err_msg=f"cnt {where}")
+    np.testing.assert_array_equal(st.idx, so.idx, err_msg=f"idx {where}")
+    np.testing.assert_array_equal(st.wsum.view(np.uint32), so.wsum.view(np.uint32), err_msg=f"wsum {where}")
+    np.testing.assert_array_equal(st.wt.view(np.uint32), so.wt.view(np.uint32), err_msg=f"wt {where}")
+    np.testing.assert_array_equal(st.col.view(np.uint32), so.col.view(np.uint32), err_msg=f"col {where}")
+
+
+def _compare_out(out, ref, where=""):
+    err = np.abs(out.astype(np.float64) - ref).max() if out.size else 0.0
+    assert err <= COLOR_TOL, f"resolve differs by {err} {where}"
+    return err
+
+
+def _run_pair(dev, spec, n_frames, mode="fused", tile=None, bias=fwrs.BIAS_BERNOULLI, every=1, src=None):
+    p, q = _params(spec, bias)
+    src = src or synth.FrameSource(spec, device=dev, n_frames=n_frames)
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream())
+    if tile is not None:
+        res.set_tile(*tile)
+    orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
+    out = torch.full((spec.height, spec.width, 3), -1.0, dtype=torch.float32, device=dev)
+    for t in range(n_frames):
+        c, lev, gx, gy = src.frame(t)
+        if mode == "fused":
+            res.step(c, lev, gx, gy, out)
+        else:
+            res.push(c, lev, gx, gy)
+            res.resolve(out)
+        orc.push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+        if (t + 1) % every == 0 or t == n_frames - 1:
+            res.sync()
+            _compare_state(res.download(), orc.state(), f"frame {t} {spec.width}x{spec.height} k={spec.k}")
+            _compare_out(out.cpu().numpy(), orc.resolve(), f"frame {t}")
+    assert res.frame_index == n_frames
+    return res, orc, out
+
+
+def test_small_workload_every_frame(dev):
+    """256x256, k = 4, 60 frames of the synthetic gaze trace, fused update + resolve."""
+    spec = synth.spec_small()
+    res, orc, _ = _run_pair(dev, spec, spec.frames)
+    takes, updates = res.stats()
+    assert updates == spec.frames * spec.pixels
+    assert takes > 0
+
+
+def test_push_then_resolve_is_bit_identical_to_fused(dev):
+    spec = synth.spec_small()
+    _, _, out_a = _run_pair(dev, spec, 12, mode="fused", every=12)
+    _, _, out_b = _run_pair(dev, spec, 12, mode="split", every=12)
+    assert torch.equal(out_a, out_b)
+
+
+@pytest.mark.parametrize("w,h,k,frames", [
+    (1, 1, 1, 5), (3, 2, 16, 4), (13, 7, 3, 6), (100, 37, 5, 4), (64, 64, 8, 5), (255, 3, 2, 5),
+    (96, 40, 7, 4), (128, 33, 12, 3), (1367, 769, 4, 3),
+])
+def test_sizes_and_slot_counts(dev, w, h, k, frames):
+    """Ragged widths (scalar path), every specialised and generic slot count, tiny images."""
+    spec = synth.StreamSpec(w, h, k, frames, max(1.0, 0.1 * w), max(2.5, 0.25 * w), 0.2 * w + 0.5, 2, 0.3 * w + 1,
+                            stream_id=k)
+    _run_pair(dev, spec, frames)
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (32, 8), (64, 4), (256, 1), (16, 4), (8, 16), (128, 2)])
+def test_tile_shape_never_changes_results(dev, tile):
+    spec = synth.StreamSpec(200, 120, 4, 5, 20.0, 50.0, 3.0, 2, 9.0)
+    _run_pair(dev, spec, 5, tile=tile)
+
+
+def test_bias_none_mode(dev):
+    spec = synth.StreamSpec(160, 96, 4, 8, 16.0, 40.0, 3.0, 3, 8.0)
+    _run_pair(dev, spec, 8, bias=fwrs.BIAS_NONE)
+
+
+def test_unaligned_buffers_take_the_scalar_path(dev):
+    """Colour and output views starting 4 bytes into their allocations: same results."""
+    spec = synth.StreamSpec(64, 32, 4, 5, 8.0, 20.0, 2.0, 2, 5.0)
+    src = synth.FrameSource(spec, device=dev)
+    p, q = _params(spec)
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream())
+    orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
+    n = spec.pixels * 3
+    cbuf = torch.empty(n + 1, dtype=torch.float32, device=dev)
+    obuf = torch.empty(n + 1, dtype=torch.float32, device=dev)
+    out = obuf[1:].view(spec.height, spec.width, 3)
+    for t in range(5):
+        c, lev, gx, gy = src.frame(t)
+        cbuf[1:].copy_(c.reshape(-1))
+        res.step(cbuf[1:].view(spec.height, spec.width, 3), lev, gx, gy, out)
+        orc.push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+    res.sync()
+    _compare_state(res.download(), orc.state())
+    _compare_out(out.cpu().numpy(), orc.resolve())
+
+
+def test_resolve_before_any_frame_is_zero(dev):
+    res = fwrs.Reservoir(40, 20, 4, stream=torch.cuda.current_stream())
+    out = torch.full((20, 40, 3), 7.0, device=dev)
+    res.resolve(out)
+    res.sync()
+    assert torch.count_nonzero(out).item() == 0
+    st = res.download()
+    assert np.all(st.idx == 0xFFFFFFFF) and np.all(st.cnt == 0)
+
+
+def test_reset_and_caller_arena(dev):
+    spec = synth.StreamSpec(128, 64, 4, 4, 12.0, 30.0, 2.0, 2, 6.0)
+    p, q = _params(spec)
+    arena = torch.empty(fwrs.state_bytes(spec.width, spec.height, spec.k), dtype=torch.uint8, device=dev)
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream(), arena=arena)
+    src = synth.FrameSource(spec, device=dev)
+    out = torch.empty((spec.height, spec.width, 3), device=dev)
+    for t in range(3):
+        res.step(*src.frame(t), out)
+    res.reset()
+    assert res.frame_index == 0
+    orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
+    for t in range(4):
+        c, lev, gx, gy = src.frame(t)
+        res.step(c, lev, gx, gy, out)
+        orc.push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+    res.sync()
+    _compare_state(res.download(), orc.state())
+    _compare_out(out.cpu().numpy(), orc.resolve())
+    assert res.stats()[1] == 4 * spec.pixels
+
+
+def test_stats_count_every_slot_replacement(dev):
+    spec = synth.StreamSpec(96, 64, 4, 10, 10.0, 25.0, 2.0, 3, 6.0)
+    p, q = _params(spec)
+    src = synth.FrameSource(spec, device=dev)
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream())
+    orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
+    out = torch.empty((spec.height, spec.width, 3), device=dev)
+    expected = 0
+    for t in range(spec.frames):
+        c, lev, gx, gy = src.frame(t)
+        res.step(c, lev, gx, gy, out)
+        orc.push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+        expected += int(np.count_nonzero(orc.state().idx == t))
+    takes, updates = res.stats()
+    assert takes == expected
+    assert updates == spec.frames * spec.pixels
+
+
+def test_4k_bands_and_whole_frame_properties(dev):
+    """3840x2160, k = 4, in the launch configuration the benchmark times: bands of rows
+    (through the gaze, the periphery and the image edges) against the oracle every few frames,
+    and properties that hold at any size over the whole frame."""
+    spec = synth.spec_4k()
+    n_frames = 24
+    src = synth.FrameSource(spec, device=dev, n_frames=n_frames)
+    p, q = _params(spec)
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream())
+    orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
+    gy0 = int(src.gaze[0, 1])
+    bands = [(0, 4), (max(0, gy0 - 6), min(spec.height, gy0 + 6)), (1000, 1008), (spec.height - 4, spec.height)]
+    out = torch.empty((spec.height, spec.width, 3), device=dev)
+    for t in range(n_frames):
+        c, lev, gx, gy = src.frame(t)
+        res.step(c, lev, gx, gy, out)
+        cn, ln = c.cpu().numpy(), lev.cpu().numpy()
+        for (y0, y1) in bands:
+            orc.push_rows(cn, ln, gx, gy, y0, y1)
+        orc.advance()
+        if t in (0, 5, n_frames - 1):
+            res.sync()
+            st, so = res.download(), orc.state()
+            ref = orc.resolve()
+            o = out.cpu().numpy()
+            for (y0, y1) in bands:
+                sl = slice(y0, y1)
+                np.testing.assert_array_equal(st.idx[:, sl], so.idx[:, sl])
+                np.testing.assert_array_equal(st.cnt[sl], so.cnt[sl])
+                np.testing.assert_array_equal(st.wsum[sl].view(np.uint32), so.wsum[sl].view(np.uint32))
+                np.testing.assert_array_equal(st.wt[:, sl].view(np.uint32), so.wt[:, sl].view(np.uint32))
+                _compare_out(o[sl], ref[sl], f"4K rows {y0}-{y1} frame {t}")
+            assert np.all(st.cnt == t + 1)
+            assert np.all(st.idx <= t)
+            assert np.all(st.wt > 0) and np.all(st.wt <= 1)
+            assert np.isfinite(o).all() and o.min() >= 0.0 and o.max() <= 1.0
+    takes, updates = res.stats()
+    assert updates == n_frames * spec.pixels and takes > 0
+
+
+# ---------------------------------------------------------------------------
+# Batched engine
+# ---------------------------------------------------------------------------
+def _mix_specs():
+    return [synth.StreamSpec(256, 144, 2, 5, 12.8, 32.0, 2.0, 2, 6.0, stream_id=0),
+            synth.StreamSpec(200, 100, 4, 5, 10.0, 25.0, 2.0, 2, 6.0, stream_id=1),
+            synth.StreamSpec(96, 64, 8, 5, 5.0, 12.5, 1.0, 2, 3.0, stream_id=2),
+            synth.StreamSpec(37, 23, 3, 5, 2.0, 5.0, 1.0, 2, 2.0, stream_id=3),
+            synth.StreamSpec(320, 180, 4, 5, 16.0, 40.0, 3.0, 2, 9.0, stream_id=4)]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_engine_tick_matches_oracle_and_plain_launches(dev, use_graph):
+    specs = _mix_specs()
+    stream = torch.cuda.current_stream()
+    srcs = [synth.FrameSource(s, device=dev) for s in specs]
+    eng = fwrs.Engine(len(specs), stream=stream, use_graph=use_graph)
+    eng.set_tile(0, 16, 16)
+    eng.set_tile(30000, 64, 4)
+    batched, plain, orcs, outs_b, outs_p = [], [], [], [], []
+    for s in specs:
+        p, q = _params(s)
+        batched.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
+        plain.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
+        orcs.append(oracle.Oracle(s.width, s.height, s.k, q))
+        outs_b.append(torch.empty((s.height, s.width, 3), device=dev))
+        outs_p.append(torch.empty((s.height, s.width, 3), device=dev))
+    for t in range(5):
+        frames = [src.frame(t) for src in srcs]
+        eng.tick([(batched[i], *frames[i], outs_b[i]) for i in range(len(specs))])
+        for i in range(len(specs)):
+            plain[i].step(*frames[i], outs_p[i])
+            c, lev, gx, gy = frames[i]
+            orcs[i].push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+    torch.cuda.synchronize()
+    for i in range(len(specs)):
+        assert batched[i].frame_index == 5
+        sb = batched[i].download()
+        _compare_state(sb, orcs[i].state(), f"stream {i}")
+        _compare_out(outs_b[i].cpu().numpy(), orcs[i].resolve(), f"stream {i}")
+        assert torch.equal(outs_b[i], outs_p[i])
+        assert batched[i].stats() == plain[i].stats()
+    eng.close()
+
+
+def test_engine_stream_alone_equals_stream_in_mix(dev):
+    specs = _mix_specs()
+    stream = torch.cuda.current_stream()
+    srcs = [synth.FrameSource(s, device=dev) for s in specs]
+    eng = fwrs.Engine(len(specs), stream=stream, use_graph=True)
+    mix = [fwrs.Reservoir(s.width, s.height, s.k, _params(s)[0], stream=stream) for s in specs]
+    alone = fwrs.Reservoir(specs[1].width, specs[1].height, specs[1].k, _params(specs[1])[0], stream=stream)
+    outs = [torch.empty((s.height, s.width, 3), device=dev) for s in specs]
+    out_alone = torch.empty_like(outs[1])
+    for t in range(4):
+        frames = [src.frame(t) for src in srcs]
+        # the mix changes membership from tick to tick
+        members = [i for i in range(len(specs)) if (i + t) % 3 != 0 or i == 1]
+        eng.tick([(mix[i], *frames[i], outs[i]) for i in members])
+        eng.tick([(alone, *frames[1], out_alone)])
+        for i in range(len(specs)):
+            if i not in members:
+                mix[i].step(*frames[i], outs[i])
+    torch.cuda.synchronize()
+    assert torch.equal(outs[1], out_alone)
+    a, b = mix[1].download(), alone.download()
+    np.testing.assert_array_equal(a.idx, b.idx)
+    np.testing.assert_array_equal(a.col, b.col)
+    eng.close()
+
+
+def test_engine_rejects_bad_ticks(dev):
+    stream = torch.cuda.current_stream()
+    eng = fwrs.Engine(2, stream=stream)
+    r = fwrs.Reservoir(32, 16, 4, stream=stream)
+    c = torch.zeros((16, 32, 3), device=dev)
+    lev = torch.zeros((16, 32), dtype=torch.uint8, device=dev)
+    out = torch.empty_like(c)
+    with pytest.raises(fwrs.FwrsError):
+        eng.tick([(r, c, lev, 1.0, 1.0, out), (r, c, lev, 1.0, 1.0, out)])   # repeated context
+    with pytest.raises(ValueError):
+        eng.tick([(r, c, lev, 1.0, 1.0, out)] * 3)                            # over capacity
+    with pytest.raises(fwrs.FwrsError):
+        eng.tick([(r, c, lev, float("nan"), 1.0, out)])
+    assert r.frame_index == 0
+    with pytest.raises(fwrs.FwrsError):
+        r.set_tile(3, 8)
+    eng.close()
