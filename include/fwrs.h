@@ -95,25 +95,26 @@ typedef struct fwrs_params {
 
 typedef struct fwrs_ctx fwrs_ctx;
 
-/* Device-side view of a context's reservoir store (structure of arrays).
- * Every plane holds `pitch` elements (pitch >= width * height, a multiple of
- * 64); element p of a plane belongs to pixel p.
- *   wsum[p]                 float32  w_sum of the pixel's reservoir (Alg. 2)
- *   cnt[p]                  uint32   candidates seen, Alg. 2's m
- *   wt[j * pitch + p]       float32  render-time weight of slot j's sample
- *   idx[j * pitch + p]      uint32   frame index of slot j's sample
- *                                    (0xFFFFFFFF while empty)
- *   col[(j*3+c) * pitch + p] float32 channel c of slot j's sample
- * The pointers are owned by the context (or by the caller's arena). */
+/* Device-side view of a context's reservoir store.  N = width * height,
+ * p = y * width + x.
+ *   wsum[p]                  float32  w_sum of the pixel's reservoir (Alg. 2)
+ *   cnt[p]                   uint32   candidates seen, Alg. 2's m
+ *   rec[(p*k + j)*4 + 0]     float32  render-time weight of slot j's sample
+ *   rec[(p*k + j)*4 + 1..3]  float32  its colour (r, g, b)
+ *   idx[p*k + j]             uint32   frame index of slot j's sample
+ *                                     (0xFFFFFFFF while empty)
+ * A pixel's k slots are one contiguous 16k-byte record, so a replacement
+ * touches only that pixel's record.  `pitch` (>= N, a multiple of 64) is the
+ * element count reserved for the wsum and cnt planes.  The pointers are owned
+ * by the context (or by the caller's arena). */
 typedef struct fwrs_state_view {
     int width, height, k;
     uint32_t frame_index;   /* frames pushed so far */
     size_t pitch;
     float* wsum;
     uint32_t* cnt;
-    float* wt;
+    float* rec;
     uint32_t* idx;
-    float* col;
 } fwrs_state_view;
 
 /* Fills `p` with the defaults for an image `width` pixels wide: seed 0,
@@ -123,7 +124,7 @@ int fwrs_default_params(int width, fwrs_params* p);
 
 /* Device bytes of the reservoir store for a width x height image with k
  * slots: 4 * pitch * (2 + 5k) plus a small statistics area, where pitch is
- * width * height rounded up to 64.  Use it for admission control and to size
+ * width * height rounded up to 64 (20 bytes per slot and 8 per pixel).  Use it for admission control and to size
  * a caller-provided arena.  Returns 0 for invalid sizes. */
 size_t fwrs_state_bytes(int width, int height, int k);
 
@@ -194,8 +195,8 @@ int fwrs_download_state(fwrs_ctx* ctx, void* host, size_t host_bytes);
  * slots replaced per pixel update is slot_takes / pixel_updates. */
 int fwrs_get_stats(fwrs_ctx* ctx, uint64_t* slot_takes, uint64_t* pixel_updates);
 
-/* Selects the thread-block tile: tile_x quads (4 horizontal pixels each) by
- * tile_y rows, tile_x * tile_y in {64, 128, 256}, both powers of two.  It only
+/* Selects the thread-block tile: tile_x pixels by tile_y rows (one thread per
+ * pixel), tile_x * tile_y in {64, 128, 256}, both powers of two.  It only
  * changes the launch shape, never the results. */
 int fwrs_set_tile(fwrs_ctx* ctx, int tile_x, int tile_y);
 

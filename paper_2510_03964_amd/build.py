@@ -14,12 +14,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwrs.so")
 SOURCES = [os.path.join(CSRC, "fwrs_kernels.hip"), os.path.join(CSRC, "fwrs_api.hip")]
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 DEPS = SOURCES + [os.path.join(CSRC, "fwrs_device.hpp"), os.path.join(CSRC, "fwrs_internal.hpp"),
                   os.path.join(os.path.dirname(HERE), "include", "fwrs.h")]
 
 ARCH = "gfx950"
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", f"-I{INCLUDE}", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt", "-fno-gpu-flush-denormals-to-zero",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-command-line-argument", "-Wno-pass-failed",

@@ -12,7 +12,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/fwrs.h"
+#include "fwrs.h"
 #include "fwrs_device.hpp"
 #include "fwrs_internal.hpp"
 
@@ -106,8 +106,7 @@ struct fwrs_ctx {
     size_t pitch = 0;
     float* wsum = nullptr;
     uint32_t* cnt = nullptr;
-    float* wt = nullptr;
-    float* col = nullptr;
+    float* rec = nullptr;
     uint32_t* idx = nullptr;
     unsigned long long* stats = nullptr;
     uint32_t t = 0;
@@ -120,7 +119,7 @@ namespace {
 int clear_store(fwrs_ctx* x)
 {
     const size_t P = x->pitch, k = (size_t)x->k;
-    // wsum, cnt, wt and col are contiguous and start out zero; idx starts empty.
+    // wsum, cnt and the slot records are contiguous and start out zero; idx starts empty.
     if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->wsum), P * (2 + 4 * k), 0u, x->stream) != hipSuccess)
         return FWRS_E_HIP;
     if (fwrs::launch_fill_u32(x->idx, P * k, 0xFFFFFFFFu, x->stream) != hipSuccess) return FWRS_E_HIP;
@@ -135,7 +134,7 @@ void fill_geometry(FrameDesc& d, int width, int height, int tx, int ty)
 {
     d.tile_x_log2 = (uint32_t)log2_exact(tx);
     d.tile_y_log2 = (uint32_t)log2_exact(ty);
-    const uint32_t tile_w = (uint32_t)tx * fwrs::kQuad;
+    const uint32_t tile_w = (uint32_t)tx;
     d.tiles_x = ((uint32_t)width + tile_w - 1) / tile_w;
     const uint32_t tiles_y = ((uint32_t)height + (uint32_t)ty - 1) / (uint32_t)ty;
     const uint32_t tiles_per_item = (uint32_t)fwrs::kBlock / (uint32_t)(tx * ty);
@@ -153,13 +152,11 @@ FrameDesc make_desc(const fwrs_ctx* x, const float* color, const uint8_t* level,
     d.out = out;
     d.wsum = x->wsum;
     d.cnt = x->cnt;
-    d.wt = x->wt;
+    d.rec = x->rec;
     d.idx = x->idx;
-    d.col = x->col;
     d.stats = x->stats;
     d.width = (uint32_t)x->width;
     d.height = (uint32_t)x->height;
-    d.pitch = (uint32_t)x->pitch;
     d.t = x->t;
     d.gx = gx;
     d.gy = gy;
@@ -170,7 +167,6 @@ FrameDesc make_desc(const fwrs_ctx* x, const float* color, const uint8_t* level,
     d.k = (uint32_t)x->k;
     fill_geometry(d, x->width, x->height, tx, ty);
     d.item_begin = 0;
-    d.vec_ok = (x->width % 4 == 0) && aligned(color, 16) && aligned(out, 16) && aligned(level, 4) ? 1u : 0u;
     return d;
 }
 
@@ -251,8 +247,7 @@ int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void
     float* base = static_cast<float*>(x->arena);
     x->wsum = base;
     x->cnt = reinterpret_cast<uint32_t*>(base + P);
-    x->wt = base + 2 * P;
-    x->col = base + (2 + kk) * P;
+    x->rec = base + 2 * P;
     x->idx = reinterpret_cast<uint32_t*>(base + (2 + 4 * kk) * P);
     x->stats = reinterpret_cast<unsigned long long*>(base + (2 + 5 * kk) * P);
     const int rc = clear_store(x);
@@ -338,9 +333,8 @@ int fwrs_get_state(const fwrs_ctx* x, fwrs_state_view* v)
     v->pitch = x->pitch;
     v->wsum = x->wsum;
     v->cnt = x->cnt;
-    v->wt = x->wt;
+    v->rec = x->rec;
     v->idx = x->idx;
-    v->col = x->col;
     return FWRS_OK;
 }
 
@@ -349,20 +343,38 @@ int fwrs_download_state(fwrs_ctx* x, void* host, size_t host_bytes)
     if (!x || !host || host_bytes != fwrs_state_host_bytes(x->width, x->height, x->k)) return FWRS_E_ARG;
     DeviceGuard g(x->device);
     if (!g.ok) return FWRS_E_HIP;
-    const size_t N = (size_t)x->width * (size_t)x->height, P = x->pitch, k = (size_t)x->k;
+    const size_t N = (size_t)x->width * (size_t)x->height, k = (size_t)x->k;
+    std::vector<float> rec;
+    std::vector<uint32_t> idx;
+    try {
+        rec.resize(N * k * 4);
+        idx.resize(N * k);
+    } catch (const std::bad_alloc&) {
+        return FWRS_E_NOMEM;
+    }
     char* h = static_cast<char*>(host);
-    auto copy_planes = [&](const void* src, size_t planes) -> bool {
-        for (size_t i = 0; i < planes; ++i) {
-            const char* s = static_cast<const char*>(src) + i * P * 4;
-            if (hipMemcpyAsync(h, s, N * 4, hipMemcpyDeviceToHost, x->stream) != hipSuccess) return false;
-            h += N * 4;
-        }
-        return true;
-    };
-    if (!copy_planes(x->wsum, 1) || !copy_planes(x->cnt, 1) || !copy_planes(x->wt, k) || !copy_planes(x->idx, k) ||
-        !copy_planes(x->col, 3 * k))
+    float* wsum = reinterpret_cast<float*>(h);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(h + 4 * N);
+    float* wt = reinterpret_cast<float*>(h + 8 * N);
+    uint32_t* hidx = reinterpret_cast<uint32_t*>(h + (8 + 4 * k) * N);
+    float* col = reinterpret_cast<float*>(h + (8 + 8 * k) * N);
+    if (hipMemcpyAsync(wsum, x->wsum, 4 * N, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
+        hipMemcpyAsync(cnt, x->cnt, 4 * N, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
+        hipMemcpyAsync(rec.data(), x->rec, 16 * N * k, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
+        hipMemcpyAsync(idx.data(), x->idx, 4 * N * k, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
+        hipStreamSynchronize(x->stream) != hipSuccess)
         return FWRS_E_HIP;
-    return hipStreamSynchronize(x->stream) == hipSuccess ? FWRS_OK : FWRS_E_HIP;
+    // device records [N][k]{w, r, g, b} -> packed planes wt[k][N], idx[k][N], col[k][3][N]
+    for (size_t p = 0; p < N; ++p)
+        for (size_t j = 0; j < k; ++j) {
+            const float* r = &rec[(p * k + j) * 4];
+            wt[j * N + p] = r[0];
+            col[(j * 3 + 0) * N + p] = r[1];
+            col[(j * 3 + 1) * N + p] = r[2];
+            col[(j * 3 + 2) * N + p] = r[3];
+            hidx[j * N + p] = idx[p * k + j];
+        }
+    return FWRS_OK;
 }
 
 int fwrs_get_stats(fwrs_ctx* x, uint64_t* slot_takes, uint64_t* pixel_updates)

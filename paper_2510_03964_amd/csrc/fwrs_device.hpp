@@ -32,25 +32,21 @@ struct Consts {
 struct alignas(16) FrameDesc {
     const float* color;         // [H][W][3] f32, the new candidates
     const uint8_t* level;       // [H][W] u8 foveation level
-    float* out;                 // [H][W][3] f32 resolve target (may be null for push-only)
-    float* wsum;                // [pitch]
-    uint32_t* cnt;              // [pitch]
-    float* wt;                  // [k][pitch]
-    uint32_t* idx;              // [k][pitch]
-    float* col;                 // [k][3][pitch]
+    float* out;                 // [H][W][3] f32 resolve target (null for update-only)
+    float* wsum;                // [N] w_sum per pixel
+    uint32_t* cnt;              // [N] candidates seen per pixel (m)
+    float* rec;                 // [N][k][4] slot records {w, r, g, b}
+    uint32_t* idx;              // [N][k] frame index of each slot's sample
     unsigned long long* stats;  // [kStatSlots] slot-take counters, or null
-    uint32_t width, height, pitch, t;
+    uint32_t width, height, t, k;
     float gx, gy;
     Consts c;
-    uint32_t seed, stream_id, bias, k;
+    uint32_t seed, stream_id, bias;
     uint32_t tile_x_log2, tile_y_log2, tiles_x, items;  // launch geometry
     uint32_t item_begin;        // first work item of this frame in a batched tick
-    uint32_t vec_ok;            // width % 4 == 0 and 16-byte aligned buffers
-    uint32_t pad[2];
 };
 
 constexpr int kBlock = 256;             // threads per block
-constexpr int kQuad = 4;                // pixels per thread
 constexpr int kStatSlots = 1024;        // spread of the slot-take counters
 constexpr uint32_t kBiasNone = 0u;
 constexpr uint32_t kBiasBernoulli = 1u;

@@ -1,12 +1,18 @@
 // HIP kernels of the weighted-reservoir-sampling pass for gfx950.
 //
-// One thread owns a quad of 4 horizontally adjacent pixels, so that every
-// structure-of-arrays plane is read and written with one 128-bit access per
-// thread and the RGB (HWC) frame and output with three.  A block of 256
-// threads covers one work item of 1024 pixels laid out as 1, 2 or 4 tiles of
-// tile_x quads by tile_y rows (the tile shape changes the access pattern,
-// never the results).  The pass is bound by HBM traffic, not arithmetic: there
-// is no contraction anywhere, so no matrix cores.
+// Store layout (per context, N pixels, k slots): w_sum[N] and m[N] as planes,
+// one record of k slots per pixel, rec[p * k + j] = {w, r, g, b} (16k bytes,
+// so at k = 4 a pixel's record is exactly one 64-byte sector), and the slots'
+// frame indices idx[p * k + j].  A slot replacement therefore dirties only the
+// sector of the pixel that replaced it, not one sector in each of k * 4
+// planes; reads of whole records stay contiguous across a wave.
+//
+// One thread per pixel; a block of 256 threads covers one work item laid out
+// as 1, 2 or 4 tiles of tile_x pixels by tile_y rows (the tile shape changes
+// the access pattern, never the results).  Every load a pixel needs is issued
+// before the arithmetic so that each wave has its whole footprint in flight
+// while the Philox rounds and the weight run.  The pass is bound by HBM
+// traffic; there is no contraction anywhere, so no matrix cores.
 //
 // Per pixel and frame (Sec. 4.1-4.2 of the paper):
 //   w    = Eq. 4 weight from the eccentricity to the gaze (level 0 -> 1)
@@ -14,8 +20,7 @@
 //   slot j takes (colour, w, t) when u_j * (W1' + w) > W1'   (Alg. 2)
 //   w_sum <- W1' + w;  m <- m + 1
 //   out  = sum_j wt_j col_j / sum_j wt_j                      (resolve)
-// The new colour is read only for quads in which some slot takes it, and a
-// slot plane is written only where some pixel of the quad replaced that slot.
+// The new colour is read only by pixels in which some slot takes it.
 #include "fwrs_device.hpp"
 #include "fwrs_internal.hpp"
 
@@ -33,7 +38,7 @@ __device__ __forceinline__ uint32_t decide(const FrameDesc& d, uint32_t p, float
     const int kk = K ? K : (int)d.k;
     uint32_t mask = 0u;
 #pragma unroll
-    for (int b = 0; b < (K ? (K + 3) / 4 : 4); ++b) {
+    for (int b = 0; b < (K ? (K + 3) / 4 : kMaxK / 4); ++b) {
         if (!K && 4 * b >= kk) break;
         const uint4 r = philox4x32_10(p, d.t, (uint32_t)b, 0u, d.seed, d.stream_id);
         const uint32_t words[4] = {r.x, r.y, r.z, r.w};
@@ -49,196 +54,113 @@ __device__ __forceinline__ uint32_t decide(const FrameDesc& d, uint32_t p, float
     return mask;
 }
 
-__device__ __forceinline__ float sel4(const float4& v, int i)
-{
-    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
-}
+struct Rgb {
+    float r, g, b;
+};
 
 // ---------------------------------------------------------------------------
-// A full quad with 16-byte aligned accesses: x0 % 4 == 0, x0 + 3 < width and
-// width % 4 == 0, so p0 = y * width + x0 is a multiple of 4.
-// ---------------------------------------------------------------------------
-template <int K, int OP>
-__device__ __forceinline__ uint32_t quad_vec(const FrameDesc& d, uint32_t x0, uint32_t y)
-{
-    const uint32_t p0 = y * d.width + x0;
-    const size_t P = d.pitch;
-    const int kk = K ? K : (int)d.k;
-    uint32_t tk[4] = {0u, 0u, 0u, 0u};
-    float w[4] = {0.f, 0.f, 0.f, 0.f};
-    uint32_t ntakes = 0u;
-
-    if (OP & kPush) {
-        const uint32_t lv = *reinterpret_cast<const uint32_t*>(d.level + p0);
-        const float4 W1 = *reinterpret_cast<const float4*>(d.wsum + p0);
-        const uint4 m = *reinterpret_cast<const uint4*>(d.cnt + p0);
-        const float dy = ((float)y + 0.5f) - d.gy;
-        const float dy2 = dy * dy;
-        const float W1v[4] = {W1.x, W1.y, W1.z, W1.w};
-        float sv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float dx = ((float)(x0 + i) + 0.5f) - d.gx;
-            w[i] = weight_eq4(d.c, dx * dx + dy2, (lv >> (8 * i)) & 0xFFu);
-            const float W1b = bias_eq6(W1v[i], w[i], d.bias);
-            sv[i] = W1b + w[i];
-            tk[i] = decide<K>(d, p0 + i, W1b, sv[i]);
-            ntakes += __popc(tk[i]);
-        }
-        *reinterpret_cast<float4*>(d.wsum + p0) = make_float4(sv[0], sv[1], sv[2], sv[3]);
-        *reinterpret_cast<uint4*>(d.cnt + p0) = make_uint4(m.x + 1u, m.y + 1u, m.z + 1u, m.w + 1u);
-    }
-
-    const uint32_t any = tk[0] | tk[1] | tk[2] | tk[3];
-    float cin[12];
-    if (any) {
-        const float4* src = reinterpret_cast<const float4*>(d.color + 3 * (size_t)p0);
-        const float4 a = src[0], b = src[1], c = src[2];
-        cin[0] = a.x; cin[1] = a.y; cin[2] = a.z; cin[3] = a.w;
-        cin[4] = b.x; cin[5] = b.y; cin[6] = b.z; cin[7] = b.w;
-        cin[8] = c.x; cin[9] = c.y; cin[10] = c.z; cin[11] = c.w;
-    }
-
-    float4 S = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 acc[3] = {S, S, S};
-#pragma unroll
-    for (int j = 0; j < (K ? K : kMaxK); ++j) {
-        if (!K && j >= kk) break;
-        const uint32_t qm = ((tk[0] >> j) & 1u) | (((tk[1] >> j) & 1u) << 1) | (((tk[2] >> j) & 1u) << 2) |
-                            (((tk[3] >> j) & 1u) << 3);
-        float* wtp = d.wt + (size_t)j * P + p0;
-        float* c0p = d.col + ((size_t)j * 3 + 0) * P + p0;
-        float* c1p = d.col + ((size_t)j * 3 + 1) * P + p0;
-        float* c2p = d.col + ((size_t)j * 3 + 2) * P + p0;
-        float4 wj = make_float4(0.f, 0.f, 0.f, 0.f), cj0 = wj, cj1 = wj, cj2 = wj;
-        const bool need_old = (OP & kResolve) || (qm != 0u && qm != 0xFu);
-        if (need_old) {
-            wj = *reinterpret_cast<const float4*>(wtp);
-            cj0 = *reinterpret_cast<const float4*>(c0p);
-            cj1 = *reinterpret_cast<const float4*>(c1p);
-            cj2 = *reinterpret_cast<const float4*>(c2p);
-        }
-        if (qm) {
-            float* wv = &wj.x;
-            float* v0 = &cj0.x;
-            float* v1 = &cj1.x;
-            float* v2 = &cj2.x;
-            uint32_t* ip = d.idx + (size_t)j * P + p0;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (qm & (1u << i)) {
-                    wv[i] = w[i];
-                    v0[i] = cin[3 * i + 0];
-                    v1[i] = cin[3 * i + 1];
-                    v2[i] = cin[3 * i + 2];
-                    ip[i] = d.t;
-                }
-            }
-            *reinterpret_cast<float4*>(wtp) = wj;
-            *reinterpret_cast<float4*>(c0p) = cj0;
-            *reinterpret_cast<float4*>(c1p) = cj1;
-            *reinterpret_cast<float4*>(c2p) = cj2;
-        }
-        if (OP & kResolve) {
-            S.x = S.x + wj.x; S.y = S.y + wj.y; S.z = S.z + wj.z; S.w = S.w + wj.w;
-            acc[0].x = acc[0].x + wj.x * cj0.x; acc[0].y = acc[0].y + wj.y * cj0.y;
-            acc[0].z = acc[0].z + wj.z * cj0.z; acc[0].w = acc[0].w + wj.w * cj0.w;
-            acc[1].x = acc[1].x + wj.x * cj1.x; acc[1].y = acc[1].y + wj.y * cj1.y;
-            acc[1].z = acc[1].z + wj.z * cj1.z; acc[1].w = acc[1].w + wj.w * cj1.w;
-            acc[2].x = acc[2].x + wj.x * cj2.x; acc[2].y = acc[2].y + wj.y * cj2.y;
-            acc[2].z = acc[2].z + wj.z * cj2.z; acc[2].w = acc[2].w + wj.w * cj2.w;
-        }
-    }
-
-    if (OP & kResolve) {
-        float o[12];
-        const float Sv[4] = {S.x, S.y, S.z, S.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            // S == 0 only before the first frame (every kept weight is > 0): output 0.
-            const float r = Sv[i] > 0.0f ? 1.0f / Sv[i] : 0.0f;
-            o[3 * i + 0] = sel4(acc[0], i) * r;
-            o[3 * i + 1] = sel4(acc[1], i) * r;
-            o[3 * i + 2] = sel4(acc[2], i) * r;
-        }
-        float4* dst = reinterpret_cast<float4*>(d.out + 3 * (size_t)p0);
-        dst[0] = make_float4(o[0], o[1], o[2], o[3]);
-        dst[1] = make_float4(o[4], o[5], o[6], o[7]);
-        dst[2] = make_float4(o[8], o[9], o[10], o[11]);
-    }
-    return ntakes;
-}
-
-// ---------------------------------------------------------------------------
-// Any single pixel, scalar accesses (ragged widths, unaligned buffers, the
-// right edge).  Same arithmetic as quad_vec.
+// One pixel.  K > 0 keeps the pixel's whole record in registers; K == 0
+// (any slot count up to kMaxK) streams the record one slot at a time.
 // ---------------------------------------------------------------------------
 template <int K, int OP>
-__device__ __forceinline__ uint32_t pixel_scalar(const FrameDesc& d, uint32_t x, uint32_t y)
+__device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32_t y)
 {
     const uint32_t p = y * d.width + x;
-    const size_t P = d.pitch;
     const int kk = K ? K : (int)d.k;
+    float4* rec = reinterpret_cast<float4*>(d.rec) + (size_t)p * (size_t)kk;
+    uint32_t* idx = d.idx + (size_t)p * (size_t)kk;
+    const Rgb* color = reinterpret_cast<const Rgb*>(d.color) + p;
+
+    // 1. loads: per-pixel state, then the record (compile-time K), all in flight together
+    uint32_t lv = 0u, m = 0u;
+    float W1 = 0.f;
+    if (OP & kPush) {
+        lv = d.level[p];
+        W1 = d.wsum[p];
+        m = d.cnt[p];
+    }
+    float4 r[K ? K : 1];
+    if (K && (OP & kResolve)) {
+#pragma unroll
+        for (int j = 0; j < (K ? K : 1); ++j) r[j] = rec[j];
+    }
+
+    // 2. weight, bias and decisions
     uint32_t tk = 0u;
     float w = 0.f;
     if (OP & kPush) {
-        const uint32_t lv = d.level[p];
-        const float W1 = d.wsum[p];
-        const float dy = ((float)y + 0.5f) - d.gy;
         const float dx = ((float)x + 0.5f) - d.gx;
+        const float dy = ((float)y + 0.5f) - d.gy;
         w = weight_eq4(d.c, dx * dx + dy * dy, lv);
         const float W1b = bias_eq6(W1, w, d.bias);
         const float s = W1b + w;
         tk = decide<K>(d, p, W1b, s);
         d.wsum[p] = s;
-        d.cnt[p] = d.cnt[p] + 1u;
+        d.cnt[p] = m + 1u;
     }
-    float cin0 = 0.f, cin1 = 0.f, cin2 = 0.f;
-    if (tk) {
-        cin0 = d.color[3 * (size_t)p + 0];
-        cin1 = d.color[3 * (size_t)p + 1];
-        cin2 = d.color[3 * (size_t)p + 2];
-    }
-    float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
+
+    // 3. the new colour where some slot takes it, then the replaced slots
+    Rgb c{0.f, 0.f, 0.f};
+    if (tk) c = *color;
+    const float4 fresh = make_float4(w, c.r, c.g, c.b);
+    if (K) {
 #pragma unroll
-    for (int j = 0; j < (K ? K : kMaxK); ++j) {
-        if (!K && j >= kk) break;
-        const size_t o = (size_t)j * P + p;
-        float wj, c0, c1, c2;
-        if ((tk >> j) & 1u) {
-            wj = w; c0 = cin0; c1 = cin1; c2 = cin2;
-            d.wt[o] = wj;
-            d.idx[o] = d.t;
-            d.col[((size_t)j * 3 + 0) * P + p] = c0;
-            d.col[((size_t)j * 3 + 1) * P + p] = c1;
-            d.col[((size_t)j * 3 + 2) * P + p] = c2;
-        } else if (OP & kResolve) {
-            wj = d.wt[o];
-            c0 = d.col[((size_t)j * 3 + 0) * P + p];
-            c1 = d.col[((size_t)j * 3 + 1) * P + p];
-            c2 = d.col[((size_t)j * 3 + 2) * P + p];
-        } else {
-            continue;
-        }
-        if (OP & kResolve) {
-            S = S + wj;
-            a0 = a0 + wj * c0;
-            a1 = a1 + wj * c1;
-            a2 = a2 + wj * c2;
+        for (int j = 0; j < (K ? K : 1); ++j) {
+            if ((tk >> j) & 1u) {
+                r[j] = fresh;
+                rec[j] = fresh;
+                idx[j] = d.t;
+            }
         }
     }
+
+    // 4. resolve: sum_j w_j col_j / sum_j w_j, slot order
     if (OP & kResolve) {
-        const float r = S > 0.0f ? 1.0f / S : 0.0f;
-        d.out[3 * (size_t)p + 0] = a0 * r;
-        d.out[3 * (size_t)p + 1] = a1 * r;
-        d.out[3 * (size_t)p + 2] = a2 * r;
+        float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        if (K) {
+#pragma unroll
+            for (int j = 0; j < (K ? K : 1); ++j) {
+                S = S + r[j].x;
+                a0 = a0 + r[j].x * r[j].y;
+                a1 = a1 + r[j].x * r[j].z;
+                a2 = a2 + r[j].x * r[j].w;
+            }
+        } else {
+            for (int j = 0; j < kk; ++j) {
+                float4 v;
+                if ((tk >> j) & 1u) {
+                    v = fresh;
+                    rec[j] = fresh;
+                    idx[j] = d.t;
+                } else {
+                    v = rec[j];
+                }
+                S = S + v.x;
+                a0 = a0 + v.x * v.y;
+                a1 = a1 + v.x * v.z;
+                a2 = a2 + v.x * v.w;
+            }
+        }
+        // S == 0 only before the first frame (every kept weight is > 0): output 0.
+        const float rs = S > 0.0f ? 1.0f / S : 0.0f;
+        Rgb o;
+        o.r = a0 * rs;
+        o.g = a1 * rs;
+        o.b = a2 * rs;
+        reinterpret_cast<Rgb*>(d.out)[p] = o;
+    } else if (!K) {
+        for (int j = 0; j < kk; ++j)
+            if ((tk >> j) & 1u) {
+                rec[j] = fresh;
+                idx[j] = d.t;
+            }
     }
     return __popc(tk);
 }
 
 // ---------------------------------------------------------------------------
-// One work item (1024 pixels) of a frame.  The wave index is made explicit
-// as a uniform value so the tile arithmetic runs on the scalar unit.
+// One work item (256 pixels).  The wave index is made explicit as a uniform
+// value so the tile arithmetic runs on the scalar unit.
 // ---------------------------------------------------------------------------
 template <int K, int OP>
 __device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t item)
@@ -253,15 +175,10 @@ __device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t it
     const uint32_t local = ((wave & ((1u << waves_per_tile_log2) - 1u)) << 6) | lane;
     const uint32_t ty = tile / d.tiles_x;
     const uint32_t tx = tile - ty * d.tiles_x;
-    const uint32_t qx = local & ((1u << d.tile_x_log2) - 1u);
-    const uint32_t ly = local >> d.tile_x_log2;
-    const uint32_t x0 = ((tx << d.tile_x_log2) + qx) * kQuad;
-    const uint32_t y = (ty << d.tile_y_log2) + ly;
-    if (y >= d.height || x0 >= d.width) return 0u;
-    if (d.vec_ok && x0 + 3u < d.width) return quad_vec<K, OP>(d, x0, y);
-    uint32_t n = 0u;
-    for (uint32_t x = x0; x < x0 + kQuad && x < d.width; ++x) n += pixel_scalar<K, OP>(d, x, y);
-    return n;
+    const uint32_t x = (tx << d.tile_x_log2) + (local & ((1u << d.tile_x_log2) - 1u));
+    const uint32_t y = (ty << d.tile_y_log2) + (local >> d.tile_x_log2);
+    if (y >= d.height || x >= d.width) return 0u;
+    return pixel<K, OP>(d, x, y);
 }
 
 __device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t v)
@@ -287,7 +204,8 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(FrameDesc d)
 // frames in the table (sorted by item_begin); each block keeps the index of
 // the frame its current item belongs to, which only moves forward.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void tick_kernel(const FrameDesc* __restrict__ descs, const uint32_t* __restrict__ hdr)
+__global__ __launch_bounds__(kBlock) void tick_kernel(const FrameDesc* __restrict__ descs,
+                                                      const uint32_t* __restrict__ hdr)
 {
     const uint32_t nframes = hdr[0];
     const uint32_t total = hdr[1];

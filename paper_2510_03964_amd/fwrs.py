@@ -63,9 +63,8 @@ class StateView(C.Structure):
         ("pitch", C.c_size_t),
         ("wsum", C.c_void_p),
         ("cnt", C.c_void_p),
-        ("wt", C.c_void_p),
+        ("rec", C.c_void_p),
         ("idx", C.c_void_p),
-        ("col", C.c_void_p),
     ]
 
 
@@ -90,7 +89,7 @@ def load(path: str | None = None):
     global _lib
     if _lib is not None and path is None:
         return _lib
-    p = path or LIB_PATH
+    p = path or os.environ.get("FWRS_LIB") or LIB_PATH
     if not os.path.exists(p):
         raise FileNotFoundError(f"{p} is missing: build it with `python -m paper_2510_03964_amd.build`")
     L = C.CDLL(p)

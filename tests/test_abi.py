@@ -53,12 +53,12 @@ def test_struct_layouts_match_header(tmp_path):
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "fwrs.h"\n'
         "int main(void){printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(fwrs_params), sizeof(fwrs_state_view),"
-        " sizeof(fwrs_frame), offsetof(fwrs_frame, out), offsetof(fwrs_state_view, col)); return 0;}\n")
+        " sizeof(fwrs_frame), offsetof(fwrs_frame, out), offsetof(fwrs_state_view, idx)); return 0;}\n")
     exe = tmp_path / "l"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [C.sizeof(fwrs.Params), C.sizeof(fwrs.StateView), C.sizeof(fwrs.Frame),
-                   fwrs.Frame.out.offset, fwrs.StateView.col.offset]
+                   fwrs.Frame.out.offset, fwrs.StateView.idx.offset]
 
 
 def test_default_params_and_sizes():
