@@ -8,10 +8,12 @@ the device before timing; a step is one fused update + resolve
 (fwrs_push_frame_resolve) of one frame, starting from an empty reservoir.
 
 Prints one JSON line: Gpixel-updates/s, ms per frame, the roofline of the
-fused kernel (algorithmic bytes per pixel-update 41 + 16k + 20 r, with r the
+fused kernel (algorithmic bytes per pixel-update 33 + 16k + 20 r, with r the
 slot replacements per pixel-update counted by the kernel, over its average
 launch time from HIP events on its stream), and the CPU oracle timed on a
-bounded sample of the same workload.
+bounded sample of the same workload.  The same frames are then run through
+the incremental entry point (output rewritten only where a slot changed),
+reported in its own object with its own byte model.
 """
 from __future__ import annotations
 
@@ -36,9 +38,16 @@ def log(msg: str) -> None:
 
 def bytes_per_update(k: int, rbar: float) -> float:
     """Algorithmic HBM bytes per pixel-update of the fused pass: colour in (12), level (1),
-    w_sum + m read and written (16), output (12), every slot's colour and weight read for the
+    w_sum read and written (8), output (12), every slot's colour and weight read for the
     resolve (16 k), and colour + weight + index written per replaced slot (20 per take)."""
-    return 41.0 + 16.0 * k + 20.0 * rbar
+    return 33.0 + 16.0 * k + 20.0 * rbar
+
+
+def bytes_per_update_incremental(k: int, rbar: float, changed: float) -> float:
+    """Same for the incremental pass: level (1) and w_sum read + write (8) everywhere; colour in,
+    the record read and the output written (12 + 16 k + 12) only at the fraction `changed` of
+    pixel-updates where some slot was replaced; 20 bytes per replaced slot."""
+    return 9.0 + changed * (24.0 + 16.0 * k) + 20.0 * rbar
 
 
 def kernel_source_hash() -> str:
@@ -60,6 +69,28 @@ def traffic_from_counters(n_pixels: int) -> float | None:
     if c.get("source_hash") != kernel_source_hash() or c.get("pixels") != n_pixels:
         return None
     return 1024.0 * (c["fetch_kib_per_dispatch"] * c["fetch_scale"] + c["write_kib_per_dispatch"] * c["write_scale"])
+
+
+def timed_run(res, frames, out, stream, step):
+    """Times len(frames) calls of `step` (one per frame) with HIP events on `stream`: per-launch
+    start/end events and one pair around the whole region."""
+    import numpy as np
+    import torch
+
+    K = len(frames)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for t in range(K):
+        c, lev, gx, gy = frames[t]
+        ev[t][0].record(stream)
+        step(c, lev, gx, gy, out)
+        ev[t][1].record(stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    return t_start.elapsed_time(t_end), np.array([a.elapsed_time(b) for (a, b) in ev])
 
 
 def cpu_baseline(frames_host, spec, n_frames: int) -> dict:
@@ -104,6 +135,7 @@ def main() -> int:
     ap.add_argument("--cpu-frames", type=int, default=8, help="frames of the oracle CPU baseline (0: skip)")
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y override")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth reference")
+    ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-resolve run")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -146,27 +178,12 @@ def main() -> int:
     res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=stream)
     if tile:
         res.set_tile(*tile)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    t_start.record(stream)
-    for t in range(K):
-        c, lev, gx, gy = frames[t]
-        ev[t][0].record(stream)
-        res.step(c, lev, gx, gy, out)
-        ev[t][1].record(stream)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    total_ms = t_start.elapsed_time(t_end)
-    per = np.array([a.elapsed_time(b) for (a, b) in ev])
-    log(f"timed {K} frames: {total_ms:.2f} ms on the GPU clock, {wall * 1e3:.1f} ms wall")
-
-    takes, updates = res.stats()
+    total_ms, per = timed_run(res, frames, out, stream, res.step)
+    log(f"timed {K} frames: {total_ms:.2f} ms on the GPU clock")
+    takes, changed, updates = res.stats()
     assert updates == K * spec.pixels
     st_ok = res.frame_index == K
+    res.close()
     rbar = takes / updates
     B = bytes_per_update(spec.k, rbar)
     kern_ms = float(per.mean())
@@ -174,6 +191,31 @@ def main() -> int:
     traffic = traffic_from_counters(spec.pixels)
     ms_per_step = total_ms / K
     value = spec.pixels * K / (total_ms / 1e3) / 1e9
+
+    incremental = None
+    if not args.no_incremental:
+        inc = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=stream)
+        if tile:
+            inc.set_tile(*tile)
+        inc.step(*frames[0], out)            # frame 0: every pixel takes, full resolve
+        inc_ms, inc_per = timed_run(inc, frames[1:], out, stream, inc.step_incremental)
+        i_takes, i_changed, i_updates = inc.stats()
+        inc.close()
+        n_inc = K - 1
+        i_rbar = (i_takes - spec.k * spec.pixels) / (n_inc * spec.pixels)
+        i_changed_frac = (i_changed - spec.pixels) / (n_inc * spec.pixels)
+        i_B = bytes_per_update_incremental(spec.k, i_rbar, i_changed_frac)
+        i_kern = float(inc_per.mean())
+        i_ach = spec.pixels * i_B / (i_kern / 1e3) / 1e9
+        incremental = {"entry": "fwrs_push_frame_resolve_incremental", "frames": n_inc,
+                       "ms_per_step": inc_ms / n_inc, "value": spec.pixels * n_inc / (inc_ms / 1e3) / 1e9,
+                       "unit": "Gpixel-updates/s", "ms_per_frame_p50": float(np.percentile(inc_per, 50)),
+                       "ms_per_frame_p99": float(np.percentile(inc_per, 99)),
+                       "roofline": {"bound": "hbm", "achieved": i_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                    "frac": i_ach / HBM_PEAK_GBPS, "kernel_ms_avg": i_kern,
+                                    "bytes_per_pixel_update": i_B, "slot_takes_per_pixel_update": i_rbar,
+                                    "changed_pixel_fraction": i_changed_frac}}
+        log(f"incremental: {inc_ms / n_inc:.4f} ms/frame")
 
     copy_gbps = None if args.no_copy else copy_bandwidth(torch, dev)
 
@@ -203,11 +245,13 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
-                     "kernel": "fwrs::frame_kernel<4, 3> (fused update + resolve)",
+                     "kernel": "fwrs::frame_kernel<4, 3> (fused update + full resolve)",
                      "kernel_ms_avg": kern_ms, "bytes_per_pixel_update": B, "slot_takes_per_pixel_update": rbar},
         "cpu_baseline": cpu,
         "ms_per_frame_p50": float(np.percentile(per, 50)),
         "ms_per_frame_p99": float(np.percentile(per, 99)),
+        "pixels_changed_per_pixel_update": changed / updates,
+        "incremental": incremental,
         "copy_gbps": copy_gbps,
         "state_ok": bool(st_ok),
     }

@@ -98,21 +98,21 @@ typedef struct fwrs_ctx fwrs_ctx;
 /* Device-side view of a context's reservoir store.  N = width * height,
  * p = y * width + x.
  *   wsum[p]                  float32  w_sum of the pixel's reservoir (Alg. 2)
- *   cnt[p]                   uint32   candidates seen, Alg. 2's m
  *   rec[(p*k + j)*4 + 0]     float32  render-time weight of slot j's sample
  *   rec[(p*k + j)*4 + 1..3]  float32  its colour (r, g, b)
  *   idx[p*k + j]             uint32   frame index of slot j's sample
  *                                     (0xFFFFFFFF while empty)
  * A pixel's k slots are one contiguous 16k-byte record, so a replacement
  * touches only that pixel's record.  `pitch` (>= N, a multiple of 64) is the
- * element count reserved for the wsum and cnt planes.  The pointers are owned
- * by the context (or by the caller's arena). */
+ * element count reserved for the wsum plane.  Alg. 2's candidate count m is
+ * the same for every pixel -- each pixel receives one candidate per frame --
+ * so it is frame_index and has no plane.  The pointers are owned by the
+ * context (or by the caller's arena). */
 typedef struct fwrs_state_view {
     int width, height, k;
     uint32_t frame_index;   /* frames pushed so far */
     size_t pitch;
     float* wsum;
-    uint32_t* cnt;
     float* rec;
     uint32_t* idx;
 } fwrs_state_view;
@@ -123,9 +123,10 @@ typedef struct fwrs_state_view {
 int fwrs_default_params(int width, fwrs_params* p);
 
 /* Device bytes of the reservoir store for a width x height image with k
- * slots: 4 * pitch * (2 + 5k) plus a small statistics area, where pitch is
- * width * height rounded up to 64 (20 bytes per slot and 8 per pixel).  Use it for admission control and to size
- * a caller-provided arena.  Returns 0 for invalid sizes. */
+ * slots: 4 * pitch * (1 + 5k) plus a small statistics area, where pitch is
+ * width * height rounded up to 64 (20 bytes per slot and 4 per pixel).  Use
+ * it for admission control and to size a caller-provided arena.  Returns 0
+ * for invalid sizes. */
 size_t fwrs_state_bytes(int width, int height, int k);
 
 /* Host bytes written by fwrs_download_state: width * height * (8 + 20k). */
@@ -133,7 +134,7 @@ size_t fwrs_state_host_bytes(int width, int height, int k);
 
 /* Creates a context with fwrs_default_params(width) on the null stream of the
  * current device.  The library allocates the reservoir store and clears it
- * to the empty state (w_sum = 0, m = 0, wt = 0, col = 0, idx = 0xFFFFFFFF).
+ * to the empty state (w_sum = 0, wt = 0, col = 0, idx = 0xFFFFFFFF; m = 0).
  * FWRS_E_ARG: width or height <= 0, width * height >= 2^31, k outside
  * [1, FWRS_MAX_K], out NULL.  FWRS_E_NOMEM: allocation failed. */
 int fwrs_create(int width, int height, int k, fwrs_ctx** out);
@@ -178,6 +179,18 @@ int fwrs_resolve(fwrs_ctx* ctx, float* out);
 int fwrs_push_frame_resolve(fwrs_ctx* ctx, const float* color, const uint8_t* level_map, float gaze_x,
                             float gaze_y, float* out);
 
+/* fwrs_push_frame_resolve for a caller that keeps its output between frames:
+ * writes `out` only at the pixels where some slot was replaced this frame,
+ * because every other pixel's resolve is unchanged.  The result is
+ * bit-identical to fwrs_push_frame_resolve.  Precondition, checked by the
+ * library: `out` is the buffer this context last resolved into -- the `out`
+ * of the previous fwrs_push_frame_resolve, fwrs_push_frame_resolve_incremental,
+ * fwrs_resolve or batched tick of this context, with no fwrs_push_frame or
+ * fwrs_reset since -- and the caller has not modified it.  FWRS_E_STATE if
+ * the library's record of the last resolve does not match. */
+int fwrs_push_frame_resolve_incremental(fwrs_ctx* ctx, const float* color, const uint8_t* level_map,
+                                        float gaze_x, float gaze_y, float* out);
+
 /* Frames pushed so far (host-side counter; no synchronisation). */
 int fwrs_frame_index(const fwrs_ctx* ctx, uint32_t* frame_index);
 
@@ -186,14 +199,14 @@ int fwrs_get_state(const fwrs_ctx* ctx, fwrs_state_view* view);
 
 /* Synchronises the stream and copies the store to host memory, packed
  * without padding in the order wsum[N], cnt[N], wt[k][N], idx[k][N],
- * col[k][3][N] (N = width * height).  `host_bytes` must equal
+ * col[k][3][N] (N = width * height; cnt[p] = m = frame_index).  `host_bytes` must equal
  * fwrs_state_host_bytes(...). */
 int fwrs_download_state(fwrs_ctx* ctx, void* host, size_t host_bytes);
 
-/* Synchronises the stream and returns the number of slot replacements (takes)
- * and pixel updates since creation or the last reset.  The average number of
- * slots replaced per pixel update is slot_takes / pixel_updates. */
-int fwrs_get_stats(fwrs_ctx* ctx, uint64_t* slot_takes, uint64_t* pixel_updates);
+/* Synchronises the stream and returns, since creation or the last reset, the
+ * number of slot replacements (takes), of pixel updates in which at least one
+ * slot was replaced, and of pixel updates.  Any pointer may be NULL. */
+int fwrs_get_stats(fwrs_ctx* ctx, uint64_t* slot_takes, uint64_t* pixels_changed, uint64_t* pixel_updates);
 
 /* Selects the thread-block tile: tile_x pixels by tile_y rows (one thread per
  * pixel), tile_x * tile_y in {64, 128, 256}, both powers of two.  It only

@@ -21,8 +21,8 @@ using fwrs::FrameDesc;
 namespace {
 
 constexpr size_t kPitchAlign = 64;   // elements; planes start on 256-byte boundaries
-constexpr size_t kStatBytes = sizeof(unsigned long long) * fwrs::kStatSlots;
-constexpr int kDefaultTileX = 64, kDefaultTileY = 4;
+constexpr size_t kStatBytes = 2 * sizeof(unsigned long long) * fwrs::kStatSlots;
+constexpr int kDefaultTileX = 64, kDefaultTileY = 1;
 
 size_t pitch_for(int width, int height)
 {
@@ -105,12 +105,17 @@ struct fwrs_ctx {
     bool owns_arena = false;
     size_t pitch = 0;
     float* wsum = nullptr;
-    uint32_t* cnt = nullptr;
     float* rec = nullptr;
     uint32_t* idx = nullptr;
     unsigned long long* stats = nullptr;
     uint32_t t = 0;
     uint64_t pixel_updates = 0;
+    // `resolved_out` holds this context's resolve as of frame `resolved_at`
+    // (valid only while `resolved` is set): the precondition of the
+    // incremental entry point.
+    const float* resolved_out = nullptr;
+    uint32_t resolved_at = 0;
+    bool resolved = false;
     int tile_x = kDefaultTileX, tile_y = kDefaultTileY;
 };
 
@@ -119,14 +124,15 @@ namespace {
 int clear_store(fwrs_ctx* x)
 {
     const size_t P = x->pitch, k = (size_t)x->k;
-    // wsum, cnt and the slot records are contiguous and start out zero; idx starts empty.
-    if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->wsum), P * (2 + 4 * k), 0u, x->stream) != hipSuccess)
+    // wsum and the slot records are contiguous and start out zero; idx starts empty.
+    if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->wsum), P * (1 + 4 * k), 0u, x->stream) != hipSuccess)
         return FWRS_E_HIP;
     if (fwrs::launch_fill_u32(x->idx, P * k, 0xFFFFFFFFu, x->stream) != hipSuccess) return FWRS_E_HIP;
     if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->stats), kStatBytes / 4, 0u, x->stream) != hipSuccess)
         return FWRS_E_HIP;
     x->t = 0;
     x->pixel_updates = 0;
+    x->resolved = false;
     return FWRS_OK;
 }
 
@@ -151,7 +157,6 @@ FrameDesc make_desc(const fwrs_ctx* x, const float* color, const uint8_t* level,
     d.level = level;
     d.out = out;
     d.wsum = x->wsum;
-    d.cnt = x->cnt;
     d.rec = x->rec;
     d.idx = x->idx;
     d.stats = x->stats;
@@ -182,6 +187,13 @@ int run_frame(fwrs_ctx* x, const float* color, const uint8_t* level, float gx, f
         x->t += 1u;
         x->pixel_updates += (uint64_t)x->width * (uint64_t)x->height;
     }
+    if (op == 2 || op == 3 || op == 5) {   // every op that leaves `out` holding the resolve
+        x->resolved_out = out;
+        x->resolved_at = x->t;
+        x->resolved = true;
+    } else {
+        x->resolved = false;
+    }
     return FWRS_OK;
 }
 
@@ -207,7 +219,7 @@ int fwrs_default_params(int width, fwrs_params* p)
 size_t fwrs_state_bytes(int width, int height, int k)
 {
     if (!sizes_ok(width, height, k)) return 0;
-    return 4 * pitch_for(width, height) * (2 + 5 * (size_t)k) + kStatBytes;
+    return 4 * pitch_for(width, height) * (1 + 5 * (size_t)k) + kStatBytes;
 }
 
 size_t fwrs_state_host_bytes(int width, int height, int k)
@@ -246,10 +258,9 @@ int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void
     const size_t P = x->pitch, kk = (size_t)k;
     float* base = static_cast<float*>(x->arena);
     x->wsum = base;
-    x->cnt = reinterpret_cast<uint32_t*>(base + P);
-    x->rec = base + 2 * P;
-    x->idx = reinterpret_cast<uint32_t*>(base + (2 + 4 * kk) * P);
-    x->stats = reinterpret_cast<unsigned long long*>(base + (2 + 5 * kk) * P);
+    x->rec = base + P;
+    x->idx = reinterpret_cast<uint32_t*>(base + (1 + 4 * kk) * P);
+    x->stats = reinterpret_cast<unsigned long long*>(base + (1 + 5 * kk) * P);
     const int rc = clear_store(x);
     if (rc != FWRS_OK) {
         if (x->owns_arena) (void)hipFree(x->arena);
@@ -316,6 +327,15 @@ int fwrs_push_frame_resolve(fwrs_ctx* x, const float* color, const uint8_t* leve
     return run_frame(x, color, level_map, gaze_x, gaze_y, out, 3);
 }
 
+int fwrs_push_frame_resolve_incremental(fwrs_ctx* x, const float* color, const uint8_t* level_map, float gaze_x,
+                                        float gaze_y, float* out)
+{
+    if (!x || !color || !level_map || !out || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
+    if (x->t == 0xFFFFFFFFu) return FWRS_E_STATE;
+    if (!x->resolved || x->resolved_out != out || x->resolved_at != x->t) return FWRS_E_STATE;
+    return run_frame(x, color, level_map, gaze_x, gaze_y, out, 5);
+}
+
 int fwrs_frame_index(const fwrs_ctx* x, uint32_t* frame_index)
 {
     if (!x || !frame_index) return FWRS_E_ARG;
@@ -332,7 +352,6 @@ int fwrs_get_state(const fwrs_ctx* x, fwrs_state_view* v)
     v->frame_index = x->t;
     v->pitch = x->pitch;
     v->wsum = x->wsum;
-    v->cnt = x->cnt;
     v->rec = x->rec;
     v->idx = x->idx;
     return FWRS_OK;
@@ -359,11 +378,12 @@ int fwrs_download_state(fwrs_ctx* x, void* host, size_t host_bytes)
     uint32_t* hidx = reinterpret_cast<uint32_t*>(h + (8 + 4 * k) * N);
     float* col = reinterpret_cast<float*>(h + (8 + 8 * k) * N);
     if (hipMemcpyAsync(wsum, x->wsum, 4 * N, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
-        hipMemcpyAsync(cnt, x->cnt, 4 * N, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
         hipMemcpyAsync(rec.data(), x->rec, 16 * N * k, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
         hipMemcpyAsync(idx.data(), x->idx, 4 * N * k, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
         hipStreamSynchronize(x->stream) != hipSuccess)
         return FWRS_E_HIP;
+    // every pixel has seen one candidate per frame: m = frame count
+    for (size_t p = 0; p < N; ++p) cnt[p] = x->t;
     // device records [N][k]{w, r, g, b} -> packed planes wt[k][N], idx[k][N], col[k][3][N]
     for (size_t p = 0; p < N; ++p)
         for (size_t j = 0; j < k; ++j) {
@@ -377,18 +397,22 @@ int fwrs_download_state(fwrs_ctx* x, void* host, size_t host_bytes)
     return FWRS_OK;
 }
 
-int fwrs_get_stats(fwrs_ctx* x, uint64_t* slot_takes, uint64_t* pixel_updates)
+int fwrs_get_stats(fwrs_ctx* x, uint64_t* slot_takes, uint64_t* pixels_changed, uint64_t* pixel_updates)
 {
     if (!x) return FWRS_E_ARG;
     DeviceGuard g(x->device);
     if (!g.ok) return FWRS_E_HIP;
-    std::vector<unsigned long long> h(fwrs::kStatSlots);
+    std::vector<unsigned long long> h(2 * fwrs::kStatSlots);
     if (hipMemcpyAsync(h.data(), x->stats, kStatBytes, hipMemcpyDeviceToHost, x->stream) != hipSuccess)
         return FWRS_E_HIP;
     if (hipStreamSynchronize(x->stream) != hipSuccess) return FWRS_E_HIP;
-    uint64_t s = 0;
-    for (unsigned long long v : h) s += v;
-    if (slot_takes) *slot_takes = s;
+    uint64_t takes = 0, changed = 0;
+    for (int i = 0; i < fwrs::kStatSlots; ++i) {
+        takes += h[2 * i];
+        changed += h[2 * i + 1];
+    }
+    if (slot_takes) *slot_takes = takes;
+    if (pixels_changed) *pixels_changed = changed;
     if (pixel_updates) *pixel_updates = x->pixel_updates;
     return FWRS_OK;
 }
@@ -611,8 +635,12 @@ int fwrs_engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n)
     if (hipEventRecord(e->done[b], e->stream) != hipSuccess) return FWRS_E_HIP;
     e->cur ^= 1;
     for (int i = 0; i < n; ++i) {
-        frames[i].ctx->t += 1u;
-        frames[i].ctx->pixel_updates += (uint64_t)frames[i].ctx->width * (uint64_t)frames[i].ctx->height;
+        fwrs_ctx* c = frames[i].ctx;
+        c->t += 1u;
+        c->pixel_updates += (uint64_t)c->width * (uint64_t)c->height;
+        c->resolved_out = frames[i].out;
+        c->resolved_at = c->t;
+        c->resolved = true;
     }
     return FWRS_OK;
 }

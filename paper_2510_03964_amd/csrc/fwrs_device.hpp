@@ -34,10 +34,9 @@ struct alignas(16) FrameDesc {
     const uint8_t* level;       // [H][W] u8 foveation level
     float* out;                 // [H][W][3] f32 resolve target (null for update-only)
     float* wsum;                // [N] w_sum per pixel
-    uint32_t* cnt;              // [N] candidates seen per pixel (m)
     float* rec;                 // [N][k][4] slot records {w, r, g, b}
     uint32_t* idx;              // [N][k] frame index of each slot's sample
-    unsigned long long* stats;  // [kStatSlots] slot-take counters, or null
+    unsigned long long* stats;  // [kStatSlots][2] counters (slots replaced, pixels changed), or null
     uint32_t width, height, t, k;
     float gx, gy;
     Consts c;

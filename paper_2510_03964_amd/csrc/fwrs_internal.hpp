@@ -11,7 +11,8 @@ namespace fwrs {
 
 constexpr int kMaxK = 16;
 
-// op: 1 = update only, 2 = resolve only, 3 = update + resolve.
+// op: 1 = update only, 2 = resolve only, 3 = update + resolve,
+// 5 = update + resolve of the changed pixels only.
 hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream);
 
 // Persistent batched kernel over a device table of frame descriptors.

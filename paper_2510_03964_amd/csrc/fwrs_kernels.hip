@@ -1,11 +1,13 @@
 // HIP kernels of the weighted-reservoir-sampling pass for gfx950.
 //
-// Store layout (per context, N pixels, k slots): w_sum[N] and m[N] as planes,
+// Store layout (per context, N pixels, k slots): a w_sum plane w_sum[N],
 // one record of k slots per pixel, rec[p * k + j] = {w, r, g, b} (16k bytes,
 // so at k = 4 a pixel's record is exactly one 64-byte sector), and the slots'
 // frame indices idx[p * k + j].  A slot replacement therefore dirties only the
 // sector of the pixel that replaced it, not one sector in each of k * 4
-// planes; reads of whole records stay contiguous across a wave.
+// planes; reads of whole records stay contiguous across a wave.  Alg. 2's
+// candidate count m is the same for every pixel (each pixel receives exactly
+// one candidate per frame), so it is the context's frame count, not a plane.
 //
 // One thread per pixel; a block of 256 threads covers one work item laid out
 // as 1, 2 or 4 tiles of tile_x pixels by tile_y rows (the tile shape changes
@@ -18,15 +20,60 @@
 //   w    = Eq. 4 weight from the eccentricity to the gaze (level 0 -> 1)
 //   W1'  = Eq. 6 biased w_sum (BERNOULLI) or w_sum (NONE)
 //   slot j takes (colour, w, t) when u_j * (W1' + w) > W1'   (Alg. 2)
-//   w_sum <- W1' + w;  m <- m + 1
+//   w_sum <- W1' + w
 //   out  = sum_j wt_j col_j / sum_j wt_j                      (resolve)
-// The new colour is read only by pixels in which some slot takes it.
+// The new colour is read only by pixels in which some slot takes it; the
+// output is written with non-temporal stores (it is not read again here).
 #include "fwrs_device.hpp"
 #include "fwrs_internal.hpp"
 
+// Which streams use non-temporal loads / stores (bits, see kNt* below); a
+// launch-shape tuning constant that never changes results.
+#ifndef FWRS_NT_MASK
+#define FWRS_NT_MASK 0xC7u
+#endif
+
 namespace fwrs {
 
-enum Op : int { kPush = 1, kResolve = 2, kFused = 3 };
+// kPush: update only; kResolve: resolve only; kFused: update + resolve of every
+// pixel; kIncremental: update + resolve of the pixels whose record changed
+// (the output already holds the previous frame's resolve everywhere else).
+enum Op : int { kPush = 1, kResolve = 2, kFused = 3, kIncremental = 5 };
+
+enum : uint32_t {
+    kNtLevel = 1u, kNtWsumLd = 2u, kNtWsumSt = 4u, kNtRecLd = 8u, kNtRecSt = 16u, kNtIdxSt = 32u,
+    kNtColor = 64u, kNtOut = 128u,
+};
+constexpr uint32_t kNt = FWRS_NT_MASK;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <uint32_t BIT, typename T>
+__device__ __forceinline__ T ld(const T* p)
+{
+    if constexpr ((kNt & BIT) != 0u) return __builtin_nontemporal_load(p);
+    return *p;
+}
+
+template <uint32_t BIT, typename T>
+__device__ __forceinline__ void st(T* p, T v)
+{
+    if constexpr ((kNt & BIT) != 0u) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <uint32_t BIT>
+__device__ __forceinline__ float4 ld4(const float4* p)
+{
+    const v4f v = ld<BIT>(reinterpret_cast<const v4f*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+template <uint32_t BIT>
+__device__ __forceinline__ void st4(float4* p, const float4& v)
+{
+    st<BIT>(reinterpret_cast<v4f*>(p), v4f{v.x, v.y, v.z, v.w});
+}
 
 // ---------------------------------------------------------------------------
 // Decisions of one pixel: bit j set when slot j takes the new candidate.
@@ -54,68 +101,74 @@ __device__ __forceinline__ uint32_t decide(const FrameDesc& d, uint32_t p, float
     return mask;
 }
 
-struct Rgb {
-    float r, g, b;
-};
-
 // ---------------------------------------------------------------------------
 // One pixel.  K > 0 keeps the pixel's whole record in registers; K == 0
 // (any slot count up to kMaxK) streams the record one slot at a time.
+// Returns the number of slots replaced plus 2^16 if there was any.
 // ---------------------------------------------------------------------------
 template <int K, int OP>
 __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32_t y)
 {
     const uint32_t p = y * d.width + x;
     const int kk = K ? K : (int)d.k;
+    constexpr bool kUpdates = OP == kPush || OP == kFused || OP == kIncremental;
+    constexpr bool kResolves = OP == kResolve || OP == kFused || OP == kIncremental;
     float4* rec = reinterpret_cast<float4*>(d.rec) + (size_t)p * (size_t)kk;
     uint32_t* idx = d.idx + (size_t)p * (size_t)kk;
-    const Rgb* color = reinterpret_cast<const Rgb*>(d.color) + p;
+    const float* color = d.color + 3 * (size_t)p;
 
     // 1. loads: per-pixel state, then the record (compile-time K), all in flight together
-    uint32_t lv = 0u, m = 0u;
+    uint32_t lv = 0u;
     float W1 = 0.f;
-    if (OP & kPush) {
-        lv = d.level[p];
-        W1 = d.wsum[p];
-        m = d.cnt[p];
+    if (kUpdates) {
+        lv = ld<kNtLevel>(d.level + p);
+        W1 = ld<kNtWsumLd>(d.wsum + p);
     }
     float4 r[K ? K : 1];
-    if (K && (OP & kResolve)) {
+    if (K && (OP == kFused || OP == kResolve)) {
 #pragma unroll
-        for (int j = 0; j < (K ? K : 1); ++j) r[j] = rec[j];
+        for (int j = 0; j < (K ? K : 1); ++j) r[j] = ld4<kNtRecLd>(rec + j);
     }
 
     // 2. weight, bias and decisions
     uint32_t tk = 0u;
     float w = 0.f;
-    if (OP & kPush) {
+    if (kUpdates) {
         const float dx = ((float)x + 0.5f) - d.gx;
         const float dy = ((float)y + 0.5f) - d.gy;
         w = weight_eq4(d.c, dx * dx + dy * dy, lv);
         const float W1b = bias_eq6(W1, w, d.bias);
         const float s = W1b + w;
         tk = decide<K>(d, p, W1b, s);
-        d.wsum[p] = s;
-        d.cnt[p] = m + 1u;
+        st<kNtWsumSt>(d.wsum + p, s);
     }
 
     // 3. the new colour where some slot takes it, then the replaced slots
-    Rgb c{0.f, 0.f, 0.f};
-    if (tk) c = *color;
-    const float4 fresh = make_float4(w, c.r, c.g, c.b);
+    float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    if (tk) {
+        c0 = ld<kNtColor>(color + 0);
+        c1 = ld<kNtColor>(color + 1);
+        c2 = ld<kNtColor>(color + 2);
+    }
+    const float4 fresh = make_float4(w, c0, c1, c2);
+    if (K && OP == kIncremental && tk) {
+        // only now is the record needed: the output changes with it
+#pragma unroll
+        for (int j = 0; j < (K ? K : 1); ++j) r[j] = ld4<kNtRecLd>(rec + j);
+    }
     if (K) {
 #pragma unroll
         for (int j = 0; j < (K ? K : 1); ++j) {
             if ((tk >> j) & 1u) {
                 r[j] = fresh;
-                rec[j] = fresh;
-                idx[j] = d.t;
+                st4<kNtRecSt>(rec + j, fresh);
+                st<kNtIdxSt>(idx + j, d.t);
             }
         }
     }
 
     // 4. resolve: sum_j w_j col_j / sum_j w_j, slot order
-    if (OP & kResolve) {
+    if (kResolves && (OP != kIncremental || tk)) {
         float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
         if (K) {
 #pragma unroll
@@ -130,10 +183,10 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
                 float4 v;
                 if ((tk >> j) & 1u) {
                     v = fresh;
-                    rec[j] = fresh;
-                    idx[j] = d.t;
+                    st4<kNtRecSt>(rec + j, fresh);
+                    st<kNtIdxSt>(idx + j, d.t);
                 } else {
-                    v = rec[j];
+                    v = ld4<kNtRecLd>(rec + j);
                 }
                 S = S + v.x;
                 a0 = a0 + v.x * v.y;
@@ -143,19 +196,18 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
         }
         // S == 0 only before the first frame (every kept weight is > 0): output 0.
         const float rs = S > 0.0f ? 1.0f / S : 0.0f;
-        Rgb o;
-        o.r = a0 * rs;
-        o.g = a1 * rs;
-        o.b = a2 * rs;
-        reinterpret_cast<Rgb*>(d.out)[p] = o;
+        float* o = d.out + 3 * (size_t)p;
+        st<kNtOut>(o + 0, a0 * rs);
+        st<kNtOut>(o + 1, a1 * rs);
+        st<kNtOut>(o + 2, a2 * rs);
     } else if (!K) {
         for (int j = 0; j < kk; ++j)
             if ((tk >> j) & 1u) {
-                rec[j] = fresh;
-                idx[j] = d.t;
+                st4<kNtRecSt>(rec + j, fresh);
+                st<kNtIdxSt>(idx + j, d.t);
             }
     }
-    return __popc(tk);
+    return __popc(tk) + (tk ? 0x10000u : 0u);
 }
 
 // ---------------------------------------------------------------------------
@@ -183,12 +235,14 @@ __device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t it
 
 __device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t v)
 {
-    // Wave sum, then one 64-bit atomic per wave on a counter chosen by the wave's id.
+    // v = replaced slots + 2^16 * (pixel changed).  Wave sum (at most 1024 slots and 64
+    // pixels), then one 64-bit atomic per counter and wave on a pair chosen by the wave's id.
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if ((threadIdx.x & 63u) == 0u && v) {
         const uint32_t slot = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) & (kStatSlots - 1);
-        atomicAdd(stats + slot, (unsigned long long)v);
+        atomicAdd(stats + 2 * slot, (unsigned long long)(v & 0xFFFFu));
+        atomicAdd(stats + 2 * slot + 1, (unsigned long long)(v >> 16));
     }
 }
 
@@ -196,7 +250,7 @@ template <int K, int OP>
 __global__ __launch_bounds__(kBlock) void frame_kernel(FrameDesc d)
 {
     const uint32_t n = process_item<K, OP>(d, blockIdx.x);
-    if ((OP & kPush) && d.stats) add_stats(d.stats, n);
+    if ((OP == kPush || OP == kFused || OP == kIncremental) && d.stats) add_stats(d.stats, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -257,6 +311,7 @@ hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream)
     switch (op) {
         case kPush: return launch_frame_op<kPush>(d, stream);
         case kResolve: return launch_frame_op<kResolve>(d, stream);
+        case kIncremental: return launch_frame_op<kIncremental>(d, stream);
         default: return launch_frame_op<kFused>(d, stream);
     }
 }

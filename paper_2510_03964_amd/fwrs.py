@@ -24,7 +24,7 @@ MAX_K = 16
 EXPORTS = (
     "fwrs_default_params", "fwrs_state_bytes", "fwrs_state_host_bytes", "fwrs_create", "fwrs_create_ex",
     "fwrs_destroy", "fwrs_set_stream", "fwrs_reset", "fwrs_push_frame", "fwrs_resolve",
-    "fwrs_push_frame_resolve", "fwrs_frame_index", "fwrs_get_state", "fwrs_download_state", "fwrs_get_stats",
+    "fwrs_push_frame_resolve", "fwrs_push_frame_resolve_incremental", "fwrs_frame_index", "fwrs_get_state", "fwrs_download_state", "fwrs_get_stats",
     "fwrs_set_tile", "fwrs_sync", "fwrs_strerror", "fwrs_engine_create", "fwrs_engine_tick",
     "fwrs_engine_set_tile", "fwrs_engine_destroy",
 )
@@ -62,7 +62,6 @@ class StateView(C.Structure):
         ("frame_index", C.c_uint32),
         ("pitch", C.c_size_t),
         ("wsum", C.c_void_p),
-        ("cnt", C.c_void_p),
         ("rec", C.c_void_p),
         ("idx", C.c_void_p),
     ]
@@ -106,10 +105,11 @@ def load(path: str | None = None):
         "fwrs_push_frame": (i, [vp, vp, vp, f, f]),
         "fwrs_resolve": (i, [vp, vp]),
         "fwrs_push_frame_resolve": (i, [vp, vp, vp, f, f, vp]),
+        "fwrs_push_frame_resolve_incremental": (i, [vp, vp, vp, f, f, vp]),
         "fwrs_frame_index": (i, [vp, C.POINTER(u32)]),
         "fwrs_get_state": (i, [vp, C.POINTER(StateView)]),
         "fwrs_download_state": (i, [vp, vp, sz]),
-        "fwrs_get_stats": (i, [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+        "fwrs_get_stats": (i, [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
         "fwrs_set_tile": (i, [vp, i, i]),
         "fwrs_sync": (i, [vp]),
         "fwrs_strerror": (C.c_char_p, [i]),
@@ -258,6 +258,15 @@ class Reservoir:
         _check(self._L.fwrs_push_frame_resolve(self._h, _ptr(color), _ptr(level), float(gaze_x), float(gaze_y),
                                                _ptr(out)), "fwrs_push_frame_resolve")
 
+    def step_incremental(self, color, level, gaze_x: float, gaze_y: float, out) -> None:
+        """fwrs_push_frame_resolve_incremental: like step(), writing only the pixels whose
+        reservoir changed; `out` must hold this context's previous resolve."""
+        self._check_frame(color, level)
+        self._check_out(out)
+        _check(self._L.fwrs_push_frame_resolve_incremental(self._h, _ptr(color), _ptr(level), float(gaze_x),
+                                                           float(gaze_y), _ptr(out)),
+               "fwrs_push_frame_resolve_incremental")
+
     @property
     def frame_index(self) -> int:
         t = C.c_uint32()
@@ -285,11 +294,11 @@ class Reservoir:
         return HostState(take(np.float32, N, (H, W)), take(np.uint32, N, (H, W)), take(np.float32, k * N, (k, H, W)),
                          take(np.uint32, k * N, (k, H, W)), take(np.float32, 3 * k * N, (k, 3, H, W)))
 
-    def stats(self) -> tuple[int, int]:
-        """(slot takes, pixel updates) since creation or reset."""
-        a, b = C.c_uint64(), C.c_uint64()
-        _check(self._L.fwrs_get_stats(self._h, C.byref(a), C.byref(b)), "fwrs_get_stats")
-        return int(a.value), int(b.value)
+    def stats(self) -> tuple[int, int, int]:
+        """(slot takes, pixel updates with a take, pixel updates) since creation or reset."""
+        a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(self._L.fwrs_get_stats(self._h, C.byref(a), C.byref(b), C.byref(c)), "fwrs_get_stats")
+        return int(a.value), int(b.value), int(c.value)
 
     def sync(self) -> None:
         _check(self._L.fwrs_sync(self._h), "fwrs_sync")

@@ -67,9 +67,9 @@ def test_default_params_and_sizes():
     assert p.bias_mode == fwrs.BIAS_BERNOULLI
     assert (p.a_k, p.r2k, p.rek) == (pytest.approx(0.9851), pytest.approx(1.058), pytest.approx(22.14))
     N = 3840 * 2160
-    assert fwrs.state_bytes(3840, 2160, 4) == 4 * N * (2 + 20) + 8192      # N is a multiple of 64
+    assert fwrs.state_bytes(3840, 2160, 4) == 4 * N * (1 + 20) + 16384      # N is a multiple of 64
     assert fwrs.state_host_bytes(3840, 2160, 4) == N * (8 + 80)
-    assert fwrs.state_bytes(13, 7, 3) == 4 * 128 * (2 + 15) + 8192        # pitch rounded up to 64
+    assert fwrs.state_bytes(13, 7, 3) == 4 * 128 * (1 + 15) + 16384        # pitch rounded up to 64
     for bad in [(0, 5, 4), (5, 0, 4), (5, 5, 0), (5, 5, 17), (65536, 65536, 1)]:
         assert fwrs.state_bytes(*bad) == 0
 

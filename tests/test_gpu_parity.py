@@ -49,6 +49,8 @@ def _compare_out(out, ref, where=""):
 
 
 def _run_pair(dev, spec, n_frames, mode="fused", tile=None, bias=fwrs.BIAS_BERNOULLI, every=1, src=None):
+    """mode: "fused" (push + resolve in one call), "split" (push, then resolve) or
+    "incremental" (first frame fused, then only the changed pixels are rewritten)."""
     p, q = _params(spec, bias)
     src = src or synth.FrameSource(spec, device=dev, n_frames=n_frames)
     res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream())
@@ -58,8 +60,10 @@ def _run_pair(dev, spec, n_frames, mode="fused", tile=None, bias=fwrs.BIAS_BERNO
     out = torch.full((spec.height, spec.width, 3), -1.0, dtype=torch.float32, device=dev)
     for t in range(n_frames):
         c, lev, gx, gy = src.frame(t)
-        if mode == "fused":
+        if mode == "fused" or (mode == "incremental" and t == 0):
             res.step(c, lev, gx, gy, out)
+        elif mode == "incremental":
+            res.step_incremental(c, lev, gx, gy, out)
         else:
             res.push(c, lev, gx, gy)
             res.resolve(out)
@@ -76,9 +80,9 @@ def test_small_workload_every_frame(dev):
     """256x256, k = 4, 60 frames of the synthetic gaze trace, fused update + resolve."""
     spec = synth.spec_small()
     res, orc, _ = _run_pair(dev, spec, spec.frames)
-    takes, updates = res.stats()
+    takes, changed, updates = res.stats()
     assert updates == spec.frames * spec.pixels
-    assert takes > 0
+    assert 0 < changed <= takes
 
 
 def test_push_then_resolve_is_bit_identical_to_fused(dev):
@@ -86,6 +90,39 @@ def test_push_then_resolve_is_bit_identical_to_fused(dev):
     _, _, out_a = _run_pair(dev, spec, 12, mode="fused", every=12)
     _, _, out_b = _run_pair(dev, spec, 12, mode="split", every=12)
     assert torch.equal(out_a, out_b)
+
+
+@pytest.mark.parametrize("k", [4, 1, 3, 8])
+def test_incremental_resolve_matches_oracle_and_full_resolve(dev, k):
+    """Writing only the changed pixels leaves out bit-identical to the full resolve."""
+    spec = synth.StreamSpec(256, 256, k, 30, 32.0, 80.0, 2.0, 10, 6.0)
+    _, _, out_inc = _run_pair(dev, spec, 30, mode="incremental", every=3)
+    _, _, out_full = _run_pair(dev, spec, 30, mode="fused", every=30)
+    assert torch.equal(out_inc, out_full)
+
+
+def test_incremental_resolve_checks_its_precondition(dev):
+    spec = synth.StreamSpec(64, 32, 4, 4, 8.0, 20.0, 2.0, 2, 5.0)
+    src = synth.FrameSource(spec, device=dev)
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, stream=torch.cuda.current_stream())
+    out = torch.empty((spec.height, spec.width, 3), device=dev)
+    other = torch.empty_like(out)
+    with pytest.raises(fwrs.FwrsError) as e:          # nothing resolved yet
+        res.step_incremental(*src.frame(0), out)
+    assert e.value.status == fwrs.E_STATE
+    res.step(*src.frame(0), out)
+    with pytest.raises(fwrs.FwrsError):               # a different buffer
+        res.step_incremental(*src.frame(1), other)
+    res.step_incremental(*src.frame(1), out)
+    res.push(*src.frame(2))
+    with pytest.raises(fwrs.FwrsError):               # an update without resolve since
+        res.step_incremental(*src.frame(3), out)
+    res.resolve(out)
+    res.step_incremental(*src.frame(3), out)
+    res.reset()
+    with pytest.raises(fwrs.FwrsError):
+        res.step_incremental(*src.frame(0), out)
+    assert res.frame_index == 0
 
 
 @pytest.mark.parametrize("w,h,k,frames", [
@@ -160,7 +197,7 @@ def test_reset_and_caller_arena(dev):
     res.sync()
     _compare_state(res.download(), orc.state())
     _compare_out(out.cpu().numpy(), orc.resolve())
-    assert res.stats()[1] == 4 * spec.pixels
+    assert res.stats()[2] == 4 * spec.pixels
 
 
 def test_stats_count_every_slot_replacement(dev):
@@ -170,14 +207,17 @@ def test_stats_count_every_slot_replacement(dev):
     res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream())
     orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
     out = torch.empty((spec.height, spec.width, 3), device=dev)
-    expected = 0
+    expected = changed_px = 0
     for t in range(spec.frames):
         c, lev, gx, gy = src.frame(t)
         res.step(c, lev, gx, gy, out)
         orc.push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
-        expected += int(np.count_nonzero(orc.state().idx == t))
-    takes, updates = res.stats()
+        now = orc.state().idx == t
+        expected += int(np.count_nonzero(now))
+        changed_px += int(np.count_nonzero(now.any(axis=0)))
+    takes, changed, updates = res.stats()
     assert takes == expected
+    assert changed == changed_px
     assert updates == spec.frames * spec.pixels
 
 
@@ -217,7 +257,7 @@ def test_4k_bands_and_whole_frame_properties(dev):
             assert np.all(st.idx <= t)
             assert np.all(st.wt > 0) and np.all(st.wt <= 1)
             assert np.isfinite(o).all() and o.min() >= 0.0 and o.max() <= 1.0
-    takes, updates = res.stats()
+    takes, changed, updates = res.stats()
     assert updates == n_frames * spec.pixels and takes > 0
 
 
@@ -263,6 +303,11 @@ def test_engine_tick_matches_oracle_and_plain_launches(dev, use_graph):
         _compare_out(outs_b[i].cpu().numpy(), orcs[i].resolve(), f"stream {i}")
         assert torch.equal(outs_b[i], outs_p[i])
         assert batched[i].stats() == plain[i].stats()
+        # the batched tick leaves `out` as this context's resolve: incremental may follow
+        c, lev, gx, gy = srcs[i].frame(4)
+        batched[i].step_incremental(c, lev, gx, gy, outs_b[i])
+        plain[i].step(c, lev, gx, gy, outs_p[i])
+        assert torch.equal(outs_b[i], outs_p[i])
     eng.close()
 
 
