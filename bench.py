@@ -158,7 +158,12 @@ def main() -> int:
     log(f"generating {K + W} frames of {spec.width}x{spec.height} on {torch.cuda.get_device_name(0)}")
     src = synth.FrameSource(spec, device=dev, n_frames=max(K, W))
     t0 = time.perf_counter()
-    frames = [src.frame(t) for t in range(K)]
+    frames = []
+    for t in range(K):
+        frames.append(src.frame(t))
+        if (t + 1) % 100 == 0:
+            torch.cuda.synchronize()
+            log(f"  {t + 1} frames")
     torch.cuda.synchronize()
     log(f"frames resident in HBM ({time.perf_counter() - t0:.1f} s)")
 

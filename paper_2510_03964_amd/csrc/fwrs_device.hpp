@@ -66,10 +66,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t x0, uint32_t x1, uint32_
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi_a = __umulhi(kPhiloxMulA, x0);
-        const uint32_t lo_a = kPhiloxMulA * x0;
-        const uint32_t hi_b = __umulhi(kPhiloxMulB, x2);
-        const uint32_t lo_b = kPhiloxMulB * x2;
+        // one 32x32 -> 64-bit multiply per product (v_mad_u64_u32) gives both halves
+        const uint64_t pa = (uint64_t)kPhiloxMulA * (uint64_t)x0;
+        const uint64_t pb = (uint64_t)kPhiloxMulB * (uint64_t)x2;
+        const uint32_t hi_a = (uint32_t)(pa >> 32), lo_a = (uint32_t)pa;
+        const uint32_t hi_b = (uint32_t)(pb >> 32), lo_b = (uint32_t)pb;
         x0 = hi_b ^ x1 ^ k0;
         x1 = lo_b;
         x2 = hi_a ^ x3 ^ k1;
@@ -120,15 +121,28 @@ __host__ __device__ __forceinline__ void density_terms(const Consts& c, float e,
     den = T * t1;
 }
 
-// Eq. 4 for a pixel whose centre lies `dist2` squared pixels from the gaze;
-// level 0 (full fidelity this frame) and e <= r_f score 1.
-__device__ __forceinline__ float weight_eq4(const Consts& c, float dist2, uint32_t level)
+// Eq. 4 for a pixel whose centre lies `dist2` squared pixels from the gaze,
+// in two parts so that the arithmetic can run before the level is loaded:
+// outside(...) is d(e) / d(r_f) (clamped to 1) and sets the eccentricity e;
+// select_eq4(...) scores level 0 (full fidelity this frame) and e <= r_f as 1.
+__device__ __forceinline__ float weight_outside(const Consts& c, float dist2, float& e)
 {
-    const float e = sqrtf(dist2) * c.iPPD;
+    e = sqrtf(dist2) * c.iPPD;
     float num, den;
     density_terms(c, e, num, den);
-    const float w = fminf(1.0f, num / (den * c.Drf));
-    return (level == 0u || e <= c.rf) ? 1.0f : w;
+    return fminf(1.0f, num / (den * c.Drf));
+}
+
+__device__ __forceinline__ float select_eq4(const Consts& c, float outside, float e, uint32_t level)
+{
+    return (level == 0u || e <= c.rf) ? 1.0f : outside;
+}
+
+__device__ __forceinline__ float weight_eq4(const Consts& c, float dist2, uint32_t level)
+{
+    float e;
+    const float o = weight_outside(c, dist2, e);
+    return select_eq4(c, o, e, level);
 }
 
 // Eq. 5-6: R1.w_sum scaled by the survival probability 1 - w / (R1.w_sum + w).

@@ -76,26 +76,54 @@ __device__ __forceinline__ void st4(float4* p, const float4& v)
 }
 
 // ---------------------------------------------------------------------------
-// Decisions of one pixel: bit j set when slot j takes the new candidate.
-// K > 0: compile-time slot count; K == 0: d.k at run time.
+// Variates and decisions of one pixel.  The Philox words depend only on the
+// pixel index and the frame, so they are computed while the pixel's loads are
+// in flight; the decision (bit j set when slot j takes the new candidate)
+// needs the loaded w_sum.  K > 0: compile-time slot count; K == 0: d.k.
 // ---------------------------------------------------------------------------
 template <int K>
-__device__ __forceinline__ uint32_t decide(const FrameDesc& d, uint32_t p, float W1b, float s)
+struct Words {
+    uint32_t w[K ? 4 * ((K + 3) / 4) : 4];
+};
+
+template <int K>
+__device__ __forceinline__ Words<K> philox_words(const FrameDesc& d, uint32_t p)
 {
-    const int kk = K ? K : (int)d.k;
+    static_assert(K > 0, "compile-time slot count");
+    Words<K> out;
+#pragma unroll
+    for (int b = 0; b < (K + 3) / 4; ++b) {
+        const uint4 r = philox4x32_10(p, d.t, (uint32_t)b, 0u, d.seed, d.stream_id);
+        out.w[4 * b + 0] = r.x;
+        out.w[4 * b + 1] = r.y;
+        out.w[4 * b + 2] = r.z;
+        out.w[4 * b + 3] = r.w;
+    }
+    return out;
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t decide_words(const Words<K>& words, float W1b, float s)
+{
     uint32_t mask = 0u;
 #pragma unroll
-    for (int b = 0; b < (K ? (K + 3) / 4 : kMaxK / 4); ++b) {
-        if (!K && 4 * b >= kk) break;
+    for (int j = 0; j < K; ++j)
+        if (unit_variate(words.w[j]) * s > W1b) mask |= 1u << j;
+    return mask;
+}
+
+// Run-time slot count: blocks drawn as needed.
+__device__ __forceinline__ uint32_t decide_any(const FrameDesc& d, uint32_t p, float W1b, float s)
+{
+    const int kk = (int)d.k;
+    uint32_t mask = 0u;
+    for (int b = 0; 4 * b < kk; ++b) {
         const uint4 r = philox4x32_10(p, d.t, (uint32_t)b, 0u, d.seed, d.stream_id);
         const uint32_t words[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int j = 4 * b + q;
-            if (j < kk) {
-                const float u = unit_variate(words[q]);
-                if (u * s > W1b) mask |= 1u << j;
-            }
+            if (j < kk && unit_variate(words[q]) * s > W1b) mask |= 1u << j;
         }
     }
     return mask;
@@ -117,7 +145,9 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
     uint32_t* idx = d.idx + (size_t)p * (size_t)kk;
     const float* color = d.color + 3 * (size_t)p;
 
-    // 1. loads: per-pixel state, then the record (compile-time K), all in flight together
+    // 1. every load that does not depend on this frame's decisions (the compiler's
+    //    own schedule interleaves them with step 2; forcing all of them ahead of
+    //    the arithmetic measured slower)
     uint32_t lv = 0u;
     float W1 = 0.f;
     if (kUpdates) {
@@ -130,16 +160,24 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
         for (int j = 0; j < (K ? K : 1); ++j) r[j] = ld4<kNtRecLd>(rec + j);
     }
 
-    // 2. weight, bias and decisions
+    // 2. arithmetic that needs no loaded value: the Philox words and the weight's geometry
+    Words<K ? K : 1> words;
+    float outside = 0.f, e = 0.f;
+    if (kUpdates) {
+        if (K) words = philox_words<K ? K : 1>(d, p);
+        const float dx = ((float)x + 0.5f) - d.gx;
+        const float dy = ((float)y + 0.5f) - d.gy;
+        outside = weight_outside(d.c, dx * dx + dy * dy, e);
+    }
+
+    // 3. weight (Eq. 4), bias (Eq. 6) and the Alg. 2 decision per slot
     uint32_t tk = 0u;
     float w = 0.f;
     if (kUpdates) {
-        const float dx = ((float)x + 0.5f) - d.gx;
-        const float dy = ((float)y + 0.5f) - d.gy;
-        w = weight_eq4(d.c, dx * dx + dy * dy, lv);
+        w = select_eq4(d.c, outside, e, lv);
         const float W1b = bias_eq6(W1, w, d.bias);
         const float s = W1b + w;
-        tk = decide<K>(d, p, W1b, s);
+        tk = K ? decide_words<K ? K : 1>(words, W1b, s) : decide_any(d, p, W1b, s);
         st<kNtWsumSt>(d.wsum + p, s);
     }
 
