@@ -93,6 +93,119 @@ def timed_run(res, frames, out, stream, step):
     return t_start.elapsed_time(t_end), np.array([a.elapsed_time(b) for (a, b) in ev])
 
 
+def multistream(dev, stream, specs, gazes, ticks: int, ring: int, use_graph: bool, label: str) -> dict:
+    """Batched ticks (one persistent launch per tick, tiles from the autotuner per resolution
+    class) against plain per-frame launches of the same kernels on the same stream, on the same
+    frames.  Frame t of a stream is frame t mod `ring` of its trace (a ring of distinct frames
+    kept resident in HBM).  The first 3 ticks of each mode are untimed."""
+    import numpy as np
+    import torch
+
+    from paper_2510_03964_amd import autotune, fwrs, synth
+
+    srcs = [synth.FrameSource(s, device=dev, gaze=g) for s, g in zip(specs, gazes)]
+    frames = [[src.frame(t % len(src)) for t in range(ring)] for src in srcs]
+    torch.cuda.synchronize()
+    eng = fwrs.Engine(len(specs), stream=stream, use_graph=use_graph)
+    eng_direct = fwrs.Engine(len(specs), stream=stream, use_graph=False)
+    classes = {}
+    for s in specs:   # one representative k per resolution class: the most frequent
+        classes.setdefault((s.width, s.height), []).append(s.k)
+    reps = [(w, h, max(set(ks), key=ks.count)) for (w, h), ks in classes.items()]
+    tuned = autotune.tune_engine(eng, reps, device=dev)
+    tiles = {(w, h): r["tile"] for (w, h, _), r in tuned.items()}
+    for (w, h), t in tiles.items():
+        eng_direct.set_tile(w * h, *t)
+    log(f"{label}: tiles {tiles}")
+
+    def make():
+        out = []
+        for s in specs:
+            p = fwrs.default_params(s.width, fovea_radius_px=s.fovea_radius_px, seed=synth.PHILOX_SEED,
+                                    stream_id=s.stream_id)
+            r = fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream)
+            r.set_tile(*tiles[(s.width, s.height)])
+            out.append((r, torch.empty((s.height, s.width, 3), dtype=torch.float32, device=dev)))
+        return out
+
+    px_tick = sum(s.pixels for s in specs)
+    result = {"streams": len(specs), "ticks": ticks, "ring": ring, "pixels_per_tick": px_tick,
+              "tiles": {f"{w}x{h}": list(t) for (w, h), t in tiles.items()}}
+    outs = {}
+    for mode in ("batched", "batched_direct", "plain"):
+        ctx = make()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(ticks)]
+        torch.cuda.synchronize()
+        for t in range(ticks):
+            fr = [frames[i][t % ring] for i in range(len(specs))]
+            ev[t][0].record(stream)
+            if mode != "plain":
+                (eng if mode == "batched" else eng_direct).tick([(ctx[i][0], *fr[i], ctx[i][1])
+                                                                 for i in range(len(specs))])
+            else:
+                for i in range(len(specs)):
+                    ctx[i][0].step(*fr[i], ctx[i][1])
+            ev[t][1].record(stream)
+        torch.cuda.synchronize()
+        lat = np.array([a.elapsed_time(b) for (a, b) in ev[3:]])
+        total = float(lat.sum())
+        result[mode] = {"ms_per_tick_mean": float(lat.mean()), "ms_per_tick_p50": float(np.percentile(lat, 50)),
+                        "ms_per_tick_p99": float(np.percentile(lat, 99)),
+                        "gpix_per_s": px_tick * len(lat) / (total / 1e3) / 1e9}
+        outs[mode] = [c[1] for c in ctx]
+        for r, _ in ctx:
+            r.close()
+    result["identical_outputs"] = all(torch.equal(a, b) and torch.equal(a, c) for a, b, c in
+                                      zip(outs["batched"], outs["plain"], outs["batched_direct"]))
+    result["batched_over_plain_throughput"] = result["batched"]["gpix_per_s"] / result["plain"]["gpix_per_s"]
+    result["batched"]["launch"] = "HIP graph replay" if use_graph else "direct launch"
+    result["batched_direct"]["launch"] = "direct launch"
+    eng.close()
+    eng_direct.close()
+    log(f"{label}: batched {result['batched']['ms_per_tick_p50']:.3f} ms p50 / {result['batched']['ms_per_tick_p99']:.3f} "
+        f"p99, plain {result['plain']['ms_per_tick_p50']:.3f} / {result['plain']['ms_per_tick_p99']:.3f}")
+    return result
+
+
+def serving(dev, stream, time_scale: float, fps_scale: float, ring: int, label: str) -> dict:
+    """32 sessions arriving as a Poisson process (mean 1/s; lifetime U[10, 60] s; 1920x1080 or
+    3840x2160; k in {4, 8}; 72, 90 or 120 Hz), arrivals and lifetimes compressed by `time_scale`
+    (same concurrency and offered load, shorter run), frame rates multiplied by `fps_scale`.
+    Reservoir budget 64 GB.  The same session mix runs through the batched executor (one graph
+    replay per tick) and the plain one (one launch per frame)."""
+    import torch
+
+    from paper_2510_03964_amd import autotune, serve, synth
+
+    base = serve.poisson_sessions(n=32, rate_per_s=1.0, seed=4242, time_scale=time_scale)
+    sessions = [serve.SessionSpec(s.sid, s.arrival_s, s.lifetime_s, s.width, s.height, s.k, s.fps * fps_scale)
+                for s in base]
+    rings, tiles = {}, {}
+    for (w, h) in sorted({(s.width, s.height) for s in sessions}):
+        spec = synth.StreamSpec(w, h, 4, ring, 0.05 * w, 0.125 * w, 8.0 * w / 3840, 90, 24.0 * w / 3840,
+                                stream_id=w)
+        src = synth.FrameSource(spec, device=dev)
+        rings[(w, h)] = [src.frame(t) for t in range(ring)]
+        tiles[(w, h)] = autotune.tune(w, h, 4, device=dev)["tile"]
+    torch.cuda.synchronize()
+    offered = sum(s.pixels * s.fps * s.lifetime_s for s in sessions) / (
+        max(s.arrival_s + s.lifetime_s for s in sessions) - min(s.arrival_s for s in sessions)) / 1e9
+    out = {"sessions": len(sessions), "time_scale": time_scale, "fps_scale": fps_scale,
+           "offered_gpix_per_s_avg": offered, "budget_gb": 64}
+    for mode in ("batched", "plain"):
+        ex = (serve.BatchedExecutor(rings, max_frames=64, stream=stream, tiles=tiles) if mode == "batched"
+              else serve.PlainExecutor(rings, stream=stream, tiles=tiles))
+        st = serve.Scheduler(ex, budget_bytes=64 * 10**9, max_active=32).run(sessions)
+        out[mode] = st.summary()
+        log(f"{label} {mode}: {out[mode]['frames']} frames, {out[mode]['gpix_per_s']:.2f} Gpix/s, "
+            f"p50 {out[mode]['latency_ms_p50']:.3f} ms, p99 {out[mode]['latency_ms_p99']:.3f} ms, "
+            f"{out[mode]['frames_per_tick']:.2f} frames/tick")
+        del ex
+        torch.cuda.synchronize()
+    out["batched_over_plain_throughput"] = out["batched"]["gpix_per_s"] / out["plain"]["gpix_per_s"]
+    return out
+
+
 def cpu_baseline(frames_host, spec, n_frames: int) -> dict:
     import oracle
 
@@ -136,6 +249,10 @@ def main() -> int:
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y override")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth reference")
     ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-resolve run")
+    ap.add_argument("--no-multistream", action="store_true", help="skip the batched-vs-plain runs")
+    ap.add_argument("--ring", type=int, default=48, help="distinct frames per stream kept resident (multistream)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving runs")
+    ap.add_argument("--serving-scale", type=float, default=0.25, help="time compression of the serving run")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -224,10 +341,33 @@ def main() -> int:
 
     copy_gbps = None if args.no_copy else copy_bandwidth(torch, dev)
 
+    host = [(c.cpu().numpy(), lev.cpu().numpy(), gx, gy) for (c, lev, gx, gy) in frames[:args.cpu_frames]]
+
+    multi = None
+    if not args.no_multistream:
+        del frames
+        torch.cuda.empty_cache()
+        left, right = synth.spec_stereo()
+        g_left = synth.gaze_trace(left)
+        g_right = g_left + np.array([synth.vergence_shift(), 0.0], dtype=np.float32)
+        g_right[:, 0] = np.clip(g_right[:, 0], 0.0, float(right.width))
+        multi = {
+            "stereo_2x2064x2208_k8": multistream(dev, stream, [left, right], [g_left, g_right], ticks=900,
+                                                 ring=args.ring, use_graph=True, label="stereo"),
+        }
+        uneven = synth.spec_uneven()
+        multi["uneven_16_streams"] = multistream(dev, stream, uneven, [synth.gaze_trace(s) for s in uneven],
+                                                 ticks=300, ring=args.ring, use_graph=True, label="uneven")
+
+    served = None
+    if not args.no_serving:
+        torch.cuda.empty_cache()
+        served = {"paced": serving(dev, stream, args.serving_scale, 1.0, 24, "serving"),
+                  "saturated": serving(dev, stream, 0.4 * args.serving_scale, 4.0, 24, "saturated")}
+
     cpu = None
     if args.cpu_frames > 0:
         log(f"timing the CPU oracle on {args.cpu_frames} frames")
-        host = [(c.cpu().numpy(), lev.cpu().numpy(), gx, gy) for (c, lev, gx, gy) in frames[:args.cpu_frames]]
         cpu = cpu_baseline(host, spec, args.cpu_frames)
 
     line = {
@@ -257,6 +397,8 @@ def main() -> int:
         "ms_per_frame_p99": float(np.percentile(per, 99)),
         "pixels_changed_per_pixel_update": changed / updates,
         "incremental": incremental,
+        "multistream": multi,
+        "serving": served,
         "copy_gbps": copy_gbps,
         "state_ok": bool(st_ok),
     }

@@ -221,7 +221,8 @@ const char* fwrs_strerror(int status);
 
 /* ---- batched form --------------------------------------------------------
  * One tick advances several contexts -- any mix of sizes and slot counts, on
- * the same device -- by one frame each with a single persistent kernel launch.
+ * the same device -- by one frame each with a single kernel launch (one block
+ * per 256-pixel work item of any of the tick's frames).
  * Each entry is the argument list of fwrs_push_frame_resolve; the results are
  * bit-identical to calling it once per entry.  A context may appear at most
  * once per tick.  Contexts' own streams are not used: the tick runs on the
@@ -238,11 +239,12 @@ typedef struct fwrs_frame {
 
 typedef struct fwrs_engine fwrs_engine;
 
-/* Creates a tick engine for up to `max_frames` entries per tick on a
- * borrowed HIP stream.  With use_graph != 0 each tick replays a captured HIP
- * graph (descriptor upload + persistent kernel) instead of issuing the two
- * operations.  The engine owns a device descriptor table and two pinned host
- * staging buffers. */
+/* Creates a tick engine for up to `max_frames` (<= 4096) entries per tick on a
+ * borrowed HIP stream.  A tick is issued as ceil(n / 24) launches of the
+ * batched kernel whose frame descriptors are kernel arguments.  With
+ * use_graph != 0 those launches are the kernel nodes of a HIP graph that each
+ * tick updates and replays (one graph per launch count, built on first use);
+ * the stream must then not be capturing. */
 int fwrs_engine_create(void* hip_stream, int max_frames, int use_graph, fwrs_engine** out);
 
 /* Enqueues one tick.  FWRS_E_ARG: n outside [0, max_frames], a NULL field, a

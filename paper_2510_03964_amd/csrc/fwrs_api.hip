@@ -57,8 +57,8 @@ fwrs::Consts derive(const fwrs_params& p, int width)
     c.IR2 = 1.0f / p.r2k;
     c.IRM = 1.0f / p.r_m;
     c.C = 1.44269504088896341f / p.rek;
-    c.ppd = (float)width / p.fov_deg;
-    c.iPPD = 1.0f / c.ppd;
+    const float ppd = (float)width / p.fov_deg;
+    c.iPPD = 1.0f / ppd;
     c.rf = p.fovea_radius_px * c.iPPD;
     float num, den;
     fwrs::density_terms(c, c.rf, num, den);
@@ -171,7 +171,6 @@ FrameDesc make_desc(const fwrs_ctx* x, const float* color, const uint8_t* level,
     d.bias = x->prm.bias_mode;
     d.k = (uint32_t)x->k;
     fill_geometry(d, x->width, x->height, tx, ty);
-    d.item_begin = 0;
     return d;
 }
 
@@ -449,7 +448,12 @@ const char* fwrs_strerror(int status)
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Batched tick engine
+// Batched tick engine: the frames of a tick go to the batched kernel in
+// launches of up to fwrs::kTickFrames frames whose descriptors are kernel
+// arguments (nothing is uploaded before a launch).  In graph mode the
+// launches of a tick are the kernel nodes of a HIP graph (one graph per
+// launch count, built on first use); each tick rewrites the nodes' arguments
+// and grids and replays it.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -458,7 +462,11 @@ struct TileClass {
     int tx, ty;
 };
 
-constexpr size_t kHdrBytes = 256;   // header (frame count, total items) padded so the table is aligned
+struct TickGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraphNode_t> nodes;
+};
 
 }  // namespace
 
@@ -467,28 +475,19 @@ struct fwrs_engine {
     int device = 0;
     int max_frames = 0;
     int use_graph = 0;
-    uint32_t grid = 0;
-    size_t table_bytes = 0;
-    void* d_buf = nullptr;          // header + descriptor table
-    void* h_stage[2] = {nullptr, nullptr};
-    hipEvent_t done[2] = {nullptr, nullptr};
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    int cur = 0;
     std::vector<TileClass> classes;
+    std::vector<fwrs::TickArgs> args;          // one per launch of the current tick
+    std::vector<TickGraph> graphs;             // graphs[m - 1]: a tick of m launches
 };
 
 namespace {
 
 void engine_free(fwrs_engine* e)
 {
-    for (int b = 0; b < 2; ++b) {
-        if (e->exec[b]) (void)hipGraphExecDestroy(e->exec[b]);
-        if (e->graph[b]) (void)hipGraphDestroy(e->graph[b]);
-        if (e->done[b]) (void)hipEventDestroy(e->done[b]);
-        if (e->h_stage[b]) (void)hipHostFree(e->h_stage[b]);
+    for (TickGraph& g : e->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
     }
-    if (e->d_buf) (void)hipFree(e->d_buf);
     delete e;
 }
 
@@ -505,6 +504,42 @@ void engine_tile(const fwrs_engine* e, long long pixels, int& tx, int& ty)
         }
 }
 
+hipKernelNodeParams tick_node_params(fwrs::TickArgs* a, void** slot)
+{
+    *slot = a;
+    hipKernelNodeParams kp{};
+    kp.func = fwrs::tick_kernel_entry();
+    kp.gridDim = dim3(a->total > 0 ? a->total : 1u);
+    kp.blockDim = dim3(fwrs::kBlock);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = slot;
+    kp.extra = nullptr;
+    return kp;
+}
+
+// The graph for a tick of m launches: m kernel nodes in a chain.
+hipError_t engine_graph(fwrs_engine* e, int m, TickGraph** out)
+{
+    if ((int)e->graphs.size() < m) e->graphs.resize(m);
+    TickGraph& g = e->graphs[m - 1];
+    if (!g.exec) {
+        hipError_t err = hipGraphCreate(&g.graph, 0);
+        hipGraphNode_t prev = nullptr;
+        for (int c = 0; c < m && err == hipSuccess; ++c) {
+            void* slot;
+            hipKernelNodeParams kp = tick_node_params(&e->args[c], &slot);
+            hipGraphNode_t node = nullptr;
+            err = hipGraphAddKernelNode(&node, g.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+            g.nodes.push_back(node);
+            prev = node;
+        }
+        if (err == hipSuccess) err = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+        if (err != hipSuccess) return err;
+    }
+    *out = &g;
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -518,58 +553,15 @@ int fwrs_engine_create(void* hip_stream, int max_frames, int use_graph, fwrs_eng
     e->stream = (hipStream_t)hip_stream;
     e->max_frames = max_frames;
     e->use_graph = use_graph ? 1 : 0;
-    if (hipGetDevice(&e->device) != hipSuccess) { delete e; return FWRS_E_HIP; }
-    int cus = 0, per_cu = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, e->device) != hipSuccess ||
-        fwrs::tick_occupancy(&per_cu) != hipSuccess) {
+    if (hipGetDevice(&e->device) != hipSuccess) {
         delete e;
         return FWRS_E_HIP;
     }
-    if (per_cu < 1) per_cu = 1;
-    e->grid = (uint32_t)(cus * per_cu);
-    e->table_bytes = kHdrBytes + sizeof(FrameDesc) * (size_t)max_frames;
-    if (hipMalloc(&e->d_buf, e->table_bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        engine_free(e);
+    try {
+        e->args.resize((size_t)(max_frames + fwrs::kTickFrames - 1) / fwrs::kTickFrames);
+    } catch (const std::bad_alloc&) {
+        delete e;
         return FWRS_E_NOMEM;
-    }
-    for (int b = 0; b < 2; ++b) {
-        if (hipHostMalloc(&e->h_stage[b], e->table_bytes, hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            engine_free(e);
-            return FWRS_E_NOMEM;
-        }
-        std::memset(e->h_stage[b], 0, e->table_bytes);
-        if (hipEventCreateWithFlags(&e->done[b], hipEventDisableTiming) != hipSuccess) {
-            engine_free(e);
-            return FWRS_E_HIP;
-        }
-    }
-    if (e->use_graph) {
-        const FrameDesc* descs = reinterpret_cast<const FrameDesc*>(static_cast<char*>(e->d_buf) + kHdrBytes);
-        const uint32_t* hdr = static_cast<const uint32_t*>(e->d_buf);
-        for (int b = 0; b < 2; ++b) {
-            hipGraphNode_t copy = nullptr, kern = nullptr;
-            bool ok = hipGraphCreate(&e->graph[b], 0) == hipSuccess &&
-                      hipGraphAddMemcpyNode1D(&copy, e->graph[b], nullptr, 0, e->d_buf, e->h_stage[b],
-                                              e->table_bytes, hipMemcpyHostToDevice) == hipSuccess;
-            if (ok) {
-                void* args[2] = {(void*)&descs, (void*)&hdr};
-                hipKernelNodeParams kp{};
-                kp.func = fwrs::tick_kernel_entry();
-                kp.gridDim = dim3(e->grid);
-                kp.blockDim = dim3(fwrs::kBlock);
-                kp.sharedMemBytes = 0;
-                kp.kernelParams = args;
-                kp.extra = nullptr;
-                ok = hipGraphAddKernelNode(&kern, e->graph[b], &copy, 1, &kp) == hipSuccess &&
-                     hipGraphInstantiate(&e->exec[b], e->graph[b], nullptr, nullptr, 0) == hipSuccess;
-            }
-            if (!ok) {
-                engine_free(e);
-                return FWRS_E_HIP;
-            }
-        }
     }
     *out = e;
     return FWRS_OK;
@@ -600,40 +592,41 @@ int fwrs_engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n)
         for (int j = 0; j < i; ++j)
             if (frames[j].ctx == f.ctx) return FWRS_E_ARG;
     }
+    if (n == 0) return FWRS_OK;
     DeviceGuard g(e->device);
     if (!g.ok) return FWRS_E_HIP;
-    const int b = e->cur;
-    // The staging buffer was last read by the tick issued two calls ago.
-    if (hipEventSynchronize(e->done[b]) != hipSuccess) return FWRS_E_HIP;
-    char* stage = static_cast<char*>(e->h_stage[b]);
-    FrameDesc* descs = reinterpret_cast<FrameDesc*>(stage + kHdrBytes);
-    uint32_t total = 0;
-    for (int i = 0; i < n; ++i) {
-        const fwrs_frame& f = frames[i];
-        int tx, ty;
-        engine_tile(e, (long long)f.ctx->width * f.ctx->height, tx, ty);
-        FrameDesc d = make_desc(f.ctx, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, tx, ty);
-        d.item_begin = total;
-        total += d.items;
-        descs[i] = d;
-    }
-    uint32_t* hdr = reinterpret_cast<uint32_t*>(stage);
-    hdr[0] = (uint32_t)n;
-    hdr[1] = total;
-    hipError_t err;
-    if (e->use_graph) {
-        err = hipGraphLaunch(e->exec[b], e->stream);
-    } else {
-        const size_t bytes = kHdrBytes + sizeof(FrameDesc) * (size_t)n;
-        err = hipMemcpyAsync(e->d_buf, stage, bytes, hipMemcpyHostToDevice, e->stream);
-        if (err == hipSuccess && total > 0) {
-            const FrameDesc* dd = reinterpret_cast<const FrameDesc*>(static_cast<char*>(e->d_buf) + kHdrBytes);
-            err = fwrs::launch_tick(dd, static_cast<const uint32_t*>(e->d_buf), e->grid, e->stream);
+    const int m = (n + fwrs::kTickFrames - 1) / fwrs::kTickFrames;
+    for (int c = 0; c < m; ++c) {
+        fwrs::TickArgs& a = e->args[c];
+        a.n = 0;
+        a.total = 0;
+        for (int i = c * fwrs::kTickFrames; i < n && i < (c + 1) * fwrs::kTickFrames; ++i) {
+            const fwrs_frame& f = frames[i];
+            int tx, ty;
+            engine_tile(e, (long long)f.ctx->width * f.ctx->height, tx, ty);
+            a.descs[a.n] = make_desc(f.ctx, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, tx, ty);
+            a.begins[a.n] = a.total;
+            a.total += a.descs[a.n].items;
+            ++a.n;
         }
     }
-    if (err != hipSuccess) return FWRS_E_HIP;
-    if (hipEventRecord(e->done[b], e->stream) != hipSuccess) return FWRS_E_HIP;
-    e->cur ^= 1;
+    hipError_t err = hipSuccess;
+    if (e->use_graph) {
+        TickGraph* tg = nullptr;
+        err = engine_graph(e, m, &tg);
+        for (int c = 0; c < m && err == hipSuccess; ++c) {
+            void* slot;
+            hipKernelNodeParams kp = tick_node_params(&e->args[c], &slot);
+            err = hipGraphExecKernelNodeSetParams(tg->exec, tg->nodes[c], &kp);
+        }
+        if (err == hipSuccess) err = hipGraphLaunch(tg->exec, e->stream);
+    } else {
+        for (int c = 0; c < m && err == hipSuccess; ++c) err = fwrs::launch_tick(e->args[c], e->stream);
+    }
+    if (err != hipSuccess) {
+        (void)hipGetLastError();
+        return FWRS_E_HIP;
+    }
     for (int i = 0; i < n; ++i) {
         fwrs_ctx* c = frames[i].ctx;
         c->t += 1u;

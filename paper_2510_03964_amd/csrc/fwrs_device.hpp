@@ -21,15 +21,14 @@ struct Consts {
     float IR2;   // 1 / r_2,k
     float IRM;   // 1 / r_m
     float C;     // log2(e) / r_e,k: exp(-e / r_e,k) = 2^(-e C)
-    float ppd;   // pixels per degree = width / fov_deg
-    float iPPD;  // 1 / ppd
+    float iPPD;  // degrees per pixel = fov_deg / width (as 1 / (width / fov_deg))
     float rf;    // foveal radius in degrees = fovea_radius_px / ppd
     float Drf;   // density at r_f (normalisation of Eq. 4)
 };
 
 // Everything one frame of one context needs on the device.  Passed by value
 // to the single-frame kernels and stored in a device table for batched ticks.
-struct alignas(16) FrameDesc {
+struct alignas(8) FrameDesc {
     const float* color;         // [H][W][3] f32, the new candidates
     const uint8_t* level;       // [H][W] u8 foveation level
     float* out;                 // [H][W][3] f32 resolve target (null for update-only)
@@ -42,10 +41,10 @@ struct alignas(16) FrameDesc {
     Consts c;
     uint32_t seed, stream_id, bias;
     uint32_t tile_x_log2, tile_y_log2, tiles_x, items;  // launch geometry
-    uint32_t item_begin;        // first work item of this frame in a batched tick
 };
 
 constexpr int kBlock = 256;             // threads per block
+constexpr int kTickFrames = 24;         // frames per batched launch (descriptors travel as kernel arguments)
 constexpr int kStatSlots = 1024;        // spread of the slot-take counters
 constexpr uint32_t kBiasNone = 0u;
 constexpr uint32_t kBiasBernoulli = 1u;

@@ -15,15 +15,21 @@ constexpr int kMaxK = 16;
 // 5 = update + resolve of the changed pixels only.
 hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream);
 
-// Persistent batched kernel over a device table of frame descriptors.
-// hdr[0] = number of frames, hdr[1] = total work items.
-hipError_t launch_tick(const FrameDesc* descs, const uint32_t* hdr, uint32_t grid, hipStream_t stream);
+// Arguments of one batched launch: n frames, `total` work items, frame f owns
+// items [begins[f], begins[f + 1]).  Passed by value (< 4 KiB).
+struct TickArgs {
+    uint32_t n, total;
+    uint32_t begins[kTickFrames];
+    FrameDesc descs[kTickFrames];
+};
+static_assert(sizeof(TickArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+
+// Batched kernel, one block per work item of the launch's frames.
+hipError_t launch_tick(const TickArgs& a, hipStream_t stream);
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t stream);
 
-hipError_t tick_occupancy(int* blocks_per_cu);
-
-// Entry point of the persistent batched kernel, for HIP graph kernel nodes.
+// Entry point of the batched kernel, for HIP graph kernel nodes.
 void* tick_kernel_entry();
 
 }  // namespace fwrs

@@ -292,29 +292,32 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(FrameDesc d)
 }
 
 // ---------------------------------------------------------------------------
-// Batched tick: a persistent grid walks the concatenated work items of all
-// frames in the table (sorted by item_begin); each block keeps the index of
-// the frame its current item belongs to, which only moves forward.
+// Batched tick: one block per work item of any of up to kTickFrames frames.
+// The descriptors travel in the kernel arguments (no upload before the
+// launch); begins[f] is the first item of frame f (increasing).  A block finds
+// its frame by counting the begins at or below its item (uniform, scalar),
+// then runs the same per-pixel code as the single-frame kernels.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void tick_kernel(const FrameDesc* __restrict__ descs,
-                                                      const uint32_t* __restrict__ hdr)
+__global__ __launch_bounds__(kBlock) void tick_kernel(const TickArgs a)
 {
-    const uint32_t nframes = hdr[0];
-    const uint32_t total = hdr[1];
-    uint32_t f = 0u;
-    for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
-        while (f + 1u < nframes && descs[f + 1u].item_begin <= item) ++f;
-        const FrameDesc& d = descs[f];
-        const uint32_t local = item - d.item_begin;
-        uint32_t n;
-        switch (d.k) {
-            case 2: n = process_item<2, kFused>(d, local); break;
-            case 4: n = process_item<4, kFused>(d, local); break;
-            case 8: n = process_item<8, kFused>(d, local); break;
-            default: n = process_item<0, kFused>(d, local); break;
-        }
-        if (d.stats) add_stats(d.stats, n);
+    const uint32_t item = blockIdx.x;
+    if (item >= a.total) return;                     // whole block
+    // frame = number of frames f >= 1 with begins[f] <= item; all begins are read
+    // at once (independent scalar loads), no chain of dependent loads
+    uint32_t lo = 0u;
+#pragma unroll
+    for (int f = 1; f < kTickFrames; ++f) lo += ((uint32_t)f < a.n && a.begins[f] <= item) ? 1u : 0u;
+    const FrameDesc& d = a.descs[lo];
+    const uint32_t local = item - a.begins[lo];
+    uint32_t n;
+    switch (d.k) {
+        case 1: n = process_item<1, kFused>(d, local); break;
+        case 2: n = process_item<2, kFused>(d, local); break;
+        case 4: n = process_item<4, kFused>(d, local); break;
+        case 8: n = process_item<8, kFused>(d, local); break;
+        default: n = process_item<0, kFused>(d, local); break;
     }
+    if (d.stats) add_stats(d.stats, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -354,9 +357,10 @@ hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream)
     }
 }
 
-hipError_t launch_tick(const FrameDesc* descs, const uint32_t* hdr, uint32_t grid, hipStream_t stream)
+hipError_t launch_tick(const TickArgs& a, hipStream_t stream)
 {
-    hipLaunchKernelGGL(tick_kernel, dim3(grid), dim3(kBlock), 0, stream, descs, hdr);
+    if (a.total == 0u) return hipSuccess;
+    hipLaunchKernelGGL(tick_kernel, dim3(a.total), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -371,9 +375,5 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t stream
 
 void* tick_kernel_entry() { return reinterpret_cast<void*>(&tick_kernel); }
 
-hipError_t tick_occupancy(int* blocks_per_cu)
-{
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, tick_kernel, kBlock, 0);
-}
 
 }  // namespace fwrs

@@ -305,7 +305,7 @@ class Reservoir:
 
 
 class Engine:
-    """Batched ticks: one persistent launch advances many contexts by one frame."""
+    """Batched ticks: one kernel launch advances many contexts by one frame."""
 
     def __init__(self, max_frames: int, stream=None, use_graph: bool = False):
         self._L = load()
