@@ -20,6 +20,7 @@ from . import build as _build
 
 BIAS_NONE = 0
 BIAS_BERNOULLI = 1
+BIAS_FULL = 2
 
 _lib = None
 
@@ -80,6 +81,11 @@ def _bind(L):
     L.fwrs_oracle_philox_many.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
                                           C.POINTER(C.c_uint32), C.c_size_t]
     L.fwrs_oracle_exp2p_many.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_size_t]
+    L.fwrs_oracle_cbrt_many.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_size_t]
+    L.fwrs_oracle_lab_many.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_size_t]
+    L.fwrs_oracle_de94_many.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                        C.c_size_t]
+    L.fwrs_oracle_slot_sums.argtypes = [vp, C.POINTER(C.c_float)]
     L.fwrs_oracle_density_many.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_size_t]
     L.fwrs_oracle_eccentricity.argtypes = [vp, C.c_int, C.c_int, C.c_float, C.c_float]
     L.fwrs_oracle_eccentricity.restype = C.c_float
@@ -110,6 +116,7 @@ class State:
     wt: np.ndarray     # [k, H, W] float32
     idx: np.ndarray    # [k, H, W] uint32
     col: np.ndarray    # [k, 3, H, W] float32
+    wslot: np.ndarray  # [k, H, W] float32 per-slot w_sum (the shared w_sum k times unless BIAS_FULL)
 
 
 class Oracle:
@@ -161,9 +168,10 @@ class Oracle:
     def state(self) -> State:
         H, W, k = self.height, self.width, self.k
         s = State(np.empty((H, W), np.float32), np.empty((H, W), np.uint32), np.empty((k, H, W), np.float32),
-                  np.empty((k, H, W), np.uint32), np.empty((k, 3, H, W), np.float32))
+                  np.empty((k, H, W), np.uint32), np.empty((k, 3, H, W), np.float32), np.empty((k, H, W), np.float32))
         self._L.fwrs_oracle_state(self._h, _ptr(s.wsum, C.c_float), _ptr(s.cnt, C.c_uint32),
                                   _ptr(s.wt, C.c_float), _ptr(s.idx, C.c_uint32), _ptr(s.col, C.c_float))
+        self._L.fwrs_oracle_slot_sums(self._h, _ptr(s.wslot, C.c_float))
         return s
 
     def constants(self) -> dict:
@@ -200,6 +208,29 @@ def philox(keys: np.ndarray, ctrs: np.ndarray) -> np.ndarray:
     n = ctrs.shape[0]
     out = np.empty((n, 4), np.uint32)
     lib().fwrs_oracle_philox_many(_ptr(keys, C.c_uint32), _ptr(ctrs, C.c_uint32), _ptr(out, C.c_uint32), n)
+    return out
+
+
+def cbrt(t: np.ndarray) -> np.ndarray:
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    out = np.empty_like(t)
+    lib().fwrs_oracle_cbrt_many(_ptr(t, C.c_float), _ptr(out, C.c_float), t.size)
+    return out
+
+
+def lab(rgb: np.ndarray) -> np.ndarray:
+    """Linear RGB [..., 3] -> CIE Lab [..., 3] (D65), binary32."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.float32)
+    out = np.empty_like(rgb)
+    lib().fwrs_oracle_lab_many(_ptr(rgb, C.c_float), _ptr(out, C.c_float), rgb.size // 3)
+    return out
+
+
+def de94(ref_lab: np.ndarray, x_lab: np.ndarray) -> np.ndarray:
+    ref_lab = np.ascontiguousarray(ref_lab, dtype=np.float32)
+    x_lab = np.ascontiguousarray(x_lab, dtype=np.float32)
+    out = np.empty(ref_lab.size // 3, np.float32)
+    lib().fwrs_oracle_de94_many(_ptr(ref_lab, C.c_float), _ptr(x_lab, C.c_float), _ptr(out, C.c_float), out.size)
     return out
 
 

@@ -19,6 +19,8 @@
  *   Sec. 4.1, Eq. 4      weight w(e) = 1 inside the fovea, d(e)/d(r_f) outside
  *   Sec. 4.2, Eq. 5, 6   Bernoulli survival bias applied to R1.w_sum before
  *                        the combine
+ *   Sec. 4.3, Eq. 7      full temporal bias: Eq. 6 additionally scaled by
+ *                        (1 - |dL|), dL from the CIE94 colour difference in Lab
  *
  * Precision.  Every quantity that decides which sample a slot keeps (the
  * weight, the biased weight sum, the uniform variate and the comparison) is
@@ -45,6 +47,11 @@
  *     biased R1.w_sum and R2.w_sum).
  *   - resolve: out = sum_j wt_j * col_j / sum_j wt_j over the slots, with the
  *     render-time weights; 0 before the first frame.
+ *   - Eq. 7 (BIAS_FULL): dL compares the new pixel with the slot's sample, so
+ *     every slot keeps its own w_sum; |dL| = min(1, dE94 / 100) with dE94 the
+ *     CIE94 difference (graphic-arts weights, the slot's sample as reference)
+ *     of the two colours in CIE Lab (D65), the colours read as linear RGB.
+ *     The factors apply left to right: (W1 * (1 - |dL|)) * (1 - w / (W1 + w)).
  */
 #include <math.h>
 #include <stddef.h>
@@ -163,6 +170,81 @@ float fwrs_oracle_weight(const fwrs_oracle* o, int x, int y, uint8_t level, floa
 }
 
 /* ------------------------------------------------------------------------ */
+/* Colour difference for Eq. 7.                                               */
+/* ------------------------------------------------------------------------ */
+/* Cube root for t > 0: a seed from the exponent bits (the bit pattern of     */
+/* t^(1/3) is about bits(t)/3 + (2/3)*127*2^23), then Newton steps            */
+/* y <- y - (y^3 - t) / (3 y^2).                                              */
+float fwrs_oracle_cbrt(float t)
+{
+    uint32_t bits;
+    memcpy(&bits, &t, 4);
+    bits = bits / 3u + 0x2A555555u;
+    float y;
+    memcpy(&y, &bits, 4);
+    for (int it = 0; it < 4; ++it) {
+        float y2 = y * y;
+        float y3 = y2 * y;
+        float num = y3 - t;
+        float den = 3.0f * y2;
+        y = y - num / den;
+    }
+    return y;
+}
+
+/* CIE Lab f(): cube root above (6/29)^3, the linear segment below. */
+static float lab_f(float t)
+{
+    const float eps = 216.0f / 24389.0f;         /* (6/29)^3 */
+    const float slope = 841.0f / 108.0f;         /* 1 / (3 (6/29)^2) */
+    const float off = 4.0f / 29.0f;
+    if (t > eps) return fwrs_oracle_cbrt(t);
+    return t * slope + off;
+}
+
+/* Linear RGB (sRGB primaries) -> XYZ -> Lab, D65 white. */
+void fwrs_oracle_lab(float r, float g, float b, float lab[3])
+{
+    float X = (0.4124564f * r + 0.3575761f * g) + 0.1804375f * b;
+    float Y = (0.2126729f * r + 0.7151522f * g) + 0.0721750f * b;
+    float Z = (0.0193339f * r + 0.1191920f * g) + 0.9503041f * b;
+    float fx = lab_f(X / 0.95047f);
+    float fy = lab_f(Y / 1.0f);
+    float fz = lab_f(Z / 1.08883f);
+    lab[0] = 116.0f * fy - 16.0f;
+    lab[1] = 500.0f * (fx - fy);
+    lab[2] = 200.0f * (fy - fz);
+}
+
+/* CIE94, graphic-arts weights (k_L = k_C = k_H = 1, K1 = 0.045, K2 = 0.015),
+ * `ref` is the reference colour whose chroma scales S_C and S_H. */
+float fwrs_oracle_de94(const float ref[3], const float x[3])
+{
+    float dL = ref[0] - x[0];
+    float C1 = sqrtf(ref[1] * ref[1] + ref[2] * ref[2]);
+    float C2 = sqrtf(x[1] * x[1] + x[2] * x[2]);
+    float dC = C1 - C2;
+    float da = ref[1] - x[1];
+    float db = ref[2] - x[2];
+    float dH2 = (da * da + db * db) - dC * dC;
+    if (dH2 < 0.0f) dH2 = 0.0f;                  /* rounding can leave it slightly negative */
+    float SC = 1.0f + 0.045f * C1;
+    float SH = 1.0f + 0.015f * C1;
+    float tC = dC / SC;
+    float sum = dL * dL + tC * tC + dH2 / (SH * SH);
+    return sqrtf(sum);
+}
+
+/* |dL| of Eq. 7 between a reservoir sample (reference) and a new pixel. */
+float fwrs_oracle_delta_l(const float rgb_ref[3], const float rgb_x[3])
+{
+    float a[3], b[3];
+    fwrs_oracle_lab(rgb_ref[0], rgb_ref[1], rgb_ref[2], a);
+    fwrs_oracle_lab(rgb_x[0], rgb_x[1], rgb_x[2], b);
+    return fminf(1.0f, fwrs_oracle_de94(a, b) / 100.0f);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Context                                                                    */
 /* ------------------------------------------------------------------------ */
 void fwrs_oracle_default_params(int width, fwrs_oracle_params* p)
@@ -209,7 +291,9 @@ fwrs_oracle* fwrs_oracle_create(int width, int height, int k, const fwrs_oracle_
     o->wt = (float*)calloc(n * (size_t)k, sizeof(float));
     o->idx = (uint32_t*)malloc(n * (size_t)k * sizeof(uint32_t));
     o->col = (float*)calloc(n * (size_t)k * 3, sizeof(float));
-    if (!o->wsum || !o->cnt || !o->wt || !o->idx || !o->col) {
+    if (o->prm.bias_mode == FWRS_ORACLE_BIAS_FULL) o->wslot = (float*)calloc(n * (size_t)k, sizeof(float));
+    if (!o->wsum || !o->cnt || !o->wt || !o->idx || !o->col ||
+        (o->prm.bias_mode == FWRS_ORACLE_BIAS_FULL && !o->wslot)) {
         fwrs_oracle_destroy(o);
         return NULL;
     }
@@ -221,7 +305,7 @@ fwrs_oracle* fwrs_oracle_create(int width, int height, int k, const fwrs_oracle_
 void fwrs_oracle_destroy(fwrs_oracle* o)
 {
     if (!o) return;
-    free(o->wsum); free(o->cnt); free(o->wt); free(o->idx); free(o->col);
+    free(o->wsum); free(o->cnt); free(o->wt); free(o->idx); free(o->col); free(o->wslot);
     free(o);
 }
 
@@ -235,10 +319,46 @@ void fwrs_oracle_destroy(fwrs_oracle* o)
 /* ------------------------------------------------------------------------ */
 static void update_pixel(const fwrs_oracle* o, int x, int y, uint32_t p, uint32_t t,
                          const float rgb[3], uint8_t level, float gx, float gy,
-                         float* wsum, uint32_t* cnt, float* wt, uint32_t* idx, float* col, size_t n)
+                         float* wsum, uint32_t* cnt, float* wt, uint32_t* idx, float* col, float* wslot, size_t n)
 {
     const int k = o->k;
     float w = fwrs_oracle_weight(o, x, y, level, gx, gy);
+    if (o->prm.bias_mode == FWRS_ORACLE_BIAS_FULL) {
+        /* Eq. 7 per slot: the slot's own w_sum, biased by its colour difference
+         * to the new pixel and by the survival probability; then Alg. 2. */
+        uint32_t key[2] = {o->prm.seed, o->prm.stream_id};
+        uint32_t words[4];
+        int have_block = -1;
+        for (int j = 0; j < k; ++j) {
+            int b = j / 4;
+            if (b != have_block) {
+                uint32_t ctr[4] = {p, t, (uint32_t)b, 0u};
+                fwrs_oracle_philox(key, ctr, words);
+                have_block = b;
+            }
+            float kept[3] = {col[((size_t)j * 3 + 0) * n], col[((size_t)j * 3 + 1) * n],
+                             col[((size_t)j * 3 + 2) * n]};
+            float dl = fwrs_oracle_delta_l(kept, rgb);
+            float W1 = wslot[(size_t)j * n];
+            float total = W1 + w;
+            float q = w / total;
+            float survive = 1.0f - q;
+            float W1b = (W1 * (1.0f - dl)) * survive;   /* Eq. 7 */
+            float s = W1b + w;
+            float u = (float)((words[j % 4] >> 8) + 1u) * 0x1p-24f;
+            if (u * s > W1b) {
+                col[((size_t)j * 3 + 0) * n] = rgb[0];
+                col[((size_t)j * 3 + 1) * n] = rgb[1];
+                col[((size_t)j * 3 + 2) * n] = rgb[2];
+                wt[(size_t)j * n] = w;
+                idx[(size_t)j * n] = t;
+            }
+            wslot[(size_t)j * n] = s;
+        }
+        *wsum = 0.0f;
+        *cnt = *cnt + 1u;
+        return;
+    }
     float W1 = *wsum;
     float W1b = W1;
     if (o->prm.bias_mode == FWRS_ORACLE_BIAS_BERNOULLI) {
@@ -283,7 +403,8 @@ void fwrs_oracle_push_rows(fwrs_oracle* o, const float* color, const uint8_t* le
         for (int x = 0; x < o->width; ++x) {
             size_t p = (size_t)y * (size_t)o->width + (size_t)x;
             update_pixel(o, x, y, (uint32_t)p, o->t, color + 3 * p, level[p], gx, gy,
-                         o->wsum + p, o->cnt + p, o->wt + p, o->idx + p, o->col + p, n);
+                         o->wsum + p, o->cnt + p, o->wt + p, o->idx + p, o->col + p,
+                         o->wslot ? o->wslot + p : NULL, n);
         }
     }
 }
@@ -297,7 +418,8 @@ void fwrs_oracle_push(fwrs_oracle* o, const float* color, const uint8_t* level, 
         for (int x = 0; x < o->width; ++x) {
             size_t p = (size_t)y * (size_t)o->width + (size_t)x;
             update_pixel(o, x, y, (uint32_t)p, o->t, color + 3 * p, level[p], gx, gy,
-                         o->wsum + p, o->cnt + p, o->wt + p, o->idx + p, o->col + p, n);
+                         o->wsum + p, o->cnt + p, o->wt + p, o->idx + p, o->col + p,
+                         o->wslot ? o->wslot + p : NULL, n);
         }
     }
     o->t += 1u;
@@ -329,6 +451,14 @@ void fwrs_oracle_resolve(const fwrs_oracle* o, double* out)
 /* ------------------------------------------------------------------------ */
 uint32_t fwrs_oracle_frame_index(const fwrs_oracle* o) { return o->t; }
 
+/* Per-slot w_sum [k][N]: BIAS_FULL's own sums, else the shared w_sum k times. */
+void fwrs_oracle_slot_sums(const fwrs_oracle* o, float* wslot)
+{
+    const size_t n = (size_t)o->width * (size_t)o->height;
+    for (int j = 0; j < o->k; ++j)
+        memcpy(wslot + (size_t)j * n, o->wslot ? o->wslot + (size_t)j * n : o->wsum, n * sizeof(float));
+}
+
 void fwrs_oracle_constants(const fwrs_oracle* o, float out[9])
 {
     out[0] = o->A; out[1] = o->B; out[2] = o->IR2; out[3] = o->IRM; out[4] = o->C;
@@ -349,6 +479,21 @@ void fwrs_oracle_state(const fwrs_oracle* o, float* wsum, uint32_t* cnt, float* 
 void fwrs_oracle_philox_many(const uint32_t* keys, const uint32_t* ctrs, uint32_t* out, size_t count)
 {
     for (size_t i = 0; i < count; ++i) fwrs_oracle_philox(keys + 2 * i, ctrs + 4 * i, out + 4 * i);
+}
+
+void fwrs_oracle_cbrt_many(const float* t, float* out, size_t count)
+{
+    for (size_t i = 0; i < count; ++i) out[i] = fwrs_oracle_cbrt(t[i]);
+}
+
+void fwrs_oracle_lab_many(const float* rgb, float* lab, size_t count)
+{
+    for (size_t i = 0; i < count; ++i) fwrs_oracle_lab(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], lab + 3 * i);
+}
+
+void fwrs_oracle_de94_many(const float* ref, const float* x, float* out, size_t count)
+{
+    for (size_t i = 0; i < count; ++i) out[i] = fwrs_oracle_de94(ref + 3 * i, x + 3 * i);
 }
 
 void fwrs_oracle_exp2p_many(const float* y, float* out, size_t count)
@@ -392,15 +537,16 @@ int fwrs_oracle_trials(int width, int height, int k, const fwrs_oracle_params* p
         o->wsum[0] = 0.0f;
         o->cnt[0] = 0u;
         for (int j = 0; j < k; ++j) {
+            if (o->wslot) o->wslot[j] = 0.0f;
             o->wt[j] = 0.0f;
             o->idx[j] = 0xFFFFFFFFu;
             o->col[3 * j + 0] = o->col[3 * j + 1] = o->col[3 * j + 2] = 0.0f;
         }
         for (int f = 0; f < n_frames; ++f)
             update_pixel(o, px, py, pix, (uint32_t)f, rgb + 3 * f, lev[f], gaze[2 * f], gaze[2 * f + 1],
-                         o->wsum, o->cnt, o->wt, o->idx, o->col, 1);
+                         o->wsum, o->cnt, o->wt, o->idx, o->col, o->wslot, 1);
         for (int j = 0; j < k; ++j) idx_out[(size_t)trial * (size_t)k + (size_t)j] = o->idx[j];
-        if (wsum_out) wsum_out[trial] = o->wsum[0];
+        if (wsum_out) wsum_out[trial] = o->wslot ? o->wslot[0] : o->wsum[0];
     }
     o->width = 1;
     o->height = 1;

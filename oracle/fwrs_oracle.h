@@ -25,6 +25,7 @@ extern "C" {
 
 #define FWRS_ORACLE_BIAS_NONE 0u
 #define FWRS_ORACLE_BIAS_BERNOULLI 1u
+#define FWRS_ORACLE_BIAS_FULL 2u      /* Eq. 7: Eq. 6 times (1 - |dL|), per-slot w_sum */
 
 typedef struct fwrs_oracle_params {
     uint32_t seed;            /* Philox key word 0 */
@@ -45,6 +46,7 @@ typedef struct fwrs_oracle {
     float* wt;
     uint32_t* idx;
     float* col;
+    float* wslot;   /* [k][N] per-slot w_sum (BIAS_FULL only; NULL otherwise) */
 } fwrs_oracle;
 
 void fwrs_oracle_default_params(int width, fwrs_oracle_params* p);
@@ -58,6 +60,15 @@ void fwrs_oracle_resolve(const fwrs_oracle* o, double* out);
 uint32_t fwrs_oracle_frame_index(const fwrs_oracle* o);
 void fwrs_oracle_constants(const fwrs_oracle* o, float out[9]);
 void fwrs_oracle_state(const fwrs_oracle* o, float* wsum, uint32_t* cnt, float* wt, uint32_t* idx, float* col);
+void fwrs_oracle_slot_sums(const fwrs_oracle* o, float* wslot);
+
+float fwrs_oracle_cbrt(float t);
+void fwrs_oracle_lab(float r, float g, float b, float lab[3]);
+float fwrs_oracle_de94(const float ref[3], const float x[3]);
+float fwrs_oracle_delta_l(const float rgb_ref[3], const float rgb_x[3]);
+void fwrs_oracle_cbrt_many(const float* t, float* out, size_t count);
+void fwrs_oracle_lab_many(const float* rgb, float* lab, size_t count);
+void fwrs_oracle_de94_many(const float* ref, const float* x, float* out, size_t count);
 
 void fwrs_oracle_philox(const uint32_t key[2], const uint32_t ctr[4], uint32_t out[4]);
 void fwrs_oracle_philox_many(const uint32_t* keys, const uint32_t* ctrs, uint32_t* out, size_t count);

@@ -1,0 +1,149 @@
+"""Pins of the oracle's Eq. 7 (full temporal bias) pieces, CPU only: the cube root against libm,
+Lab and CIE94 against a binary64 evaluation of the published definitions and their closed-form
+special cases, and the whole update against Eq. 6 where dL vanishes and against "always replace"
+where it saturates."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2510_03964_amd import synth
+
+# CIE constants: sRGB primaries to XYZ (D65) and the D65 white
+M = np.array([[0.4124564, 0.3575761, 0.1804375],
+              [0.2126729, 0.7151522, 0.0721750],
+              [0.0193339, 0.1191920, 0.9503041]])
+WHITE = np.array([0.95047, 1.0, 1.08883])
+
+
+def lab64(rgb):
+    xyz = np.asarray(rgb, np.float64) @ M.T / WHITE
+    d = 6.0 / 29.0
+    f = np.where(xyz > d ** 3, np.cbrt(xyz), xyz / (3 * d * d) + 4.0 / 29.0)
+    return np.stack([116 * f[..., 1] - 16, 500 * (f[..., 0] - f[..., 1]), 200 * (f[..., 1] - f[..., 2])], -1)
+
+
+def de94_64(ref, x):
+    ref, x = np.asarray(ref, np.float64), np.asarray(x, np.float64)
+    dL = ref[..., 0] - x[..., 0]
+    c1 = np.hypot(ref[..., 1], ref[..., 2])
+    c2 = np.hypot(x[..., 1], x[..., 2])
+    dC = c1 - c2
+    dH2 = np.maximum((ref[..., 1] - x[..., 1]) ** 2 + (ref[..., 2] - x[..., 2]) ** 2 - dC ** 2, 0.0)
+    return np.sqrt(dL ** 2 + (dC / (1 + 0.045 * c1)) ** 2 + dH2 / (1 + 0.015 * c1) ** 2)
+
+
+def test_cbrt_against_libm(oracle_mod):
+    a = np.array([216.0 / 24389.0], np.float32).view(np.uint32)[0]
+    b = np.array([2.0], np.float32).view(np.uint32)[0]
+    t = np.arange(a, b, 7, dtype=np.uint32).view(np.float32)
+    got = oracle_mod.cbrt(t).astype(np.float64)
+    want = np.cbrt(t.astype(np.float64))
+    ulp = np.ldexp(1.0, np.floor(np.log2(want)).astype(np.int64) - 23)
+    assert (np.abs(got - want) / ulp).max() <= 1.0
+    assert oracle_mod.cbrt(np.array([1.0, 0.125, 8.0], np.float32)).tolist() == [1.0, 0.5, 2.0]
+
+
+def test_lab_special_cases(oracle_mod):
+    v = np.linspace(0.0, 1.0, 1001, dtype=np.float32)
+    greys = np.stack([v, v, v], -1)
+    lab = oracle_mod.lab(greys).astype(np.float64)
+    # grey: a = b = 0 and L* = 116 Y^(1/3) - 16 above the knee, 903.3 Y below (closed form)
+    y = v.astype(np.float64)
+    knee = (6.0 / 29.0) ** 3
+    L = np.where(y > knee, 116 * np.cbrt(y) - 16, y * (29.0 / 3.0) ** 3)
+    assert np.abs(lab[:, 0] - L).max() < 2e-4
+    assert np.abs(lab[:, 1:]).max() < 2e-4
+    assert lab[-1, 0] == 100.0 and lab[0, 0] == 0.0
+
+
+def test_lab_matches_binary64_definition(oracle_mod):
+    rng = np.random.Generator(np.random.PCG64(4))
+    rgb = rng.uniform(0.0, 1.0, (20000, 3)).astype(np.float32)
+    got = oracle_mod.lab(rgb).astype(np.float64)
+    assert np.abs(got - lab64(rgb)).max() < 2e-3
+
+
+def test_de94_special_cases_and_binary64(oracle_mod):
+    rng = np.random.Generator(np.random.PCG64(5))
+    a = oracle_mod.lab(rng.uniform(0, 1, (5000, 3)).astype(np.float32))
+    b = oracle_mod.lab(rng.uniform(0, 1, (5000, 3)).astype(np.float32))
+    assert np.all(oracle_mod.de94(a, a) == 0.0)
+    got = oracle_mod.de94(a, b).astype(np.float64)
+    want = de94_64(a, b)
+    assert np.max(np.abs(got - want) / np.maximum(want, 1e-3)) < 1e-4
+    # achromatic pairs: dE94 = |dL*|
+    g1 = np.array([[40.0, 0.0, 0.0]] * 3, np.float32)
+    g2 = np.array([[70.0, 0.0, 0.0], [40.0, 0.0, 0.0], [10.0, 0.0, 0.0]], np.float32)
+    assert oracle_mod.de94(g1, g2).tolist() == [30.0, 0.0, 30.0]
+    # chroma only, same hue: dE94 = |dC| / (1 + 0.045 C_ref)
+    r = np.array([[50.0, 40.0, 0.0]], np.float32)
+    x = np.array([[50.0, 10.0, 0.0]], np.float32)
+    assert oracle_mod.de94(r, x)[0] == pytest.approx(30.0 / (1 + 0.045 * 40.0), rel=1e-6)
+    # hue only at equal chroma: dE94 = |dH| / (1 + 0.015 C)
+    r = np.array([[50.0, 30.0, 0.0]], np.float32)
+    x = np.array([[50.0, 0.0, 30.0]], np.float32)
+    assert oracle_mod.de94(r, x)[0] == pytest.approx(np.sqrt(2 * 30.0 ** 2) / (1 + 0.015 * 30.0), rel=1e-5)
+
+
+def _run(oracle_mod, spec, bias, frames):
+    p = oracle_mod.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED,
+                                  bias_mode=bias)
+    o = oracle_mod.Oracle(spec.width, spec.height, spec.k, p)
+    for (c, lev, gx, gy) in frames:
+        o.push(c, lev, gx, gy)
+    return o
+
+
+def test_eq7_reduces_to_eq6_when_colours_do_not_change(oracle_mod):
+    """Every frame offers each pixel the same colour (stationary gaze, static scene): dL = 0 and
+    Eq. 7 equals Eq. 6 bit for bit, slot by slot."""
+    spec = synth.StreamSpec(64, 48, 4, 12, 8.0, 20.0, 1.0, 4, 3.0)
+    src = synth.FrameSource(spec, gaze=np.tile(np.array([[20.3, 30.6]], np.float32), (12, 1)))
+    frames = [(c.numpy(), l.numpy(), gx, gy) for (c, l, gx, gy) in src]
+    full = _run(oracle_mod, spec, oracle_mod.BIAS_FULL, frames).state()
+    bern = _run(oracle_mod, spec, oracle_mod.BIAS_BERNOULLI, frames).state()
+    np.testing.assert_array_equal(full.idx, bern.idx)
+    np.testing.assert_array_equal(full.wt, bern.wt)
+    np.testing.assert_array_equal(full.col, bern.col)
+    np.testing.assert_array_equal(full.wslot, bern.wslot)
+
+
+def test_eq7_saturated_difference_always_replaces(oracle_mod):
+    """Black and white frames alternate: dE94 = 100, |dL| = 1, the biased sum is 0 and every slot
+    takes every new frame."""
+    spec = synth.StreamSpec(16, 8, 3, 6, 2.0, 5.0, 0.0, 100, 0.0)
+    lev = np.full((8, 16), 2, np.uint8)
+    frames = [(np.full((8, 16, 3), float(t % 2), np.float32), lev, 7.0, 3.0) for t in range(6)]
+    st = _run(oracle_mod, spec, oracle_mod.BIAS_FULL, frames).state()
+    assert np.all(st.idx == 5)
+    np.testing.assert_array_equal(st.wslot, st.wt)      # W1' = 0, so w_sum = w
+
+
+def test_eq7_partial_difference_follows_the_product_law(oracle_mod):
+    """One pixel, constant w = 1, colours alternating between two greys whose L* differ by d:
+    with k = 1 the slot's sample alternates, but the sum obeys W' = W (1 - |dL|)(1 - 1/(W + 1)) + 1
+    whenever the slot holds the other grey -- checked frame by frame from the trials' final sums."""
+    grey = lambda v: np.array([v, v, v], np.float32)
+    a, b = grey(0.2), grey(0.3)
+    la, lb = oracle_mod.lab(np.stack([a, b]))[:, 0].astype(np.float64)
+    d = abs(la - lb) / 100.0
+    p = oracle_mod.default_params(8, fovea_radius_px=100.0, bias_mode=oracle_mod.BIAS_FULL)
+    # two frames: frame 0 fills the slot with a, frame 1 offers b -> one biased step
+    rgb = np.stack([a, b])
+    idx, wsum = oracle_mod.trials(8, 8, 1, p, 1, 1, 0, 1, rgb, np.zeros(2, np.uint8),
+                                  np.array([[1.5, 1.5]] * 2, np.float32))
+    W = 1.0
+    expected = W * (1 - d) * (1 - 1 / (W + 1)) + 1
+    assert abs(float(wsum[0]) - expected) < 1e-5
+
+
+def test_eq7_difference_is_clamped_to_one(oracle_mod):
+    """Bright (HDR) and black frames alternate: dE94 = L* of the bright grey > 100, |dL| clamps to 1,
+    so the biased sum is exactly 0 and the stored sum is the new weight."""
+    spec = synth.StreamSpec(16, 8, 2, 5, 2.0, 5.0, 0.0, 100, 0.0)
+    lev = np.full((8, 16), 2, np.uint8)
+    frames = [(np.full((8, 16, 3), 4.0 * (t % 2), np.float32), lev, 7.0, 3.0) for t in range(5)]
+    st = _run(oracle_mod, spec, oracle_mod.BIAS_FULL, frames).state()
+    assert np.all(st.idx == 4)
+    np.testing.assert_array_equal(st.wslot, st.wt)
