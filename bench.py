@@ -12,8 +12,9 @@ fused kernel (algorithmic bytes per pixel-update 33 + 16k + 20 r, with r the
 slot replacements per pixel-update counted by the kernel, over its average
 launch time from HIP events on its stream), and the CPU oracle timed on a
 bounded sample of the same workload.  The same frames are then run through
-the incremental entry point (output rewritten only where a slot changed),
-reported in its own object with its own byte model.
+the incremental entry point (output rewritten only where a slot changed) and
+through the full temporal bias of Eq. 7 (per-slot w_sum, CIE94 colour
+difference), each reported in its own object with its own byte model.
 """
 from __future__ import annotations
 
@@ -48,6 +49,13 @@ def bytes_per_update_incremental(k: int, rbar: float, changed: float) -> float:
     the record read and the output written (12 + 16 k + 12) only at the fraction `changed` of
     pixel-updates where some slot was replaced; 20 bytes per replaced slot."""
     return 9.0 + changed * (24.0 + 16.0 * k) + 20.0 * rbar
+
+
+def bytes_per_update_eq7(k: int, rbar: float) -> float:
+    """Same for the fused pass under Eq. 7: colour in (12, every pixel compares it with its
+    slots), level (1), each slot's own w_sum read and written (8 k), every slot's record read
+    (16 k), output (12) and 20 bytes per replaced slot."""
+    return 25.0 + 24.0 * k + 20.0 * rbar
 
 
 def kernel_source_hash() -> str:
@@ -249,6 +257,7 @@ def main() -> int:
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y override")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth reference")
     ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-resolve run")
+    ap.add_argument("--no-eq7", action="store_true", help="skip the Eq. 7 (full temporal bias) run")
     ap.add_argument("--no-multistream", action="store_true", help="skip the batched-vs-plain runs")
     ap.add_argument("--ring", type=int, default=48, help="distinct frames per stream kept resident (multistream)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving runs")
@@ -339,6 +348,32 @@ def main() -> int:
                                     "changed_pixel_fraction": i_changed_frac}}
         log(f"incremental: {inc_ms / n_inc:.4f} ms/frame")
 
+    eq7 = None
+    if not args.no_eq7:
+        pf = fwrs.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED,
+                                 bias_mode=fwrs.BIAS_FULL)
+        full = fwrs.Reservoir(spec.width, spec.height, spec.k, pf, stream=stream)
+        if tile:
+            full.set_tile(*tile)
+        for t in range(min(W, 8)):
+            full.step(*frames[t], out)
+        full.reset()
+        f_ms, f_per = timed_run(full, frames, out, stream, full.step)
+        f_takes, f_changed, f_updates = full.stats()
+        full.close()
+        f_rbar = f_takes / f_updates
+        f_B = bytes_per_update_eq7(spec.k, f_rbar)
+        f_kern = float(f_per.mean())
+        f_ach = spec.pixels * f_B / (f_kern / 1e3) / 1e9
+        eq7 = {"entry": "fwrs_push_frame_resolve (FWRS_BIAS_FULL)", "frames": K, "ms_per_step": f_ms / K,
+               "value": spec.pixels * K / (f_ms / 1e3) / 1e9, "unit": "Gpixel-updates/s",
+               "ms_per_frame_p50": float(np.percentile(f_per, 50)),
+               "ms_per_frame_p99": float(np.percentile(f_per, 99)),
+               "hbm": {"achieved": f_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": f_ach / HBM_PEAK_GBPS,
+                       "kernel_ms_avg": f_kern, "bytes_per_pixel_update": f_B,
+                       "slot_takes_per_pixel_update": f_rbar}}
+        log(f"eq7: {f_ms / K:.4f} ms/frame")
+
     copy_gbps = None if args.no_copy else copy_bandwidth(torch, dev)
 
     host = [(c.cpu().numpy(), lev.cpu().numpy(), gx, gy) for (c, lev, gx, gy) in frames[:args.cpu_frames]]
@@ -397,6 +432,7 @@ def main() -> int:
         "ms_per_frame_p99": float(np.percentile(per, 99)),
         "pixels_changed_per_pixel_update": changed / updates,
         "incremental": incremental,
+        "eq7": eq7,
         "multistream": multi,
         "serving": served,
         "copy_gbps": copy_gbps,

@@ -66,6 +66,12 @@ extern "C" {
 /* ---- temporal bias modes (Sec. 4.2) ------------------------------------- */
 #define FWRS_BIAS_NONE 0u       /* plain Alg. 2: R1.w_sum is not biased */
 #define FWRS_BIAS_BERNOULLI 1u  /* Eq. 6: R1.w_sum *= 1 - w / (R1.w_sum + w) */
+/* Eq. 7: every slot keeps its own w_sum, which is scaled by (1 - |dL|) and
+ * then by Eq. 6's factor before the slot's Alg. 2 decision; |dL| =
+ * min(1, dE94 / 100) with dE94 the CIE94 difference (graphic-arts weights) in
+ * CIE Lab (D65 white, linear sRGB primaries) between the slot's sample
+ * (reference) and the new pixel. */
+#define FWRS_BIAS_FULL 2u
 
 /* Largest slot count per pixel. */
 #define FWRS_MAX_K 16
@@ -97,14 +103,16 @@ typedef struct fwrs_ctx fwrs_ctx;
 
 /* Device-side view of a context's reservoir store.  N = width * height,
  * p = y * width + x.
- *   wsum[p]                  float32  w_sum of the pixel's reservoir (Alg. 2)
+ *   wsum[p]                  float32  w_sum of the pixel's reservoir (Alg. 2);
+ *                                     under FWRS_BIAS_FULL wsum[p*k + j] is
+ *                                     slot j's own w_sum (wsum_slots = k)
  *   rec[(p*k + j)*4 + 0]     float32  render-time weight of slot j's sample
  *   rec[(p*k + j)*4 + 1..3]  float32  its colour (r, g, b)
  *   idx[p*k + j]             uint32   frame index of slot j's sample
  *                                     (0xFFFFFFFF while empty)
  * A pixel's k slots are one contiguous 16k-byte record, so a replacement
- * touches only that pixel's record.  `pitch` (>= N, a multiple of 64) is the
- * element count reserved for the wsum plane.  Alg. 2's candidate count m is
+ * touches only that pixel's record.  `pitch` (>= N, a multiple of 64) times
+ * `wsum_slots` is the element count reserved for the wsum plane.  Alg. 2's candidate count m is
  * the same for every pixel -- each pixel receives one candidate per frame --
  * so it is frame_index and has no plane.  The pointers are owned by the
  * context (or by the caller's arena). */
@@ -115,6 +123,7 @@ typedef struct fwrs_state_view {
     float* wsum;
     float* rec;
     uint32_t* idx;
+    int wsum_slots;         /* 1, or k under FWRS_BIAS_FULL */
 } fwrs_state_view;
 
 /* Fills `p` with the defaults for an image `width` pixels wide: seed 0,
@@ -123,13 +132,18 @@ typedef struct fwrs_state_view {
 int fwrs_default_params(int width, fwrs_params* p);
 
 /* Device bytes of the reservoir store for a width x height image with k
- * slots: 4 * pitch * (1 + 5k) plus a small statistics area, where pitch is
- * width * height rounded up to 64 (20 bytes per slot and 4 per pixel).  Use
- * it for admission control and to size a caller-provided arena.  Returns 0
- * for invalid sizes. */
+ * slots under FWRS_BIAS_NONE or FWRS_BIAS_BERNOULLI: 4 * pitch * (1 + 5k)
+ * plus a small statistics area, where pitch is width * height rounded up to
+ * 64 (20 bytes per slot and 4 per pixel).  Use it for admission control and
+ * to size a caller-provided arena.  Returns 0 for invalid sizes. */
 size_t fwrs_state_bytes(int width, int height, int k);
 
-/* Host bytes written by fwrs_download_state: width * height * (8 + 20k). */
+/* As fwrs_state_bytes for a given bias mode: FWRS_BIAS_FULL keeps one w_sum
+ * per slot, 4 * pitch * 6k plus the statistics area.  Returns 0 for invalid
+ * sizes or an unknown mode. */
+size_t fwrs_state_bytes_mode(int width, int height, int k, uint32_t bias_mode);
+
+/* Host bytes written by fwrs_download_state: width * height * (8 + 24k). */
 size_t fwrs_state_host_bytes(int width, int height, int k);
 
 /* Creates a context with fwrs_default_params(width) on the null stream of the
@@ -141,7 +155,8 @@ int fwrs_create(int width, int height, int k, fwrs_ctx** out);
 
 /* As fwrs_create with explicit parameters, a borrowed HIP stream (hipStream_t,
  * NULL = null stream) and an optional caller-owned device arena of
- * `arena_bytes` >= fwrs_state_bytes(width, height, k) bytes, aligned to 256
+ * `arena_bytes` >= fwrs_state_bytes_mode(width, height, k, params->bias_mode)
+ * bytes, aligned to 256
  * bytes, that the library uses for the store and never frees.  With arena ==
  * NULL the library allocates.  The arena is cleared on the stream.
  * FWRS_E_ARG also for: params NULL, fov_deg or fovea_radius_px not finite and
@@ -165,7 +180,9 @@ int fwrs_reset(fwrs_ctx* ctx);
  * eccentricity to (gaze_x, gaze_y) (Eq. 3-4; level 0 scores 1), bias of the
  * pixel's w_sum by Eq. 6 (BERNOULLI), then Alg. 2 per slot: the slot takes
  * (color, w, frame index) when u * (W1' + w) > W1', and w_sum <- W1' + w,
- * m <- m + 1.  Then the frame index advances by 1.
+ * m <- m + 1.  Under FWRS_BIAS_FULL each slot runs the same test on its own
+ * w_sum, biased by Eq. 7 against its own sample.  Then the frame index
+ * advances by 1.
  * FWRS_E_ARG: NULL pointers, non-finite gaze.  Level values above 2 are
  * treated like 2 (reduced resolution).  FWRS_E_STATE: 2^32 - 1 frames pushed. */
 int fwrs_push_frame(fwrs_ctx* ctx, const float* color, const uint8_t* level_map, float gaze_x, float gaze_y);
@@ -199,7 +216,9 @@ int fwrs_get_state(const fwrs_ctx* ctx, fwrs_state_view* view);
 
 /* Synchronises the stream and copies the store to host memory, packed
  * without padding in the order wsum[N], cnt[N], wt[k][N], idx[k][N],
- * col[k][3][N] (N = width * height; cnt[p] = m = frame_index).  `host_bytes` must equal
+ * col[k][3][N], wslot[k][N] (N = width * height; cnt[p] = m = frame_index;
+ * wslot[j][p] = slot j's w_sum: its own under FWRS_BIAS_FULL, where wsum[p]
+ * is 0, else wsum[p] for every j).  `host_bytes` must equal
  * fwrs_state_host_bytes(...). */
 int fwrs_download_state(fwrs_ctx* ctx, void* host, size_t host_bytes);
 

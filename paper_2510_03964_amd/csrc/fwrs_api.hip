@@ -43,7 +43,8 @@ bool params_ok(const fwrs_params* p)
 {
     if (!p) return false;
     if (!finite_pos(p->fov_deg) || !finite_pos(p->fovea_radius_px)) return false;
-    if (p->bias_mode != FWRS_BIAS_NONE && p->bias_mode != FWRS_BIAS_BERNOULLI) return false;
+    if (p->bias_mode != FWRS_BIAS_NONE && p->bias_mode != FWRS_BIAS_BERNOULLI && p->bias_mode != FWRS_BIAS_FULL)
+        return false;
     if (!(p->a_k > 0.0f && p->a_k <= 1.0f)) return false;
     return finite_pos(p->r_m) && finite_pos(p->r2k) && finite_pos(p->rek);
 }
@@ -104,6 +105,7 @@ struct fwrs_ctx {
     void* arena = nullptr;
     bool owns_arena = false;
     size_t pitch = 0;
+    size_t wsum_slots = 1;   // 1: one w_sum per pixel; k under Eq. 7 (one per slot)
     float* wsum = nullptr;
     float* rec = nullptr;
     uint32_t* idx = nullptr;
@@ -125,7 +127,8 @@ int clear_store(fwrs_ctx* x)
 {
     const size_t P = x->pitch, k = (size_t)x->k;
     // wsum and the slot records are contiguous and start out zero; idx starts empty.
-    if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->wsum), P * (1 + 4 * k), 0u, x->stream) != hipSuccess)
+    if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->wsum), P * (x->wsum_slots + 4 * k), 0u, x->stream) !=
+        hipSuccess)
         return FWRS_E_HIP;
     if (fwrs::launch_fill_u32(x->idx, P * k, 0xFFFFFFFFu, x->stream) != hipSuccess) return FWRS_E_HIP;
     if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->stats), kStatBytes / 4, 0u, x->stream) != hipSuccess)
@@ -215,16 +218,23 @@ int fwrs_default_params(int width, fwrs_params* p)
     return FWRS_OK;
 }
 
-size_t fwrs_state_bytes(int width, int height, int k)
+size_t fwrs_state_bytes_mode(int width, int height, int k, uint32_t bias_mode)
 {
     if (!sizes_ok(width, height, k)) return 0;
-    return 4 * pitch_for(width, height) * (1 + 5 * (size_t)k) + kStatBytes;
+    if (bias_mode != FWRS_BIAS_NONE && bias_mode != FWRS_BIAS_BERNOULLI && bias_mode != FWRS_BIAS_FULL) return 0;
+    const size_t wslots = bias_mode == FWRS_BIAS_FULL ? (size_t)k : 1;
+    return 4 * pitch_for(width, height) * (wslots + 5 * (size_t)k) + kStatBytes;
+}
+
+size_t fwrs_state_bytes(int width, int height, int k)
+{
+    return fwrs_state_bytes_mode(width, height, k, FWRS_BIAS_BERNOULLI);
 }
 
 size_t fwrs_state_host_bytes(int width, int height, int k)
 {
     if (!sizes_ok(width, height, k)) return 0;
-    return (size_t)width * (size_t)height * (8 + 20 * (size_t)k);
+    return (size_t)width * (size_t)height * (8 + 24 * (size_t)k);
 }
 
 int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void* hip_stream, void* arena,
@@ -232,7 +242,7 @@ int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void
 {
     if (!out || !sizes_ok(width, height, k) || !params_ok(params)) return FWRS_E_ARG;
     *out = nullptr;
-    const size_t need = fwrs_state_bytes(width, height, k);
+    const size_t need = fwrs_state_bytes_mode(width, height, k, params->bias_mode);
     if (arena && (arena_bytes < need || !aligned(arena, 256))) return FWRS_E_ARG;
     fwrs_ctx* x = new (std::nothrow) fwrs_ctx();
     if (!x) return FWRS_E_NOMEM;
@@ -244,6 +254,7 @@ int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void
     x->c = derive(*params, width);
     x->stream = (hipStream_t)hip_stream;
     x->pitch = pitch_for(width, height);
+    x->wsum_slots = params->bias_mode == FWRS_BIAS_FULL ? (size_t)k : 1;
     if (arena) {
         x->arena = arena;
     } else {
@@ -255,11 +266,12 @@ int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void
         x->owns_arena = true;
     }
     const size_t P = x->pitch, kk = (size_t)k;
+    const size_t ws = x->wsum_slots;
     float* base = static_cast<float*>(x->arena);
     x->wsum = base;
-    x->rec = base + P;
-    x->idx = reinterpret_cast<uint32_t*>(base + (1 + 4 * kk) * P);
-    x->stats = reinterpret_cast<unsigned long long*>(base + (1 + 5 * kk) * P);
+    x->rec = base + ws * P;
+    x->idx = reinterpret_cast<uint32_t*>(base + (ws + 4 * kk) * P);
+    x->stats = reinterpret_cast<unsigned long long*>(base + (ws + 5 * kk) * P);
     const int rc = clear_store(x);
     if (rc != FWRS_OK) {
         if (x->owns_arena) (void)hipFree(x->arena);
@@ -350,6 +362,7 @@ int fwrs_get_state(const fwrs_ctx* x, fwrs_state_view* v)
     v->k = x->k;
     v->frame_index = x->t;
     v->pitch = x->pitch;
+    v->wsum_slots = (int)x->wsum_slots;
     v->wsum = x->wsum;
     v->rec = x->rec;
     v->idx = x->idx;
@@ -362,11 +375,13 @@ int fwrs_download_state(fwrs_ctx* x, void* host, size_t host_bytes)
     DeviceGuard g(x->device);
     if (!g.ok) return FWRS_E_HIP;
     const size_t N = (size_t)x->width * (size_t)x->height, k = (size_t)x->k;
-    std::vector<float> rec;
+    const size_t ws = x->wsum_slots;
+    std::vector<float> rec, sums;
     std::vector<uint32_t> idx;
     try {
         rec.resize(N * k * 4);
         idx.resize(N * k);
+        sums.resize(N * ws);
     } catch (const std::bad_alloc&) {
         return FWRS_E_NOMEM;
     }
@@ -376,13 +391,20 @@ int fwrs_download_state(fwrs_ctx* x, void* host, size_t host_bytes)
     float* wt = reinterpret_cast<float*>(h + 8 * N);
     uint32_t* hidx = reinterpret_cast<uint32_t*>(h + (8 + 4 * k) * N);
     float* col = reinterpret_cast<float*>(h + (8 + 8 * k) * N);
-    if (hipMemcpyAsync(wsum, x->wsum, 4 * N, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
+    float* wslot = reinterpret_cast<float*>(h + (8 + 20 * k) * N);
+    if (hipMemcpyAsync(sums.data(), x->wsum, 4 * N * ws, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
         hipMemcpyAsync(rec.data(), x->rec, 16 * N * k, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
         hipMemcpyAsync(idx.data(), x->idx, 4 * N * k, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
         hipStreamSynchronize(x->stream) != hipSuccess)
         return FWRS_E_HIP;
     // every pixel has seen one candidate per frame: m = frame count
     for (size_t p = 0; p < N; ++p) cnt[p] = x->t;
+    // per-slot sums [k][N]: Eq. 7's own ([N][k] on the device; the shared
+    // w_sum is then 0), else the shared w_sum repeated for every slot
+    const bool per_slot = x->prm.bias_mode == FWRS_BIAS_FULL;
+    for (size_t p = 0; p < N; ++p) wsum[p] = per_slot ? 0.0f : sums[p];
+    for (size_t j = 0; j < k; ++j)
+        for (size_t p = 0; p < N; ++p) wslot[j * N + p] = per_slot ? sums[p * k + j] : sums[p];
     // device records [N][k]{w, r, g, b} -> packed planes wt[k][N], idx[k][N], col[k][3][N]
     for (size_t p = 0; p < N; ++p)
         for (size_t j = 0; j < k; ++j) {

@@ -32,7 +32,7 @@ struct alignas(8) FrameDesc {
     const float* color;         // [H][W][3] f32, the new candidates
     const uint8_t* level;       // [H][W] u8 foveation level
     float* out;                 // [H][W][3] f32 resolve target (null for update-only)
-    float* wsum;                // [N] w_sum per pixel
+    float* wsum;                // [N] w_sum per pixel; [N][k] per slot under Eq. 7
     float* rec;                 // [N][k][4] slot records {w, r, g, b}
     uint32_t* idx;              // [N][k] frame index of each slot's sample
     unsigned long long* stats;  // [kStatSlots][2] counters (slots replaced, pixels changed), or null
@@ -48,6 +48,7 @@ constexpr int kTickFrames = 24;         // frames per batched launch (descriptor
 constexpr int kStatSlots = 1024;        // spread of the slot-take counters
 constexpr uint32_t kBiasNone = 0u;
 constexpr uint32_t kBiasBernoulli = 1u;
+constexpr uint32_t kBiasFull = 2u;      // Eq. 7: per-slot w_sum scaled by (1 - |dL|) and Eq. 6
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11).  Counter (x0..x3),
@@ -151,6 +152,69 @@ __device__ __forceinline__ float bias_eq6(float W1, float w, uint32_t mode)
     const float q = w / total;
     const float survive = 1.0f - q;
     return mode == kBiasBernoulli ? W1 * survive : W1;
+}
+
+// ---------------------------------------------------------------------------
+// Eq. 7's colour difference: both colours (linear RGB, sRGB primaries) to CIE
+// Lab (D65 white), then the CIE94 difference with graphic-arts weights and the
+// reservoir sample as the reference; |dL| = min(1, dE94 / 100).
+// ---------------------------------------------------------------------------
+// Cube root, t > 0: exponent-bit seed (bits(t^(1/3)) ~ bits(t)/3 + 2/3 * 127 * 2^23)
+// refined by four Newton steps y <- y - (y^3 - t) / (3 y^2).
+__device__ __forceinline__ float cube_root(float t)
+{
+    float y = __uint_as_float(__float_as_uint(t) / 3u + 0x2A555555u);
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const float y2 = y * y;
+        const float y3 = y2 * y;
+        const float num = y3 - t;
+        const float den = 3.0f * y2;
+        y = y - num / den;
+    }
+    return y;
+}
+
+__device__ __forceinline__ float lab_curve(float t)
+{
+    // t^(1/3) above (6/29)^3, the linear segment t / (3 (6/29)^2) + 4/29 below
+    const float lin = t * (841.0f / 108.0f) + 4.0f / 29.0f;
+    return t > 216.0f / 24389.0f ? cube_root(t) : lin;
+}
+
+__device__ __forceinline__ float3 rgb_to_lab(float r, float g, float b)
+{
+    const float X = (0.4124564f * r + 0.3575761f * g) + 0.1804375f * b;
+    const float Y = (0.2126729f * r + 0.7151522f * g) + 0.0721750f * b;
+    const float Z = (0.0193339f * r + 0.1191920f * g) + 0.9503041f * b;
+    const float fx = lab_curve(X / 0.95047f);
+    const float fy = lab_curve(Y);
+    const float fz = lab_curve(Z / 1.08883f);
+    return make_float3(116.0f * fy - 16.0f, 500.0f * (fx - fy), 200.0f * (fy - fz));
+}
+
+__device__ __forceinline__ float cie94(const float3& ref, const float3& x)
+{
+    const float dL = ref.x - x.x;
+    const float C1 = sqrtf(ref.y * ref.y + ref.z * ref.z);
+    const float C2 = sqrtf(x.y * x.y + x.z * x.z);
+    const float dC = C1 - C2;
+    const float da = ref.y - x.y;
+    const float db = ref.z - x.z;
+    const float dH2 = fmaxf((da * da + db * db) - dC * dC, 0.0f);
+    const float SC = 1.0f + 0.045f * C1;
+    const float SH = 1.0f + 0.015f * C1;
+    const float tC = dC / SC;
+    return sqrtf((dL * dL + tC * tC) + dH2 / (SH * SH));
+}
+
+// Eq. 7: (W1 (1 - |dL|)) (1 - w / (W1 + w)).
+__device__ __forceinline__ float bias_eq7(float W1, float w, float dl)
+{
+    const float total = W1 + w;
+    const float q = w / total;
+    const float survive = 1.0f - q;
+    return (W1 * (1.0f - dl)) * survive;
 }
 
 }  // namespace fwrs

@@ -18,7 +18,8 @@
 //
 // Per pixel and frame (Sec. 4.1-4.2 of the paper):
 //   w    = Eq. 4 weight from the eccentricity to the gaze (level 0 -> 1)
-//   W1'  = Eq. 6 biased w_sum (BERNOULLI) or w_sum (NONE)
+//   W1'  = Eq. 6 biased w_sum (BERNOULLI) or w_sum (NONE); under FULL every
+//          slot has its own w_sum, biased by Eq. 7 against its own sample
 //   slot j takes (colour, w, t) when u_j * (W1' + w) > W1'   (Alg. 2)
 //   w_sum <- W1' + w
 //   out  = sum_j wt_j col_j / sum_j wt_j                      (resolve)
@@ -249,10 +250,108 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
 }
 
 // ---------------------------------------------------------------------------
+// One pixel under Eq. 7 (bias mode FULL): every slot keeps its own w_sum,
+// wslot[p * k + j], biased by the slot's colour difference to the new pixel
+// before its Alg. 2 decision.  Needs the new colour for every pixel (each slot
+// compares against it) and every slot's colour, so the records are read by
+// every op that updates.  Same store layout otherwise.
+// ---------------------------------------------------------------------------
+template <int K, int OP>
+__device__ __forceinline__ uint32_t pixel_eq7(const FrameDesc& d, uint32_t x, uint32_t y)
+{
+    const uint32_t p = y * d.width + x;
+    const int kk = K ? K : (int)d.k;
+    constexpr int R = K ? K : 1;
+    constexpr bool kUpdates = OP == kPush || OP == kFused || OP == kIncremental;
+    constexpr bool kResolves = OP == kFused || OP == kIncremental;
+    float4* rec = reinterpret_cast<float4*>(d.rec) + (size_t)p * (size_t)kk;
+    uint32_t* idx = d.idx + (size_t)p * (size_t)kk;
+    float* wslot = d.wsum + (size_t)p * (size_t)kk;
+
+    // every slot's record and sum up front (K > 0), then the pixel's own inputs
+    float4 r[R];
+    float W[R];
+    if (K) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) r[j] = ld4<kNtRecLd>(rec + j);
+        if (K % 4 == 0) {
+#pragma unroll
+            for (int j = 0; j < R; j += 4) {
+                const float4 v = ld4<kNtWsumLd>(reinterpret_cast<const float4*>(wslot + j));
+                W[j] = v.x;
+                W[(j + 1) % R] = v.y;
+                W[(j + 2) % R] = v.z;
+                W[(j + 3) % R] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) W[j] = ld<kNtWsumLd>(wslot + j);
+        }
+    }
+    const uint32_t lv = ld<kNtLevel>(d.level + p);
+    const float* color = d.color + 3 * (size_t)p;
+    const float c0 = ld<kNtColor>(color + 0);
+    const float c1 = ld<kNtColor>(color + 1);
+    const float c2 = ld<kNtColor>(color + 2);
+    const float dx = ((float)x + 0.5f) - d.gx;
+    const float dy = ((float)y + 0.5f) - d.gy;
+    const float w = weight_eq4(d.c, dx * dx + dy * dy, lv);
+    const float3 lab_new = rgb_to_lab(c0, c1, c2);
+    const float4 fresh = make_float4(w, c0, c1, c2);
+
+    float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    uint32_t tk = 0u;
+    uint4 words = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int j = 0; j < kk; ++j) {
+        float4 v = K ? r[K ? j : 0] : ld4<kNtRecLd>(rec + j);
+        const float W1 = K ? W[K ? j : 0] : ld<kNtWsumLd>(wslot + j);
+        if ((j & 3) == 0) words = philox4x32_10(p, d.t, (uint32_t)(j >> 2), 0u, d.seed, d.stream_id);
+        const uint32_t word = (j & 3) == 0 ? words.x : (j & 3) == 1 ? words.y : (j & 3) == 2 ? words.z : words.w;
+        // Eq. 7 against this slot's sample, then the slot's Alg. 2 decision
+        const float dl = fminf(1.0f, cie94(rgb_to_lab(v.y, v.z, v.w), lab_new) / 100.0f);
+        const float W1b = bias_eq7(W1, w, dl);
+        const float s = W1b + w;
+        if (unit_variate(word) * s > W1b) {
+            tk |= 1u << j;
+            v = fresh;
+            st4<kNtRecSt>(rec + j, fresh);
+            st<kNtIdxSt>(idx + j, d.t);
+        }
+        if (K) W[K ? j : 0] = s;
+        else st<kNtWsumSt>(wslot + j, s);
+        S = S + v.x;
+        a0 = a0 + v.x * v.y;
+        a1 = a1 + v.x * v.z;
+        a2 = a2 + v.x * v.w;
+    }
+    if (K) {
+        if (K % 4 == 0) {
+#pragma unroll
+            for (int j = 0; j < R; j += 4)
+                st4<kNtWsumSt>(reinterpret_cast<float4*>(wslot + j),
+                               make_float4(W[j], W[(j + 1) % R], W[(j + 2) % R], W[(j + 3) % R]));
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) st<kNtWsumSt>(wslot + j, W[j]);
+        }
+    }
+    if (kResolves && (OP != kIncremental || tk)) {
+        const float rs = S > 0.0f ? 1.0f / S : 0.0f;
+        float* o = d.out + 3 * (size_t)p;
+        st<kNtOut>(o + 0, a0 * rs);
+        st<kNtOut>(o + 1, a1 * rs);
+        st<kNtOut>(o + 2, a2 * rs);
+    }
+    static_assert(kUpdates, "the resolve-only pass is the same under every bias mode");
+    return __popc(tk) + (tk ? 0x10000u : 0u);
+}
+
+// ---------------------------------------------------------------------------
 // One work item (256 pixels).  The wave index is made explicit as a uniform
 // value so the tile arithmetic runs on the scalar unit.
 // ---------------------------------------------------------------------------
-template <int K, int OP>
+template <int K, int OP, bool EQ7 = false>
 __device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t item)
 {
     const uint32_t tid = threadIdx.x;
@@ -268,6 +367,7 @@ __device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t it
     const uint32_t x = (tx << d.tile_x_log2) + (local & ((1u << d.tile_x_log2) - 1u));
     const uint32_t y = (ty << d.tile_y_log2) + (local >> d.tile_x_log2);
     if (y >= d.height || x >= d.width) return 0u;
+    if constexpr (EQ7) return pixel_eq7<K, OP>(d, x, y);
     return pixel<K, OP>(d, x, y);
 }
 
@@ -284,10 +384,10 @@ __device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t v)
     }
 }
 
-template <int K, int OP>
+template <int K, int OP, bool EQ7 = false>
 __global__ __launch_bounds__(kBlock) void frame_kernel(FrameDesc d)
 {
-    const uint32_t n = process_item<K, OP>(d, blockIdx.x);
+    const uint32_t n = process_item<K, OP, EQ7>(d, blockIdx.x);
     if ((OP == kPush || OP == kFused || OP == kIncremental) && d.stats) add_stats(d.stats, n);
 }
 
@@ -310,6 +410,11 @@ __global__ __launch_bounds__(kBlock) void tick_kernel(const TickArgs a)
     const FrameDesc& d = a.descs[lo];
     const uint32_t local = item - a.begins[lo];
     uint32_t n;
+    if (d.bias == kBiasFull) {
+        n = process_item<0, kFused, true>(d, local);
+        if (d.stats) add_stats(d.stats, n);
+        return;
+    }
     switch (d.k) {
         case 1: n = process_item<1, kFused>(d, local); break;
         case 2: n = process_item<2, kFused>(d, local); break;
@@ -336,6 +441,16 @@ template <int OP>
 static hipError_t launch_frame_op(const FrameDesc& d, hipStream_t stream)
 {
     const dim3 grid(d.items), block(kBlock);
+    if constexpr (OP != kResolve) {
+        if (d.bias == kBiasFull) {
+            switch (d.k) {
+                case 4: hipLaunchKernelGGL((frame_kernel<4, OP, true>), grid, block, 0, stream, d); break;
+                case 8: hipLaunchKernelGGL((frame_kernel<8, OP, true>), grid, block, 0, stream, d); break;
+                default: hipLaunchKernelGGL((frame_kernel<0, OP, true>), grid, block, 0, stream, d); break;
+            }
+            return hipGetLastError();
+        }
+    }
     switch (d.k) {
         case 1: hipLaunchKernelGGL((frame_kernel<1, OP>), grid, block, 0, stream, d); break;
         case 2: hipLaunchKernelGGL((frame_kernel<2, OP>), grid, block, 0, stream, d); break;

@@ -17,12 +17,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfwrs.so")
 
 OK, E_ARG, E_NOMEM, E_HIP, E_STATE = 0, 1, 2, 3, 4
-BIAS_NONE, BIAS_BERNOULLI = 0, 1
+BIAS_NONE, BIAS_BERNOULLI, BIAS_FULL = 0, 1, 2
 MAX_K = 16
 
 #: every symbol include/fwrs.h declares
 EXPORTS = (
-    "fwrs_default_params", "fwrs_state_bytes", "fwrs_state_host_bytes", "fwrs_create", "fwrs_create_ex",
+    "fwrs_default_params", "fwrs_state_bytes", "fwrs_state_bytes_mode", "fwrs_state_host_bytes", "fwrs_create", "fwrs_create_ex",
     "fwrs_destroy", "fwrs_set_stream", "fwrs_reset", "fwrs_push_frame", "fwrs_resolve",
     "fwrs_push_frame_resolve", "fwrs_push_frame_resolve_incremental", "fwrs_frame_index", "fwrs_get_state", "fwrs_download_state", "fwrs_get_stats",
     "fwrs_set_tile", "fwrs_sync", "fwrs_strerror", "fwrs_engine_create", "fwrs_engine_tick",
@@ -64,6 +64,7 @@ class StateView(C.Structure):
         ("wsum", C.c_void_p),
         ("rec", C.c_void_p),
         ("idx", C.c_void_p),
+        ("wsum_slots", C.c_int),
     ]
 
 
@@ -96,6 +97,7 @@ def load(path: str | None = None):
     sig = {
         "fwrs_default_params": (i, [i, C.POINTER(Params)]),
         "fwrs_state_bytes": (sz, [i, i, i]),
+        "fwrs_state_bytes_mode": (sz, [i, i, i, u32]),
         "fwrs_state_host_bytes": (sz, [i, i, i]),
         "fwrs_create": (i, [i, i, i, C.POINTER(vp)]),
         "fwrs_create_ex": (i, [i, i, i, C.POINTER(Params), vp, vp, sz, C.POINTER(vp)]),
@@ -147,8 +149,11 @@ def default_params(width: int, **overrides) -> Params:
     return p
 
 
-def state_bytes(width: int, height: int, k: int) -> int:
-    return int(load().fwrs_state_bytes(int(width), int(height), int(k)))
+def state_bytes(width: int, height: int, k: int, bias_mode: int | None = None) -> int:
+    """Device bytes of a context's store (``bias_mode`` None: the NONE/BERNOULLI layout)."""
+    if bias_mode is None:
+        return int(load().fwrs_state_bytes(int(width), int(height), int(k)))
+    return int(load().fwrs_state_bytes_mode(int(width), int(height), int(k), int(bias_mode)))
 
 
 def state_host_bytes(width: int, height: int, k: int) -> int:
@@ -176,13 +181,14 @@ class HostState:
     wt: np.ndarray     # [k, H, W] f32
     idx: np.ndarray    # [k, H, W] u32
     col: np.ndarray    # [k, 3, H, W] f32
+    wslot: np.ndarray  # [k, H, W] f32: slot j's w_sum (its own under BIAS_FULL, else wsum)
 
 
 class Reservoir:
     """A context: the k-slot reservoirs of every pixel of a width x height stream.
 
     ``arena`` may be a caller-owned device tensor (uint8, at least
-    ``state_bytes(width, height, k)`` bytes, 256-byte aligned) that holds the
+    ``state_bytes(width, height, k, params.bias_mode)`` bytes, 256-byte aligned) that holds the
     store; otherwise the library allocates it."""
 
     def __init__(self, width: int, height: int, k: int, params: Params | None = None, stream=None, arena=None):
@@ -292,7 +298,8 @@ class Reservoir:
             return a
 
         return HostState(take(np.float32, N, (H, W)), take(np.uint32, N, (H, W)), take(np.float32, k * N, (k, H, W)),
-                         take(np.uint32, k * N, (k, H, W)), take(np.float32, 3 * k * N, (k, 3, H, W)))
+                         take(np.uint32, k * N, (k, H, W)), take(np.float32, 3 * k * N, (k, 3, H, W)),
+                         take(np.float32, k * N, (k, H, W)))
 
     def stats(self) -> tuple[int, int, int]:
         """(slot takes, pixel updates with a take, pixel updates) since creation or reset."""

@@ -53,12 +53,14 @@ def test_struct_layouts_match_header(tmp_path):
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "fwrs.h"\n'
         "int main(void){printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(fwrs_params), sizeof(fwrs_state_view),"
-        " sizeof(fwrs_frame), offsetof(fwrs_frame, out), offsetof(fwrs_state_view, idx)); return 0;}\n")
+        " sizeof(fwrs_frame), offsetof(fwrs_frame, out), offsetof(fwrs_state_view, idx));"
+        " printf(\"%zu %u\\n\", offsetof(fwrs_state_view, wsum_slots), FWRS_BIAS_FULL); return 0;}\n")
     exe = tmp_path / "l"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [C.sizeof(fwrs.Params), C.sizeof(fwrs.StateView), C.sizeof(fwrs.Frame),
-                   fwrs.Frame.out.offset, fwrs.StateView.idx.offset]
+                   fwrs.Frame.out.offset, fwrs.StateView.idx.offset, fwrs.StateView.wsum_slots.offset,
+                   fwrs.BIAS_FULL]
 
 
 def test_default_params_and_sizes():
@@ -68,8 +70,14 @@ def test_default_params_and_sizes():
     assert (p.a_k, p.r2k, p.rek) == (pytest.approx(0.9851), pytest.approx(1.058), pytest.approx(22.14))
     N = 3840 * 2160
     assert fwrs.state_bytes(3840, 2160, 4) == 4 * N * (1 + 20) + 16384      # N is a multiple of 64
-    assert fwrs.state_host_bytes(3840, 2160, 4) == N * (8 + 80)
+    assert fwrs.state_host_bytes(3840, 2160, 4) == N * (8 + 96)
     assert fwrs.state_bytes(13, 7, 3) == 4 * 128 * (1 + 15) + 16384        # pitch rounded up to 64
+    # Eq. 7 keeps one w_sum per slot
+    for mode in (fwrs.BIAS_NONE, fwrs.BIAS_BERNOULLI):
+        assert fwrs.state_bytes(13, 7, 3, mode) == fwrs.state_bytes(13, 7, 3)
+    assert fwrs.state_bytes(3840, 2160, 4, fwrs.BIAS_FULL) == 4 * N * (4 + 20) + 16384
+    assert fwrs.state_bytes(13, 7, 3, fwrs.BIAS_FULL) == 4 * 128 * (3 + 15) + 16384
+    assert fwrs.state_bytes(13, 7, 3, 3) == 0
     for bad in [(0, 5, 4), (5, 0, 4), (5, 5, 0), (5, 5, 17), (65536, 65536, 1)]:
         assert fwrs.state_bytes(*bad) == 0
 
@@ -89,6 +97,10 @@ def test_invalid_arguments_are_rejected_before_any_gpu_work():
     # a caller arena that is too small or misaligned
     assert L.fwrs_create_ex(64, 64, 4, C.byref(p), None, 256, 16, C.byref(h)) == fwrs.E_ARG
     assert L.fwrs_create_ex(64, 64, 4, C.byref(p), None, 4100, 1 << 30, C.byref(h)) == fwrs.E_ARG
+    # an arena sized for the shared-sum layout is too small under Eq. 7
+    q = fwrs.default_params(64)
+    q.bias_mode = fwrs.BIAS_FULL
+    assert L.fwrs_create_ex(64, 64, 4, C.byref(q), None, 256, fwrs.state_bytes(64, 64, 4), C.byref(h)) == fwrs.E_ARG
     assert L.fwrs_push_frame(None, None, None, 0.0, 0.0) == fwrs.E_ARG
     assert L.fwrs_resolve(None, None) == fwrs.E_ARG
     assert L.fwrs_destroy(None) == fwrs.OK

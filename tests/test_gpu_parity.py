@@ -40,6 +40,7 @@ def _compare_state(st, so, where=""):
     np.testing.assert_array_equal(st.wsum.view(np.uint32), so.wsum.view(np.uint32), err_msg=f"wsum {where}")
     np.testing.assert_array_equal(st.wt.view(np.uint32), so.wt.view(np.uint32), err_msg=f"wt {where}")
     np.testing.assert_array_equal(st.col.view(np.uint32), so.col.view(np.uint32), err_msg=f"col {where}")
+    np.testing.assert_array_equal(st.wslot.view(np.uint32), so.wslot.view(np.uint32), err_msg=f"wslot {where}")
 
 
 def _compare_out(out, ref, where=""):
@@ -221,14 +222,15 @@ def test_stats_count_every_slot_replacement(dev):
     assert updates == spec.frames * spec.pixels
 
 
-def test_4k_bands_and_whole_frame_properties(dev):
+@pytest.mark.parametrize("bias", [fwrs.BIAS_BERNOULLI, fwrs.BIAS_FULL])
+def test_4k_bands_and_whole_frame_properties(dev, bias):
     """3840x2160, k = 4, in the launch configuration the benchmark times: bands of rows
     (through the gaze, the periphery and the image edges) against the oracle every few frames,
     and properties that hold at any size over the whole frame."""
     spec = synth.spec_4k()
     n_frames = 24
     src = synth.FrameSource(spec, device=dev, n_frames=n_frames)
-    p, q = _params(spec)
+    p, q = _params(spec, bias)
     res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream())
     orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
     gy0 = int(src.gaze[0, 1])
@@ -252,6 +254,7 @@ def test_4k_bands_and_whole_frame_properties(dev):
                 np.testing.assert_array_equal(st.cnt[sl], so.cnt[sl])
                 np.testing.assert_array_equal(st.wsum[sl].view(np.uint32), so.wsum[sl].view(np.uint32))
                 np.testing.assert_array_equal(st.wt[:, sl].view(np.uint32), so.wt[:, sl].view(np.uint32))
+                np.testing.assert_array_equal(st.wslot[:, sl].view(np.uint32), so.wslot[:, sl].view(np.uint32))
                 _compare_out(o[sl], ref[sl], f"4K rows {y0}-{y1} frame {t}")
             assert np.all(st.cnt == t + 1)
             assert np.all(st.idx <= t)
@@ -353,4 +356,105 @@ def test_engine_rejects_bad_ticks(dev):
     assert r.frame_index == 0
     with pytest.raises(fwrs.FwrsError):
         r.set_tile(3, 8)
+    eng.close()
+
+
+# ---------------------------------------------------------------------------
+# Full temporal bias (Eq. 7): per-slot w_sum and the CIE94 colour difference
+# ---------------------------------------------------------------------------
+def test_eq7_small_workload_every_frame(dev):
+    spec = synth.spec_small()
+    res, _, _ = _run_pair(dev, spec, spec.frames, bias=fwrs.BIAS_FULL)
+    assert res.state_view().wsum_slots == spec.k
+    st = res.download()
+    assert np.all(st.wsum == 0.0)
+
+
+@pytest.mark.parametrize("w,h,k,frames", [
+    (1, 1, 1, 4), (3, 2, 16, 4), (13, 7, 3, 5), (100, 37, 5, 4), (64, 64, 8, 5), (96, 40, 4, 4), (255, 3, 2, 4),
+    (1367, 769, 4, 3),
+])
+def test_eq7_sizes_and_slot_counts(dev, w, h, k, frames):
+    spec = synth.StreamSpec(w, h, k, frames, max(1.0, 0.1 * w), max(2.5, 0.25 * w), 0.2 * w + 0.5, 2, 0.3 * w + 1,
+                            stream_id=k)
+    _run_pair(dev, spec, frames, bias=fwrs.BIAS_FULL)
+
+
+@pytest.mark.parametrize("k", [4, 3, 8])
+def test_eq7_split_and_incremental_equal_fused(dev, k):
+    spec = synth.StreamSpec(160, 96, k, 12, 16.0, 40.0, 3.0, 4, 8.0)
+    _, _, out_f = _run_pair(dev, spec, 12, bias=fwrs.BIAS_FULL, every=4)
+    _, _, out_s = _run_pair(dev, spec, 12, mode="split", bias=fwrs.BIAS_FULL, every=12)
+    _, _, out_i = _run_pair(dev, spec, 12, mode="incremental", bias=fwrs.BIAS_FULL, every=3)
+    assert torch.equal(out_f, out_s)
+    assert torch.equal(out_f, out_i)
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (256, 1)])
+def test_eq7_tile_shape_never_changes_results(dev, tile):
+    spec = synth.StreamSpec(200, 120, 4, 5, 20.0, 50.0, 3.0, 2, 9.0)
+    _run_pair(dev, spec, 5, tile=tile, bias=fwrs.BIAS_FULL)
+
+
+def test_eq7_static_scene_equals_eq6(dev):
+    """A stationary gaze over a static scene offers every pixel the same colour each frame:
+    |dL| = 0, so the per-slot sums equal Eq. 6's shared sum and the samples agree bit for bit."""
+    spec = synth.StreamSpec(128, 72, 4, 10, 8.0, 20.0, 1.0, 4, 3.0)
+    gaze = np.tile(np.array([[40.3, 30.6]], np.float32), (10, 1))
+    outs, states = [], []
+    for bias in (fwrs.BIAS_BERNOULLI, fwrs.BIAS_FULL):
+        src = synth.FrameSource(spec, device=dev, gaze=gaze)
+        res, _, out = _run_pair(dev, spec, 10, bias=bias, every=10, src=src)
+        outs.append(out)
+        states.append(res.download())
+    assert torch.equal(outs[0], outs[1])
+    np.testing.assert_array_equal(states[0].idx, states[1].idx)
+    np.testing.assert_array_equal(states[0].wslot, states[1].wslot)
+
+
+def test_eq7_caller_arena_is_sized_by_mode(dev):
+    spec = synth.StreamSpec(128, 64, 4, 4, 12.0, 30.0, 2.0, 2, 6.0)
+    p, q = _params(spec, fwrs.BIAS_FULL)
+    small = torch.empty(fwrs.state_bytes(spec.width, spec.height, spec.k), dtype=torch.uint8, device=dev)
+    with pytest.raises(fwrs.FwrsError):
+        fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream(), arena=small)
+    arena = torch.full((fwrs.state_bytes(spec.width, spec.height, spec.k, fwrs.BIAS_FULL),), 0xAB,
+                       dtype=torch.uint8, device=dev)
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream(), arena=arena)
+    orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
+    src = synth.FrameSource(spec, device=dev)
+    out = torch.empty((spec.height, spec.width, 3), device=dev)
+    for t in range(4):
+        c, lev, gx, gy = src.frame(t)
+        res.step(c, lev, gx, gy, out)
+        orc.push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+    res.sync()
+    _compare_state(res.download(), orc.state())
+    _compare_out(out.cpu().numpy(), orc.resolve())
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_eq7_engine_mixes_bias_modes(dev, use_graph):
+    """One batched tick over contexts of all three bias modes matches the oracle per context."""
+    specs = _mix_specs()
+    modes = [fwrs.BIAS_FULL, fwrs.BIAS_BERNOULLI, fwrs.BIAS_FULL, fwrs.BIAS_NONE, fwrs.BIAS_FULL]
+    stream = torch.cuda.current_stream()
+    srcs = [synth.FrameSource(s, device=dev) for s in specs]
+    eng = fwrs.Engine(len(specs), stream=stream, use_graph=use_graph)
+    ctxs, orcs, outs = [], [], []
+    for s, m in zip(specs, modes):
+        p, q = _params(s, m)
+        ctxs.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
+        orcs.append(oracle.Oracle(s.width, s.height, s.k, q))
+        outs.append(torch.empty((s.height, s.width, 3), device=dev))
+    for t in range(5):
+        frames = [src.frame(t) for src in srcs]
+        eng.tick([(ctxs[i], *frames[i], outs[i]) for i in range(len(specs))])
+        for i in range(len(specs)):
+            c, lev, gx, gy = frames[i]
+            orcs[i].push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+    torch.cuda.synchronize()
+    for i in range(len(specs)):
+        _compare_state(ctxs[i].download(), orcs[i].state(), f"stream {i} bias {modes[i]}")
+        _compare_out(outs[i].cpu().numpy(), orcs[i].resolve(), f"stream {i}")
     eng.close()
