@@ -98,6 +98,12 @@ def _bind(L):
                                      C.POINTER(C.c_uint8), C.POINTER(C.c_float), C.POINTER(C.c_uint32),
                                      C.POINTER(C.c_float)]
     L.fwrs_oracle_trials.restype = C.c_int
+    L.fwrs_oracle_push_reproject.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_uint8), C.POINTER(C.c_float),
+                                             C.POINTER(C.c_float), C.c_float, C.c_float, C.c_float]
+    L.fwrs_oracle_push_reproject.restype = C.c_int
+    L.fwrs_oracle_depth.argtypes = [vp, C.POINTER(C.c_float)]
+    L.fwrs_oracle_flushes.argtypes = [vp]
+    L.fwrs_oracle_flushes.restype = C.c_uint64
     return L
 
 
@@ -159,6 +165,32 @@ class Oracle:
 
     def advance(self) -> None:
         self._L.fwrs_oracle_advance(self._h)
+
+    def push_reproject(self, color: np.ndarray, level: np.ndarray, motion: np.ndarray, depth: np.ndarray,
+                       gx: float, gy: float, depth_tol: float) -> None:
+        """One frame with reverse reprojection by `motion` ([H, W, 2], pixels, current minus previous
+        position) and the depth-based flush (`depth` [H, W], relative tolerance `depth_tol`)."""
+        color = np.ascontiguousarray(color, dtype=np.float32)
+        level = np.ascontiguousarray(level, dtype=np.uint8)
+        motion = np.ascontiguousarray(motion, dtype=np.float32)
+        depth = np.ascontiguousarray(depth, dtype=np.float32)
+        H, W = self.height, self.width
+        assert color.shape == (H, W, 3) and level.shape == (H, W) and motion.shape == (H, W, 2)
+        assert depth.shape == (H, W)
+        rc = self._L.fwrs_oracle_push_reproject(self._h, _ptr(color, C.c_float), _ptr(level, C.c_uint8),
+                                                _ptr(motion, C.c_float), _ptr(depth, C.c_float), C.c_float(gx),
+                                                C.c_float(gy), C.c_float(depth_tol))
+        if rc != 0:
+            raise MemoryError("oracle reprojection: out of memory")
+
+    def depth(self) -> np.ndarray:
+        out = np.empty((self.height, self.width), np.float32)
+        self._L.fwrs_oracle_depth(self._h, _ptr(out, C.c_float))
+        return out
+
+    @property
+    def flushes(self) -> int:
+        return int(self._L.fwrs_oracle_flushes(self._h))
 
     def resolve(self) -> np.ndarray:
         out = np.empty((self.height, self.width, 3), dtype=np.float64)

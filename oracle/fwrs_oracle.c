@@ -21,6 +21,10 @@
  *                        the combine
  *   Sec. 4.3, Eq. 7      full temporal bias: Eq. 6 additionally scaled by
  *                        (1 - |dL|), dL from the CIE94 colour difference in Lab
+ *   Sec. 4.3             temporal reprojection by motion vectors; a depth
+ *                        disagreement between frames (occlusion or
+ *                        disocclusion) flushes the reservoir's history
+ *                        (Sec. 6: the pixel falls back to the new sample)
  *
  * Precision.  Every quantity that decides which sample a slot keeps (the
  * weight, the biased weight sum, the uniform variate and the comparison) is
@@ -52,6 +56,13 @@
  *     CIE94 difference (graphic-arts weights, the slot's sample as reference)
  *     of the two colours in CIE Lab (D65), the colours read as linear RGB.
  *     The factors apply left to right: (W1 * (1 - |dL|)) * (1 - w / (W1 + w)).
+ *   - reprojection is reverse and nearest: pixel (x, y) continues the
+ *     reservoir of the pixel that contains its centre moved back by its motion
+ *     vector, (floor(x + 0.5 - mx), floor(y + 0.5 - my)); that history is kept
+ *     when the point is inside the image and |depth - previous depth there| <=
+ *     depth_tol * depth, otherwise the pixel starts from an empty reservoir
+ *     (m = 0, w_sum = 0, slots empty) before the frame's update.  Before the
+ *     first reprojected frame no depth exists, so every pixel starts empty.
  */
 #include <math.h>
 #include <stddef.h>
@@ -292,12 +303,14 @@ fwrs_oracle* fwrs_oracle_create(int width, int height, int k, const fwrs_oracle_
     o->idx = (uint32_t*)malloc(n * (size_t)k * sizeof(uint32_t));
     o->col = (float*)calloc(n * (size_t)k * 3, sizeof(float));
     if (o->prm.bias_mode == FWRS_ORACLE_BIAS_FULL) o->wslot = (float*)calloc(n * (size_t)k, sizeof(float));
-    if (!o->wsum || !o->cnt || !o->wt || !o->idx || !o->col ||
+    o->depth = (float*)malloc(n * sizeof(float));
+    if (!o->wsum || !o->cnt || !o->wt || !o->idx || !o->col || !o->depth ||
         (o->prm.bias_mode == FWRS_ORACLE_BIAS_FULL && !o->wslot)) {
         fwrs_oracle_destroy(o);
         return NULL;
     }
     for (size_t i = 0; i < n * (size_t)k; ++i) o->idx[i] = 0xFFFFFFFFu;   /* empty slot */
+    for (size_t i = 0; i < n; ++i) o->depth[i] = NAN;                     /* no previous frame */
     derive_constants(o);
     return o;
 }
@@ -305,7 +318,7 @@ fwrs_oracle* fwrs_oracle_create(int width, int height, int k, const fwrs_oracle_
 void fwrs_oracle_destroy(fwrs_oracle* o)
 {
     if (!o) return;
-    free(o->wsum); free(o->cnt); free(o->wt); free(o->idx); free(o->col); free(o->wslot);
+    free(o->wsum); free(o->cnt); free(o->wt); free(o->idx); free(o->col); free(o->wslot); free(o->depth);
     free(o);
 }
 
@@ -424,6 +437,96 @@ void fwrs_oracle_push(fwrs_oracle* o, const float* color, const uint8_t* level, 
     }
     o->t += 1u;
 }
+
+/* ------------------------------------------------------------------------ */
+/* One frame with camera or object motion (Sec. 4.3).  Reverse reprojection:  */
+/* every pixel looks up where its surface point was in the previous frame     */
+/* (its centre minus its motion vector) and continues the reservoir of the    */
+/* pixel containing that point.  A point outside the previous image, or one   */
+/* whose stored depth disagrees with the current depth (the point was hidden  */
+/* or has just become visible), has no usable history: the reservoir is       */
+/* flushed to the empty state, and the frame's candidate then fills it, so    */
+/* the pixel falls back to plain foveated rendering (Sec. 6).  The frame's    */
+/* update (Eq. 4, the bias, Alg. 2 per slot) follows as in oracle push.       */
+/* Returns 0, or 1 if memory for the new state cannot be allocated.          */
+/* ------------------------------------------------------------------------ */
+int fwrs_oracle_push_reproject(fwrs_oracle* o, const float* color, const uint8_t* level, const float* motion,
+                               const float* depth, float gx, float gy, float depth_tol)
+{
+    const int W = o->width, H = o->height, k = o->k;
+    const size_t n = (size_t)W * (size_t)H;
+    float* wsum = (float*)malloc(n * sizeof(float));
+    uint32_t* cnt = (uint32_t*)malloc(n * sizeof(uint32_t));
+    float* wt = (float*)malloc(n * (size_t)k * sizeof(float));
+    uint32_t* idx = (uint32_t*)malloc(n * (size_t)k * sizeof(uint32_t));
+    float* col = (float*)malloc(n * (size_t)k * 3 * sizeof(float));
+    float* wslot = o->wslot ? (float*)malloc(n * (size_t)k * sizeof(float)) : NULL;
+    float* dnew = (float*)malloc(n * sizeof(float));
+    if (!wsum || !cnt || !wt || !idx || !col || !dnew || (o->wslot && !wslot)) {
+        free(wsum); free(cnt); free(wt); free(idx); free(col); free(wslot); free(dnew);
+        return 1;
+    }
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            const size_t p = (size_t)y * (size_t)W + (size_t)x;
+            /* where this pixel's centre was in the previous frame */
+            const float sx = ((float)x + 0.5f) - motion[2 * p + 0];
+            const float sy = ((float)y + 0.5f) - motion[2 * p + 1];
+            int keep = 0;
+            size_t q = 0;
+            if (sx >= 0.0f && sx < (float)W && sy >= 0.0f && sy < (float)H) {
+                const int qx = (int)floorf(sx);
+                const int qy = (int)floorf(sy);
+                q = (size_t)qy * (size_t)W + (size_t)qx;
+                const float dc = depth[p];
+                const float dp = o->depth[q];
+                /* the same surface within the tolerance; NaN compares false */
+                if (fabsf(dc - dp) <= depth_tol * dc) keep = 1;
+            }
+            if (keep) {
+                wsum[p] = o->wsum[q];
+                cnt[p] = o->cnt[q];
+                for (int j = 0; j < k; ++j) {
+                    wt[(size_t)j * n + p] = o->wt[(size_t)j * n + q];
+                    idx[(size_t)j * n + p] = o->idx[(size_t)j * n + q];
+                    for (int c = 0; c < 3; ++c)
+                        col[((size_t)j * 3 + c) * n + p] = o->col[((size_t)j * 3 + c) * n + q];
+                    if (wslot) wslot[(size_t)j * n + p] = o->wslot[(size_t)j * n + q];
+                }
+            } else {
+                /* flush: the empty reservoir */
+                wsum[p] = 0.0f;
+                cnt[p] = 0u;
+                for (int j = 0; j < k; ++j) {
+                    wt[(size_t)j * n + p] = 0.0f;
+                    idx[(size_t)j * n + p] = 0xFFFFFFFFu;
+                    for (int c = 0; c < 3; ++c) col[((size_t)j * 3 + c) * n + p] = 0.0f;
+                    if (wslot) wslot[(size_t)j * n + p] = 0.0f;
+                }
+                o->flushes += 1u;
+            }
+            dnew[p] = depth[p];
+        }
+    }
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            const size_t p = (size_t)y * (size_t)W + (size_t)x;
+            update_pixel(o, x, y, (uint32_t)p, o->t, color + 3 * p, level[p], gx, gy,
+                         wsum + p, cnt + p, wt + p, idx + p, col + p, wslot ? wslot + p : NULL, n);
+        }
+    }
+    free(o->wsum); free(o->cnt); free(o->wt); free(o->idx); free(o->col); free(o->wslot); free(o->depth);
+    o->wsum = wsum; o->cnt = cnt; o->wt = wt; o->idx = idx; o->col = col; o->wslot = wslot; o->depth = dnew;
+    o->t += 1u;
+    return 0;
+}
+
+void fwrs_oracle_depth(const fwrs_oracle* o, float* depth)
+{
+    memcpy(depth, o->depth, (size_t)o->width * (size_t)o->height * sizeof(float));
+}
+
+uint64_t fwrs_oracle_flushes(const fwrs_oracle* o) { return o->flushes; }
 
 /* Weighted combination of the k slots (the k-slot resolve; at k = 1 it is the
  * paper's output R_out.x).  Binary64 from the stored binary32 values. */

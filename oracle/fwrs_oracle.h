@@ -11,7 +11,11 @@
  *   idx[j * N + p]       uint32, frame index of the sample in slot j
  *                        (0xFFFFFFFF while empty)
  *   col[(j*3 + c)*N + p] binary32, channel c of the sample in slot j
- * Frames are [H][W][3] binary32 (HWC) with a [H][W] uint8 level map.
+ *   depth[p]             binary32, the depth the pixel had in the previous
+ *                        reprojected frame (NaN before the first one)
+ * Frames are [H][W][3] binary32 (HWC) with a [H][W] uint8 level map; motion
+ * vectors are [H][W][2] binary32 in pixels (current minus previous screen
+ * position of the surface point), depth [H][W] binary32 (> 0).
  */
 #ifndef FWRS_ORACLE_H
 #define FWRS_ORACLE_H
@@ -47,6 +51,8 @@ typedef struct fwrs_oracle {
     uint32_t* idx;
     float* col;
     float* wslot;   /* [k][N] per-slot w_sum (BIAS_FULL only; NULL otherwise) */
+    float* depth;   /* [N] previous reprojected frame's depth */
+    uint64_t flushes;   /* reprojected pixel-updates that started from an empty reservoir */
 } fwrs_oracle;
 
 void fwrs_oracle_default_params(int width, fwrs_oracle_params* p);
@@ -61,6 +67,10 @@ uint32_t fwrs_oracle_frame_index(const fwrs_oracle* o);
 void fwrs_oracle_constants(const fwrs_oracle* o, float out[9]);
 void fwrs_oracle_state(const fwrs_oracle* o, float* wsum, uint32_t* cnt, float* wt, uint32_t* idx, float* col);
 void fwrs_oracle_slot_sums(const fwrs_oracle* o, float* wslot);
+int fwrs_oracle_push_reproject(fwrs_oracle* o, const float* color, const uint8_t* level, const float* motion,
+                               const float* depth, float gx, float gy, float depth_tol);
+void fwrs_oracle_depth(const fwrs_oracle* o, float* depth);
+uint64_t fwrs_oracle_flushes(const fwrs_oracle* o);
 
 float fwrs_oracle_cbrt(float t);
 void fwrs_oracle_lab(float r, float g, float b, float lab[3]);

@@ -13,7 +13,11 @@ This module stands in for them with:
   paper's mipmap foveation is equivalent to (Sec. 4.3);
 * a gaze trace: fixation with per-frame Gaussian microsaccade jitter and a
   saccade to a uniform random target with Gaussian landing scatter every P
-  frames (Sec. 2.1.2 describes both eye movements).
+  frames (Sec. 2.1.2 describes both eye movements);
+* for a moving camera (the lateral back-and-forth motion of Sec. 5.3), a
+  panning view of the same procedural scene with a textured foreground disc
+  moving at its own speed in front of it, with per-pixel motion vectors and
+  depth (MovingSource).
 
 It holds none of the reservoir method's arithmetic and is used by both the
 GPU path's callers and the oracle's tests: random numbers come only from
@@ -234,6 +238,130 @@ class FrameSource:
         gx, gy = float(self.gaze[t, 0]), float(self.gaze[t, 1])
         lev = level_map(self.spec, gx, gy, self.device)
         return foveated_frame(self.fs, lev), lev, gx, gy
+
+    def __iter__(self):
+        for t in range(len(self)):
+            yield self.frame(t)
+
+
+# --------------------------------------------------------------------------
+# Moving camera
+# --------------------------------------------------------------------------
+@dataclass(frozen=True)
+class MotionSpec:
+    """Lateral back-and-forth camera motion and one moving occluder (pixels, frames).
+
+    The camera offset is c(t) = pan_amp sin(2 pi t / pan_period): pixel u of
+    frame t shows scene point u + c(t).  A disc of radius disc_radius (depth
+    disc_depth) centred at (W/2 + disc_amp sin(2 pi t / disc_period + 1), 0.55 H)
+    carries its own texture; the background's depth is bg_depth (1 + 0.05
+    sin(2 pi v / H)).  Both periods divide `period`, so frame t and frame
+    t + period are identical and a ring of `period` frames loops seamlessly."""
+
+    pan_amp: float
+    pan_period: int
+    disc_radius: float
+    disc_amp: float
+    disc_period: int
+    disc_depth: float = 3.0
+    bg_depth: float = 10.0
+
+    @property
+    def period(self) -> int:
+        return math.lcm(self.pan_period, self.disc_period)
+
+
+def motion_for(spec: StreamSpec) -> MotionSpec:
+    """Motion scaled by the image width: the pan swings 4% of the width (at 4K up to
+    about 4 px per frame over a 240-frame back-and-forth), the disc (6% of the width
+    in radius) swings 25% of the width over 120 frames."""
+    W = float(spec.width)
+    return MotionSpec(0.04 * W, 240, 0.06 * W, 0.25 * W, 120)
+
+
+def _waves(rng):
+    theta = rng.uniform(0.0, math.pi, size=(3, 8))
+    freq = rng.uniform(0.5, 16.0, size=(3, 8))
+    phase = rng.uniform(0.0, 2.0 * math.pi, size=(3, 8))
+    off = rng.choice([1, 2, 3, 5, 6, 7], size=2)
+    return theta, freq, phase, off
+
+
+def _texture(waves, X: torch.Tensor, Y: torch.Tensor) -> torch.Tensor:
+    """The procedural texture of scene() at continuous coordinates (float64 [H, W] each),
+    [H, W, 3] float64."""
+    theta, freq, phase, off = waves
+    cx = torch.floor((X + float(off[0])) / 8.0)
+    cy = torch.floor((Y + float(off[1])) / 8.0)
+    checker = torch.where(torch.remainder(cx + cy, 2.0) == 0.0, 1.0, -1.0).to(torch.float64)
+    out = torch.empty(X.shape + (3,), dtype=torch.float64, device=X.device)
+    for c in range(3):
+        acc = torch.zeros_like(X)
+        for i in range(8):
+            kx = 2.0 * math.pi * freq[c, i] * math.cos(theta[c, i]) / 256.0
+            ky = 2.0 * math.pi * freq[c, i] * math.sin(theta[c, i]) / 256.0
+            acc += torch.sin(Y * ky + X * kx + phase[c, i])
+        out[..., c] = 0.5 + 0.35 * (acc / 8.0) + 0.15 * checker
+    return out
+
+
+class MovingSource:
+    """Frames of one stream under camera and object motion:
+    (colour [H, W, 3] f32, level [H, W] u8, motion [H, W, 2] f32, depth [H, W] f32, gx, gy).
+
+    Frame t renders the panned background and the disc at full resolution (float64), takes
+    grid-aligned 2x2 and 4x4 block means of that frame for the reduced levels, and selects by
+    the level map of gaze t (as FrameSource).  Motion vectors are the displacement of each
+    pixel's surface point since frame t - 1 (current minus previous position): c(t-1) - c(t)
+    horizontally on the background, the disc's own displacement inside it.  Background texture
+    seed 1000 + stream_id, disc texture seed 1500 + stream_id; gaze as FrameSource."""
+
+    def __init__(self, spec: StreamSpec, motion: MotionSpec | None = None, device="cpu",
+                 gaze: np.ndarray | None = None, n_frames: int | None = None):
+        self.spec = spec
+        self.motion = motion or motion_for(spec)
+        self.device = torch.device(device)
+        self.gaze = gaze if gaze is not None else gaze_trace(spec, n_frames)
+        self._bg = _waves(np.random.Generator(np.random.PCG64(1000 + spec.stream_id)))
+        self._disc = _waves(np.random.Generator(np.random.PCG64(1500 + spec.stream_id)))
+        dev = self.device
+        self._u = (torch.arange(spec.width, dtype=torch.float64, device=dev) + 0.5)[None, :].expand(spec.height, -1)
+        self._v = (torch.arange(spec.height, dtype=torch.float64, device=dev) + 0.5)[:, None].expand(-1, spec.width)
+
+    def __len__(self) -> int:
+        return len(self.gaze)
+
+    def pan(self, t: int) -> float:
+        m = self.motion
+        return m.pan_amp * math.sin(2.0 * math.pi * t / m.pan_period)
+
+    def disc_x(self, t: int) -> float:
+        m = self.motion
+        return 0.5 * self.spec.width + m.disc_amp * math.sin(2.0 * math.pi * t / m.disc_period + 1.0)
+
+    def render(self, t: int):
+        """Full-resolution colour [H, W, 3] f32, motion [H, W, 2] f32 and depth [H, W] f32."""
+        m, spec = self.motion, self.spec
+        u, v = self._u, self._v
+        c, c_prev = self.pan(t), self.pan(t - 1)
+        ox, ox_prev = self.disc_x(t), self.disc_x(t - 1)
+        oy = 0.55 * spec.height
+        inside = (u - ox) ** 2 + (v - oy) ** 2 <= m.disc_radius ** 2
+        bg = _texture(self._bg, u + c, v)
+        disc = _texture(self._disc, u - ox, v - oy)
+        colour = torch.where(inside[..., None], disc, bg).to(torch.float32)
+        mv = torch.zeros((spec.height, spec.width, 2), dtype=torch.float64, device=self.device)
+        mv[..., 0] = torch.where(inside, ox - ox_prev, c_prev - c)
+        depth = torch.where(inside, torch.full_like(u, m.disc_depth),
+                            m.bg_depth * (1.0 + 0.05 * torch.sin(2.0 * math.pi * v / spec.height)))
+        return colour.contiguous(), mv.to(torch.float32).contiguous(), depth.to(torch.float32).contiguous()
+
+    def frame(self, t: int):
+        gx, gy = float(self.gaze[t, 0]), float(self.gaze[t, 1])
+        full, mv, depth = self.render(t)
+        fs = FoveatedScene(full, block_mean(full, 2), block_mean(full, 4))
+        lev = level_map(self.spec, gx, gy, self.device)
+        return foveated_frame(fs, lev), lev, mv, depth, gx, gy
 
     def __iter__(self):
         for t in range(len(self)):

@@ -51,6 +51,17 @@ MUTANTS = {
     "cie94_chroma_of_wrong_colour": ("float SC = 1.0f + 0.045f * C1;", "float SC = 1.0f + 0.045f * C2;"),
     "cbrt_too_few_newton_steps": ("for (int it = 0; it < 4; ++it) {", "for (int it = 0; it < 1; ++it) {"),
     "xyz_matrix_entry": ("0.3575761f * g", "0.3757561f * g"),
+    "reproject_motion_sign": ("const float sx = ((float)x + 0.5f) - motion[2 * p + 0];",
+                              "const float sx = ((float)x + 0.5f) + motion[2 * p + 0];"),
+    "reproject_rounds_to_nearest": ("const int qx = (int)floorf(sx);", "const int qx = (int)floorf(sx + 0.5f);"),
+    "reproject_axes_swapped": ("q = (size_t)qy * (size_t)W + (size_t)qx;", "q = (size_t)qx * (size_t)W + (size_t)qy;"),
+    "depth_test_absolute": ("if (fabsf(dc - dp) <= depth_tol * dc) keep = 1;", "if (fabsf(dc - dp) <= depth_tol) keep = 1;"),
+    "depth_test_strict": ("if (fabsf(dc - dp) <= depth_tol * dc) keep = 1;",
+                          "if (fabsf(dc - dp) < depth_tol * dc) keep = 1;"),
+    "flush_keeps_count": ("                cnt[p] = 0u;\n", "                cnt[p] = o->cnt[p];\n"),
+    "flush_keeps_wsum": ("                wsum[p] = 0.0f;\n", "                wsum[p] = o->wsum[p];\n"),
+    "history_from_own_pixel": ("wsum[p] = o->wsum[q];", "wsum[p] = o->wsum[p];"),
+    "depth_not_stored": ("dnew[p] = depth[p];", "dnew[p] = o->depth[p];"),
 }
 
 
@@ -67,7 +78,8 @@ def _run_mutant(name, tmpdir):
                    capture_output=True)
     env = dict(os.environ, FWRS_ORACLE_LIB=lib, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_oracle_eq7.py")],
+                        os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_oracle_eq7.py"),
+                        os.path.join(HERE, "test_oracle_reproject.py")],
                        cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=600)
     return name, r.returncode, r.stdout[-400:]
