@@ -58,6 +58,14 @@ def bytes_per_update_eq7(k: int, rbar: float) -> float:
     return 25.0 + 24.0 * k + 20.0 * rbar
 
 
+def bytes_per_update_reproject(k: int, wsum_slots: int = 1) -> float:
+    """Algorithmic HBM bytes per pixel-update of the reprojecting pass (a gather from the previous
+    bank, a dense write of the next): motion (8), depth (4), the source's previous depth (4), level
+    (1), colour (12), the source's w_sum(s) (4 s), count (4), records (16 k) and frame indices (4 k)
+    read; records, indices, w_sum(s), count, depth (4) and output (12) written."""
+    return 8 + 4 + 4 + 1 + 12 + 4 * wsum_slots + 4 + 20 * k + 20 * k + 4 * wsum_slots + 4 + 4 + 12
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2510_03964_amd", "csrc")
@@ -92,9 +100,9 @@ def timed_run(res, frames, out, stream, step):
     torch.cuda.synchronize()
     t_start.record(stream)
     for t in range(K):
-        c, lev, gx, gy = frames[t]
+        args = frames[t]
         ev[t][0].record(stream)
-        step(c, lev, gx, gy, out)
+        step(*args, out)
         ev[t][1].record(stream)
     t_end.record(stream)
     torch.cuda.synchronize()
@@ -214,6 +222,68 @@ def serving(dev, stream, time_scale: float, fps_scale: float, ring: int, label: 
     return out
 
 
+def reprojection(dev, stream, spec, steps: int, warmup: int, ring: int, tile) -> dict:
+    """The moving-camera workload at the headline size: a ring of `ring` distinct frames (camera
+    pan and occluder both periodic in it) resident in HBM, `steps` reprojected frames timed after
+    `warmup` untimed ones on a throwaway context."""
+    import numpy as np
+    import torch
+
+    from paper_2510_03964_amd import fwrs, synth
+
+    tol = 0.1
+    gaze = synth.gaze_trace(spec, ring)
+    src = synth.MovingSource(spec, device=dev, gaze=gaze)
+    assert ring % src.motion.period == 0, "the ring must hold whole motion periods"
+    log(f"reprojection: generating {ring} moving frames of {spec.width}x{spec.height}")
+    t0 = time.perf_counter()
+    frames = []
+    for t in range(ring):
+        frames.append(src.frame(t))
+        if (t + 1) % 60 == 0:
+            torch.cuda.synchronize()
+            log(f"  {t + 1} frames")
+    torch.cuda.synchronize()
+    log(f"  resident ({time.perf_counter() - t0:.1f} s)")
+    p = fwrs.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED,
+                            flags=fwrs.FLAG_REPROJECT)
+    out = torch.empty((spec.height, spec.width, 3), dtype=torch.float32, device=dev)
+
+    def run(res, n):
+        def step(c, lev, mv, d, gx, gy, o):
+            res.step_reproject(c, lev, mv, d, gx, gy, tol, o)
+        return timed_run(res, [frames[t % ring] for t in range(n)], out, stream, step)
+
+    warm = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=stream)
+    if tile:
+        warm.set_tile(*tile)
+    run(warm, max(warmup, 2))
+    warm.close()
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=stream)
+    if tile:
+        res.set_tile(*tile)
+    total_ms, per = run(res, steps)
+    takes, changed, updates = res.stats()
+    flushed = res.flushes()
+    res.close()
+    del frames
+    torch.cuda.empty_cache()
+    B = bytes_per_update_reproject(spec.k)
+    kern = float(per.mean())
+    ach = spec.pixels * B / (kern / 1e3) / 1e9
+    log(f"reprojection: {total_ms / steps:.4f} ms/frame")
+    return {"entry": "fwrs_push_frame_reproject", "frames": steps, "ring": ring,
+            "workload": f"{spec.width}x{spec.height} k={spec.k}: lateral camera pan (4% of the width, "
+                        f"240-frame back-and-forth) and a moving occluding disc, motion vectors + depth, "
+                        f"relative depth tolerance {tol}",
+            "ms_per_step": total_ms / steps, "value": spec.pixels * steps / (total_ms / 1e3) / 1e9,
+            "unit": "Gpixel-updates/s", "ms_per_frame_p50": float(np.percentile(per, 50)),
+            "ms_per_frame_p99": float(np.percentile(per, 99)),
+            "flushed_per_pixel_update": flushed / updates, "slot_takes_per_pixel_update": takes / updates,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBPS, "kernel_ms_avg": kern, "bytes_per_pixel_update": B}}
+
+
 def cpu_baseline(frames_host, spec, n_frames: int) -> dict:
     import oracle
 
@@ -258,6 +328,8 @@ def main() -> int:
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth reference")
     ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-resolve run")
     ap.add_argument("--no-eq7", action="store_true", help="skip the Eq. 7 (full temporal bias) run")
+    ap.add_argument("--no-reproject", action="store_true", help="skip the moving-camera (reprojection) run")
+    ap.add_argument("--reproject-ring", type=int, default=240, help="distinct moving frames kept resident")
     ap.add_argument("--no-multistream", action="store_true", help="skip the batched-vs-plain runs")
     ap.add_argument("--ring", type=int, default=48, help="distinct frames per stream kept resident (multistream)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving runs")
@@ -378,10 +450,15 @@ def main() -> int:
 
     host = [(c.cpu().numpy(), lev.cpu().numpy(), gx, gy) for (c, lev, gx, gy) in frames[:args.cpu_frames]]
 
+    del frames
+    torch.cuda.empty_cache()
+
+    reproject = None
+    if not args.no_reproject:
+        reproject = reprojection(dev, stream, spec, K, W, args.reproject_ring, tile)
+
     multi = None
     if not args.no_multistream:
-        del frames
-        torch.cuda.empty_cache()
         left, right = synth.spec_stereo()
         g_left = synth.gaze_trace(left)
         g_right = g_left + np.array([synth.vergence_shift(), 0.0], dtype=np.float32)
@@ -433,6 +510,7 @@ def main() -> int:
         "pixels_changed_per_pixel_update": changed / updates,
         "incremental": incremental,
         "eq7": eq7,
+        "reproject": reproject,
         "multistream": multi,
         "serving": served,
         "copy_gbps": copy_gbps,

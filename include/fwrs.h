@@ -30,8 +30,8 @@
  *    image (pixel centres are at x + 0.5, y + 0.5).
  *  - Calls that enqueue GPU work return as soon as it is enqueued.  An
  *    asynchronous failure is reported by fwrs_sync (FWRS_E_HIP).
- *  - Every call returns a status (FWRS_OK on success) except fwrs_state_bytes
- *    and fwrs_strerror.  On FWRS_E_ARG nothing was enqueued and the context is
+ *  - Every call returns a status (FWRS_OK on success) except
+ *    fwrs_state_bytes, fwrs_state_bytes_params and fwrs_strerror.  On FWRS_E_ARG nothing was enqueued and the context is
  *    unchanged.
  *  - A context is not thread-safe; distinct contexts are independent.
  *
@@ -76,6 +76,11 @@ extern "C" {
 /* Largest slot count per pixel. */
 #define FWRS_MAX_K 16
 
+/* ---- context flags ------------------------------------------------------- */
+/* The context follows a moving camera (Sec. 4.3): it keeps two banks of the
+ * store and is updated only by fwrs_push_frame_reproject. */
+#define FWRS_FLAG_REPROJECT 1u
+
 /* Method parameters.
  *   seed, stream_id   Philox key words.
  *   fov_deg           horizontal field of view spanned by `width` pixels; the
@@ -86,6 +91,7 @@ extern "C" {
  *   r_m, a_k, r2k, rek  parameters of the retinal density d(e) of Eq. 3
  *                     (Sec. 4.1 prints a_k = 0.9851, r_2,k = 1.058,
  *                     r_e,k = 22.14; r_m is not printed, default 41.03).
+ *   flags             FWRS_FLAG_* (0 by default).
  */
 typedef struct fwrs_params {
     uint32_t seed;
@@ -97,6 +103,7 @@ typedef struct fwrs_params {
     float a_k;
     float r2k;
     float rek;
+    uint32_t flags;
 } fwrs_params;
 
 typedef struct fwrs_ctx fwrs_ctx;
@@ -114,8 +121,14 @@ typedef struct fwrs_ctx fwrs_ctx;
  * touches only that pixel's record.  `pitch` (>= N, a multiple of 64) times
  * `wsum_slots` is the element count reserved for the wsum plane.  Alg. 2's candidate count m is
  * the same for every pixel -- each pixel receives one candidate per frame --
- * so it is frame_index and has no plane.  The pointers are owned by the
- * context (or by the caller's arena). */
+ * so it is frame_index and has no plane -- except in a reprojecting context,
+ * where a flush restarts a pixel's count: there
+ *   cnt[p]                   uint32   m of the pixel's reservoir
+ *   depth[p]                 float32  the pixel's depth in the last frame
+ *                                     (NaN before the first frame)
+ * describe the current bank (NULL otherwise).  The pointers are owned by the
+ * context (or by the caller's arena); in a reprojecting context they change
+ * with every frame (the banks alternate). */
 typedef struct fwrs_state_view {
     int width, height, k;
     uint32_t frame_index;   /* frames pushed so far */
@@ -124,11 +137,13 @@ typedef struct fwrs_state_view {
     float* rec;
     uint32_t* idx;
     int wsum_slots;         /* 1, or k under FWRS_BIAS_FULL */
+    uint32_t* cnt;
+    float* depth;
 } fwrs_state_view;
 
 /* Fills `p` with the defaults for an image `width` pixels wide: seed 0,
- * stream 0, fov 70 degrees, fovea radius 5% of the width, BERNOULLI bias and
- * the Eq. 3 parameters above.  FWRS_E_ARG if width <= 0 or p is NULL. */
+ * stream 0, fov 70 degrees, fovea radius 5% of the width, BERNOULLI bias,
+ * the Eq. 3 parameters above and no flags.  FWRS_E_ARG if width <= 0 or p is NULL. */
 int fwrs_default_params(int width, fwrs_params* p);
 
 /* Device bytes of the reservoir store for a width x height image with k
@@ -138,10 +153,11 @@ int fwrs_default_params(int width, fwrs_params* p);
  * to size a caller-provided arena.  Returns 0 for invalid sizes. */
 size_t fwrs_state_bytes(int width, int height, int k);
 
-/* As fwrs_state_bytes for a given bias mode: FWRS_BIAS_FULL keeps one w_sum
- * per slot, 4 * pitch * 6k plus the statistics area.  Returns 0 for invalid
- * sizes or an unknown mode. */
-size_t fwrs_state_bytes_mode(int width, int height, int k, uint32_t bias_mode);
+/* As fwrs_state_bytes for given parameters: FWRS_BIAS_FULL keeps one w_sum
+ * per slot (4 * pitch * 6k), FWRS_FLAG_REPROJECT two banks, each with a
+ * count and a depth per pixel (2 * 4 * pitch * (s + 5k + 2), s = 1 or k),
+ * plus the statistics area.  Returns 0 for invalid sizes or parameters. */
+size_t fwrs_state_bytes_params(int width, int height, int k, const fwrs_params* params);
 
 /* Host bytes written by fwrs_download_state: width * height * (8 + 24k). */
 size_t fwrs_state_host_bytes(int width, int height, int k);
@@ -155,13 +171,13 @@ int fwrs_create(int width, int height, int k, fwrs_ctx** out);
 
 /* As fwrs_create with explicit parameters, a borrowed HIP stream (hipStream_t,
  * NULL = null stream) and an optional caller-owned device arena of
- * `arena_bytes` >= fwrs_state_bytes_mode(width, height, k, params->bias_mode)
- * bytes, aligned to 256
+ * `arena_bytes` >= fwrs_state_bytes_params(width, height, k, params) bytes,
+ * aligned to 256
  * bytes, that the library uses for the store and never frees.  With arena ==
  * NULL the library allocates.  The arena is cleared on the stream.
  * FWRS_E_ARG also for: params NULL, fov_deg or fovea_radius_px not finite and
  * > 0, bias_mode unknown, a_k outside (0, 1], r_m, r2k or rek not finite and
- * > 0, arena too small or misaligned. */
+ * > 0, unknown flags, arena too small or misaligned. */
 int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void* hip_stream, void* arena,
                    size_t arena_bytes, fwrs_ctx** out);
 
@@ -184,7 +200,10 @@ int fwrs_reset(fwrs_ctx* ctx);
  * w_sum, biased by Eq. 7 against its own sample.  Then the frame index
  * advances by 1.
  * FWRS_E_ARG: NULL pointers, non-finite gaze.  Level values above 2 are
- * treated like 2 (reduced resolution).  FWRS_E_STATE: 2^32 - 1 frames pushed. */
+ * treated like 2 (reduced resolution).  FWRS_E_STATE: 2^32 - 1 frames pushed,
+ * or a reprojecting context (use fwrs_push_frame_reproject).  The same holds
+ * for fwrs_push_frame_resolve, fwrs_push_frame_resolve_incremental and the
+ * engine's ticks. */
 int fwrs_push_frame(fwrs_ctx* ctx, const float* color, const uint8_t* level_map, float gaze_x, float gaze_y);
 
 /* Enqueues the resolve into `out` ([height][width][3] float32): for each
@@ -208,6 +227,28 @@ int fwrs_push_frame_resolve(fwrs_ctx* ctx, const float* color, const uint8_t* le
 int fwrs_push_frame_resolve_incremental(fwrs_ctx* ctx, const float* color, const uint8_t* level_map,
                                         float gaze_x, float gaze_y, float* out);
 
+/* One frame of a reprojecting context (FWRS_FLAG_REPROJECT) with a moving
+ * camera or moving objects (Sec. 4.3).  `motion` is [height][width][2]
+ * float32, 8-byte aligned: the screen-space displacement in pixels of the
+ * surface point seen at each pixel since the previous frame (current minus
+ * previous position); `depth` is [height][width] float32, the point's depth
+ * (> 0, any linear unit).  Reverse reprojection: pixel (x, y) continues the
+ * reservoir of pixel (floor(x + 0.5 - mx), floor(y + 0.5 - my)) of the
+ * previous frame, if that pixel is inside the image and
+ * |depth - its previous depth| <= depth_tol * depth; otherwise (the point was
+ * off-screen, occluded or just disoccluded) the pixel's history is flushed and
+ * it starts from the empty reservoir (m = 0), so the new candidate fills every
+ * slot -- the fall-back to plain foveated rendering of Sec. 6.  Then the
+ * frame's update (weight, bias, Alg. 2 per slot) as in fwrs_push_frame, and
+ * the resolve into `out` unless `out` is NULL.  Before the first frame there
+ * is no previous depth: every pixel starts empty.  Pixels flushed are counted
+ * by fwrs_get_stats.
+ * FWRS_E_ARG: NULL color, level_map, motion or depth; motion misaligned;
+ * non-finite gaze; depth_tol negative or not finite.  FWRS_E_STATE: the
+ * context was not created with FWRS_FLAG_REPROJECT, or 2^32 - 1 frames. */
+int fwrs_push_frame_reproject(fwrs_ctx* ctx, const float* color, const uint8_t* level_map, const float* motion,
+                              const float* depth, float gaze_x, float gaze_y, float depth_tol, float* out);
+
 /* Frames pushed so far (host-side counter; no synchronisation). */
 int fwrs_frame_index(const fwrs_ctx* ctx, uint32_t* frame_index);
 
@@ -224,8 +265,10 @@ int fwrs_download_state(fwrs_ctx* ctx, void* host, size_t host_bytes);
 
 /* Synchronises the stream and returns, since creation or the last reset, the
  * number of slot replacements (takes), of pixel updates in which at least one
- * slot was replaced, and of pixel updates.  Any pointer may be NULL. */
-int fwrs_get_stats(fwrs_ctx* ctx, uint64_t* slot_takes, uint64_t* pixels_changed, uint64_t* pixel_updates);
+ * slot was replaced, of pixel updates, and of reprojected pixel updates whose
+ * history was flushed.  Any pointer may be NULL. */
+int fwrs_get_stats(fwrs_ctx* ctx, uint64_t* slot_takes, uint64_t* pixels_changed, uint64_t* pixel_updates,
+                   uint64_t* pixels_flushed);
 
 /* Selects the thread-block tile: tile_x pixels by tile_y rows (one thread per
  * pixel), tile_x * tile_y in {64, 128, 256}, both powers of two.  It only

@@ -21,7 +21,7 @@ using fwrs::FrameDesc;
 namespace {
 
 constexpr size_t kPitchAlign = 64;   // elements; planes start on 256-byte boundaries
-constexpr size_t kStatBytes = 2 * sizeof(unsigned long long) * fwrs::kStatSlots;
+constexpr size_t kStatBytes = 3 * sizeof(unsigned long long) * fwrs::kStatSlots;
 constexpr int kDefaultTileX = 64, kDefaultTileY = 1;
 
 size_t pitch_for(int width, int height)
@@ -46,7 +46,18 @@ bool params_ok(const fwrs_params* p)
     if (p->bias_mode != FWRS_BIAS_NONE && p->bias_mode != FWRS_BIAS_BERNOULLI && p->bias_mode != FWRS_BIAS_FULL)
         return false;
     if (!(p->a_k > 0.0f && p->a_k <= 1.0f)) return false;
+    if ((p->flags & ~(uint32_t)FWRS_FLAG_REPROJECT) != 0u) return false;
     return finite_pos(p->r_m) && finite_pos(p->r2k) && finite_pos(p->rek);
+}
+
+// Elements (4 bytes) of one bank of the store: w_sum (one per pixel, or one per
+// slot under Eq. 7), the slot records, the slot frame indices, and for a
+// reprojecting context the pixel counts and depths.
+size_t bank_elems(size_t pitch, size_t k, uint32_t bias_mode, uint32_t flags)
+{
+    const size_t ws = bias_mode == FWRS_BIAS_FULL ? k : 1;
+    const size_t extra = (flags & FWRS_FLAG_REPROJECT) ? 2 : 0;
+    return pitch * (ws + 5 * k + extra);
 }
 
 // Per-context constants, derived with the same binary32 functions the kernels use.
@@ -106,9 +117,18 @@ struct fwrs_ctx {
     bool owns_arena = false;
     size_t pitch = 0;
     size_t wsum_slots = 1;   // 1: one w_sum per pixel; k under Eq. 7 (one per slot)
+    // the current bank (the store the next frame reads)
     float* wsum = nullptr;
     float* rec = nullptr;
     uint32_t* idx = nullptr;
+    // reprojecting contexts: two banks; bank[b] = {wsum, rec, idx, cnt, depth}
+    bool reproject = false;
+    int cur = 0;
+    float* bank_wsum[2] = {nullptr, nullptr};
+    float* bank_rec[2] = {nullptr, nullptr};
+    uint32_t* bank_idx[2] = {nullptr, nullptr};
+    uint32_t* bank_cnt[2] = {nullptr, nullptr};
+    float* bank_depth[2] = {nullptr, nullptr};
     unsigned long long* stats = nullptr;
     uint32_t t = 0;
     uint64_t pixel_updates = 0;
@@ -131,6 +151,13 @@ int clear_store(fwrs_ctx* x)
         hipSuccess)
         return FWRS_E_HIP;
     if (fwrs::launch_fill_u32(x->idx, P * k, 0xFFFFFFFFu, x->stream) != hipSuccess) return FWRS_E_HIP;
+    if (x->reproject) {
+        // counts 0; depths NaN: no previous frame, so the first reprojected frame flushes
+        if (fwrs::launch_fill_u32(x->bank_cnt[x->cur], P, 0u, x->stream) != hipSuccess ||
+            fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->bank_depth[x->cur]), P, 0x7FC00000u, x->stream) !=
+                hipSuccess)
+            return FWRS_E_HIP;
+    }
     if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->stats), kStatBytes / 4, 0u, x->stream) != hipSuccess)
         return FWRS_E_HIP;
     x->t = 0;
@@ -215,20 +242,22 @@ int fwrs_default_params(int width, fwrs_params* p)
     p->a_k = 0.9851f;
     p->r2k = 1.058f;
     p->rek = 22.14f;
+    p->flags = 0u;
     return FWRS_OK;
 }
 
-size_t fwrs_state_bytes_mode(int width, int height, int k, uint32_t bias_mode)
+size_t fwrs_state_bytes_params(int width, int height, int k, const fwrs_params* params)
 {
-    if (!sizes_ok(width, height, k)) return 0;
-    if (bias_mode != FWRS_BIAS_NONE && bias_mode != FWRS_BIAS_BERNOULLI && bias_mode != FWRS_BIAS_FULL) return 0;
-    const size_t wslots = bias_mode == FWRS_BIAS_FULL ? (size_t)k : 1;
-    return 4 * pitch_for(width, height) * (wslots + 5 * (size_t)k) + kStatBytes;
+    if (!sizes_ok(width, height, k) || !params_ok(params)) return 0;
+    const size_t banks = (params->flags & FWRS_FLAG_REPROJECT) ? 2 : 1;
+    return 4 * banks * bank_elems(pitch_for(width, height), (size_t)k, params->bias_mode, params->flags) + kStatBytes;
 }
 
 size_t fwrs_state_bytes(int width, int height, int k)
 {
-    return fwrs_state_bytes_mode(width, height, k, FWRS_BIAS_BERNOULLI);
+    fwrs_params p;
+    if (fwrs_default_params(width > 0 ? width : 1, &p) != FWRS_OK) return 0;
+    return fwrs_state_bytes_params(width, height, k, &p);
 }
 
 size_t fwrs_state_host_bytes(int width, int height, int k)
@@ -242,7 +271,7 @@ int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void
 {
     if (!out || !sizes_ok(width, height, k) || !params_ok(params)) return FWRS_E_ARG;
     *out = nullptr;
-    const size_t need = fwrs_state_bytes_mode(width, height, k, params->bias_mode);
+    const size_t need = fwrs_state_bytes_params(width, height, k, params);
     if (arena && (arena_bytes < need || !aligned(arena, 256))) return FWRS_E_ARG;
     fwrs_ctx* x = new (std::nothrow) fwrs_ctx();
     if (!x) return FWRS_E_NOMEM;
@@ -255,6 +284,7 @@ int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void
     x->stream = (hipStream_t)hip_stream;
     x->pitch = pitch_for(width, height);
     x->wsum_slots = params->bias_mode == FWRS_BIAS_FULL ? (size_t)k : 1;
+    x->reproject = (params->flags & FWRS_FLAG_REPROJECT) != 0u;
     if (arena) {
         x->arena = arena;
     } else {
@@ -267,11 +297,22 @@ int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void
     }
     const size_t P = x->pitch, kk = (size_t)k;
     const size_t ws = x->wsum_slots;
+    const size_t bank = bank_elems(P, kk, params->bias_mode, params->flags);
     float* base = static_cast<float*>(x->arena);
-    x->wsum = base;
-    x->rec = base + ws * P;
-    x->idx = reinterpret_cast<uint32_t*>(base + (ws + 4 * kk) * P);
-    x->stats = reinterpret_cast<unsigned long long*>(base + (ws + 5 * kk) * P);
+    for (int b = 0; b < (x->reproject ? 2 : 1); ++b) {
+        float* B = base + (size_t)b * bank;
+        x->bank_wsum[b] = B;
+        x->bank_rec[b] = B + ws * P;
+        x->bank_idx[b] = reinterpret_cast<uint32_t*>(B + (ws + 4 * kk) * P);
+        if (x->reproject) {
+            x->bank_cnt[b] = reinterpret_cast<uint32_t*>(B + (ws + 5 * kk) * P);
+            x->bank_depth[b] = B + (ws + 5 * kk + 1) * P;
+        }
+    }
+    x->wsum = x->bank_wsum[0];
+    x->rec = x->bank_rec[0];
+    x->idx = x->bank_idx[0];
+    x->stats = reinterpret_cast<unsigned long long*>(base + (x->reproject ? 2 : 1) * bank);
     const int rc = clear_store(x);
     if (rc != FWRS_OK) {
         if (x->owns_arena) (void)hipFree(x->arena);
@@ -320,7 +361,7 @@ int fwrs_reset(fwrs_ctx* x)
 int fwrs_push_frame(fwrs_ctx* x, const float* color, const uint8_t* level_map, float gaze_x, float gaze_y)
 {
     if (!x || !color || !level_map || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
-    if (x->t == 0xFFFFFFFFu) return FWRS_E_STATE;
+    if (x->t == 0xFFFFFFFFu || x->reproject) return FWRS_E_STATE;
     return run_frame(x, color, level_map, gaze_x, gaze_y, nullptr, 1);
 }
 
@@ -334,7 +375,7 @@ int fwrs_push_frame_resolve(fwrs_ctx* x, const float* color, const uint8_t* leve
                             float* out)
 {
     if (!x || !color || !level_map || !out || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
-    if (x->t == 0xFFFFFFFFu) return FWRS_E_STATE;
+    if (x->t == 0xFFFFFFFFu || x->reproject) return FWRS_E_STATE;
     return run_frame(x, color, level_map, gaze_x, gaze_y, out, 3);
 }
 
@@ -342,9 +383,44 @@ int fwrs_push_frame_resolve_incremental(fwrs_ctx* x, const float* color, const u
                                         float gaze_y, float* out)
 {
     if (!x || !color || !level_map || !out || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
-    if (x->t == 0xFFFFFFFFu) return FWRS_E_STATE;
+    if (x->t == 0xFFFFFFFFu || x->reproject) return FWRS_E_STATE;
     if (!x->resolved || x->resolved_out != out || x->resolved_at != x->t) return FWRS_E_STATE;
     return run_frame(x, color, level_map, gaze_x, gaze_y, out, 5);
+}
+
+int fwrs_push_frame_reproject(fwrs_ctx* x, const float* color, const uint8_t* level_map, const float* motion,
+                              const float* depth, float gaze_x, float gaze_y, float depth_tol, float* out)
+{
+    if (!x || !color || !level_map || !motion || !depth || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
+    if (!std::isfinite(depth_tol) || depth_tol < 0.0f || !aligned(motion, 8)) return FWRS_E_ARG;
+    if (!x->reproject || x->t == 0xFFFFFFFFu) return FWRS_E_STATE;
+    DeviceGuard g(x->device);
+    if (!g.ok) return FWRS_E_HIP;
+    const int src = x->cur, dst = 1 - x->cur;
+    fwrs::ReprojDesc r{};
+    r.f = make_desc(x, color, level_map, gaze_x, gaze_y, out, x->tile_x, x->tile_y);
+    r.f.wsum = x->bank_wsum[dst];
+    r.f.rec = x->bank_rec[dst];
+    r.f.idx = x->bank_idx[dst];
+    r.motion = motion;
+    r.depth = depth;
+    r.src_wsum = x->bank_wsum[src];
+    r.src_rec = x->bank_rec[src];
+    r.src_idx = x->bank_idx[src];
+    r.src_cnt = x->bank_cnt[src];
+    r.src_depth = x->bank_depth[src];
+    r.cnt = x->bank_cnt[dst];
+    r.depth_out = x->bank_depth[dst];
+    r.tol = depth_tol;
+    if (fwrs::launch_reproject(r, x->stream) != hipSuccess) return FWRS_E_HIP;
+    x->cur = dst;
+    x->wsum = x->bank_wsum[dst];
+    x->rec = x->bank_rec[dst];
+    x->idx = x->bank_idx[dst];
+    x->t += 1u;
+    x->pixel_updates += (uint64_t)x->width * (uint64_t)x->height;
+    x->resolved = false;
+    return FWRS_OK;
 }
 
 int fwrs_frame_index(const fwrs_ctx* x, uint32_t* frame_index)
@@ -363,6 +439,8 @@ int fwrs_get_state(const fwrs_ctx* x, fwrs_state_view* v)
     v->frame_index = x->t;
     v->pitch = x->pitch;
     v->wsum_slots = (int)x->wsum_slots;
+    v->cnt = x->reproject ? x->bank_cnt[x->cur] : nullptr;
+    v->depth = x->reproject ? x->bank_depth[x->cur] : nullptr;
     v->wsum = x->wsum;
     v->rec = x->rec;
     v->idx = x->idx;
@@ -398,7 +476,14 @@ int fwrs_download_state(fwrs_ctx* x, void* host, size_t host_bytes)
         hipStreamSynchronize(x->stream) != hipSuccess)
         return FWRS_E_HIP;
     // every pixel has seen one candidate per frame: m = frame count
-    for (size_t p = 0; p < N; ++p) cnt[p] = x->t;
+    if (x->reproject) {
+        // per-pixel m: a flush restarts it
+        if (hipMemcpyAsync(cnt, x->bank_cnt[x->cur], 4 * N, hipMemcpyDeviceToHost, x->stream) != hipSuccess ||
+            hipStreamSynchronize(x->stream) != hipSuccess)
+            return FWRS_E_HIP;
+    } else {
+        for (size_t p = 0; p < N; ++p) cnt[p] = x->t;
+    }
     // per-slot sums [k][N]: Eq. 7's own ([N][k] on the device; the shared
     // w_sum is then 0), else the shared w_sum repeated for every slot
     const bool per_slot = x->prm.bias_mode == FWRS_BIAS_FULL;
@@ -418,23 +503,26 @@ int fwrs_download_state(fwrs_ctx* x, void* host, size_t host_bytes)
     return FWRS_OK;
 }
 
-int fwrs_get_stats(fwrs_ctx* x, uint64_t* slot_takes, uint64_t* pixels_changed, uint64_t* pixel_updates)
+int fwrs_get_stats(fwrs_ctx* x, uint64_t* slot_takes, uint64_t* pixels_changed, uint64_t* pixel_updates,
+                   uint64_t* pixels_flushed)
 {
     if (!x) return FWRS_E_ARG;
     DeviceGuard g(x->device);
     if (!g.ok) return FWRS_E_HIP;
-    std::vector<unsigned long long> h(2 * fwrs::kStatSlots);
+    std::vector<unsigned long long> h(3 * fwrs::kStatSlots);
     if (hipMemcpyAsync(h.data(), x->stats, kStatBytes, hipMemcpyDeviceToHost, x->stream) != hipSuccess)
         return FWRS_E_HIP;
     if (hipStreamSynchronize(x->stream) != hipSuccess) return FWRS_E_HIP;
-    uint64_t takes = 0, changed = 0;
+    uint64_t takes = 0, changed = 0, flushed = 0;
     for (int i = 0; i < fwrs::kStatSlots; ++i) {
-        takes += h[2 * i];
-        changed += h[2 * i + 1];
+        takes += h[3 * i];
+        changed += h[3 * i + 1];
+        flushed += h[3 * i + 2];
     }
     if (slot_takes) *slot_takes = takes;
     if (pixels_changed) *pixels_changed = changed;
     if (pixel_updates) *pixel_updates = x->pixel_updates;
+    if (pixels_flushed) *pixels_flushed = flushed;
     return FWRS_OK;
 }
 
@@ -610,7 +698,7 @@ int fwrs_engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n)
         const fwrs_frame& f = frames[i];
         if (!f.ctx || !f.color || !f.level_map || !f.out || !gaze_ok(f.gaze_x, f.gaze_y)) return FWRS_E_ARG;
         if (f.ctx->device != e->device) return FWRS_E_ARG;
-        if (f.ctx->t == 0xFFFFFFFFu) return FWRS_E_STATE;
+        if (f.ctx->t == 0xFFFFFFFFu || f.ctx->reproject) return FWRS_E_STATE;
         for (int j = 0; j < i; ++j)
             if (frames[j].ctx == f.ctx) return FWRS_E_ARG;
     }

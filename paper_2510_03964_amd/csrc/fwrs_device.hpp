@@ -35,12 +35,29 @@ struct alignas(8) FrameDesc {
     float* wsum;                // [N] w_sum per pixel; [N][k] per slot under Eq. 7
     float* rec;                 // [N][k][4] slot records {w, r, g, b}
     uint32_t* idx;              // [N][k] frame index of each slot's sample
-    unsigned long long* stats;  // [kStatSlots][2] counters (slots replaced, pixels changed), or null
+    unsigned long long* stats;  // [kStatSlots][3] counters (slots replaced, pixels changed, flushed), or null
     uint32_t width, height, t, k;
     float gx, gy;
     Consts c;
     uint32_t seed, stream_id, bias;
     uint32_t tile_x_log2, tile_y_log2, tiles_x, items;  // launch geometry
+};
+
+// Reprojected frame (Sec. 4.3): the reservoirs are gathered from the previous
+// bank at each pixel's motion-compensated source and written densely to the
+// other bank (f's wsum / rec / idx), with the pixel counts and depths.
+struct alignas(8) ReprojDesc {
+    FrameDesc f;
+    const float* motion;        // [H][W][2] f32 pixels, current minus previous position
+    const float* depth;         // [H][W] f32 current depth (> 0)
+    const float* src_wsum;      // previous bank (layout as f's)
+    const float* src_rec;
+    const uint32_t* src_idx;
+    const uint32_t* src_cnt;    // [N] candidates seen (Alg. 2's m)
+    const float* src_depth;     // [N] depth of the previous frame (NaN: none)
+    uint32_t* cnt;              // this frame's bank
+    float* depth_out;
+    float tol;                  // relative depth tolerance
 };
 
 constexpr int kBlock = 256;             // threads per block

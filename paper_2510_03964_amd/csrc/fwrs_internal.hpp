@@ -27,6 +27,9 @@ static_assert(sizeof(TickArgs) <= 4096, "kernel arguments are limited to 4 KiB")
 // Batched kernel, one block per work item of the launch's frames.
 hipError_t launch_tick(const TickArgs& a, hipStream_t stream);
 
+// Reprojected frame: gather from the previous bank, dense write to this one.
+hipError_t launch_reproject(const ReprojDesc& r, hipStream_t stream);
+
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t stream);
 
 // Entry point of the batched kernel, for HIP graph kernel nodes.

@@ -71,6 +71,14 @@ __device__ __forceinline__ float4 ld4(const float4* p)
 }
 
 template <uint32_t BIT>
+__device__ __forceinline__ float2 ld2(const float* p)
+{
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    const v2f v = ld<BIT>(reinterpret_cast<const v2f*>(p));
+    return make_float2(v.x, v.y);
+}
+
+template <uint32_t BIT>
 __device__ __forceinline__ void st4(float4* p, const float4& v)
 {
     st<BIT>(reinterpret_cast<v4f*>(p), v4f{v.x, v.y, v.z, v.w});
@@ -373,14 +381,16 @@ __device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t it
 
 __device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t v)
 {
-    // v = replaced slots + 2^16 * (pixel changed).  Wave sum (at most 1024 slots and 64
-    // pixels), then one 64-bit atomic per counter and wave on a pair chosen by the wave's id.
+    // v = replaced slots + 2^16 * (pixel changed) + 2^24 * (pixel flushed).  Wave sum (at
+    // most 1024 slots and 64 pixels per field), then one 64-bit atomic per non-zero counter
+    // and wave on a triple chosen by the wave's id.
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if ((threadIdx.x & 63u) == 0u && v) {
         const uint32_t slot = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) & (kStatSlots - 1);
-        atomicAdd(stats + 2 * slot, (unsigned long long)(v & 0xFFFFu));
-        atomicAdd(stats + 2 * slot + 1, (unsigned long long)(v >> 16));
+        atomicAdd(stats + 3 * slot, (unsigned long long)(v & 0xFFFFu));
+        atomicAdd(stats + 3 * slot + 1, (unsigned long long)((v >> 16) & 0xFFu));
+        if (v >> 24) atomicAdd(stats + 3 * slot + 2, (unsigned long long)(v >> 24));
     }
 }
 
@@ -428,6 +438,150 @@ __global__ __launch_bounds__(kBlock) void tick_kernel(const TickArgs a)
 // ---------------------------------------------------------------------------
 // Store initialisation: the empty reservoir.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Reprojected frame (Sec. 4.3).  Pixel p continues the reservoir of the pixel
+// containing its centre moved back by its motion vector, if that point is in
+// the image and its previous depth agrees with p's depth within the relative
+// tolerance; otherwise p starts from the empty reservoir (flush).  Then the
+// frame's update as in the other kernels (Eq. 4, the bias, Alg. 2 per slot),
+// written densely to this frame's bank, and the resolve.  A gather from the
+// previous bank, so the banks alternate; every slot is rewritten.
+// ---------------------------------------------------------------------------
+template <int K, bool EQ7>
+__device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_t x, uint32_t y)
+{
+    const FrameDesc& d = r.f;
+    const uint32_t p = y * d.width + x;
+    const int kk = K ? K : (int)d.k;
+    constexpr int R = K ? K : 1;
+
+    // 1. the motion-compensated source and the depth test
+    const float2 mv = ld2<kNtColor>(r.motion + 2 * (size_t)p);
+    const float dc = ld<kNtColor>(r.depth + p);
+    const float sx = ((float)x + 0.5f) - mv.x;
+    const float sy = ((float)y + 0.5f) - mv.y;
+    bool keep = false;
+    uint32_t q = 0u;
+    if (sx >= 0.0f && sx < (float)d.width && sy >= 0.0f && sy < (float)d.height) {
+        const uint32_t qx = (uint32_t)floorf(sx);
+        const uint32_t qy = (uint32_t)floorf(sy);
+        q = qy * d.width + qx;
+        const float dp = r.src_depth[q];
+        keep = fabsf(dc - dp) <= r.tol * dc;      // NaN (no previous frame) compares false
+    }
+
+    // 2. the history: the source reservoir, or the empty one
+    const float4* src = reinterpret_cast<const float4*>(r.src_rec) + (size_t)q * (size_t)kk;
+    const uint32_t* sidx = r.src_idx + (size_t)q * (size_t)kk;
+    float4 rv[R];
+    uint32_t iv[R];
+    float W[R];
+    const float4 empty = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (K) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            rv[j] = keep ? src[j] : empty;
+            iv[j] = keep ? sidx[j] : 0xFFFFFFFFu;
+            if (EQ7) W[j] = keep ? r.src_wsum[(size_t)q * (size_t)kk + j] : 0.f;
+        }
+    }
+    float W1 = 0.f;
+    uint32_t m = 0u;
+    if (keep) {
+        if (!EQ7) W1 = r.src_wsum[q];
+        m = r.src_cnt[q];
+    }
+
+    // 3. this frame's candidate
+    const uint32_t lv = ld<kNtLevel>(d.level + p);
+    const float* color = d.color + 3 * (size_t)p;
+    const float c0 = ld<kNtColor>(color + 0);
+    const float c1 = ld<kNtColor>(color + 1);
+    const float c2 = ld<kNtColor>(color + 2);
+    const float dx = ((float)x + 0.5f) - d.gx;
+    const float dy = ((float)y + 0.5f) - d.gy;
+    const float w = weight_eq4(d.c, dx * dx + dy * dy, lv);
+    const float4 fresh = make_float4(w, c0, c1, c2);
+    float3 lab_new = make_float3(0.f, 0.f, 0.f);
+    if (EQ7) lab_new = rgb_to_lab(c0, c1, c2);
+    const float W1b = EQ7 ? 0.f : bias_eq6(W1, w, d.bias);
+    const float s = W1b + w;
+
+    // 4. Alg. 2 per slot, dense stores to this frame's bank, resolve sums
+    float4* rec = reinterpret_cast<float4*>(d.rec) + (size_t)p * (size_t)kk;
+    uint32_t* idx = d.idx + (size_t)p * (size_t)kk;
+    float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    uint32_t tk = 0u;
+    uint4 words = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int j = 0; j < kk; ++j) {
+        float4 v;
+        uint32_t vi;
+        float Wj = 0.f;
+        if (K) {
+            v = rv[K ? j : 0];
+            vi = iv[K ? j : 0];
+            if (EQ7) Wj = W[K ? j : 0];
+        } else {
+            v = keep ? src[j] : empty;
+            vi = keep ? sidx[j] : 0xFFFFFFFFu;
+            if (EQ7) Wj = keep ? r.src_wsum[(size_t)q * (size_t)kk + j] : 0.f;
+        }
+        if ((j & 3) == 0) words = philox4x32_10(p, d.t, (uint32_t)(j >> 2), 0u, d.seed, d.stream_id);
+        const uint32_t word = (j & 3) == 0 ? words.x : (j & 3) == 1 ? words.y : (j & 3) == 2 ? words.z : words.w;
+        float W1j = W1b, sj = s;
+        if (EQ7) {
+            const float dl = fminf(1.0f, cie94(rgb_to_lab(v.y, v.z, v.w), lab_new) / 100.0f);
+            W1j = bias_eq7(Wj, w, dl);
+            sj = W1j + w;
+            st<kNtWsumSt>(d.wsum + (size_t)p * (size_t)kk + j, sj);
+        }
+        if (unit_variate(word) * sj > W1j) {
+            tk |= 1u << j;
+            v = fresh;
+            vi = d.t;
+        }
+        st4<kNtRecSt>(rec + j, v);
+        st<kNtIdxSt>(idx + j, vi);
+        S = S + v.x;
+        a0 = a0 + v.x * v.y;
+        a1 = a1 + v.x * v.z;
+        a2 = a2 + v.x * v.w;
+    }
+    if (!EQ7) st<kNtWsumSt>(d.wsum + p, s);
+    st<kNtWsumSt>(r.cnt + p, m + 1u);
+    st<kNtWsumSt>(r.depth_out + p, dc);
+    if (d.out) {
+        const float rs = S > 0.0f ? 1.0f / S : 0.0f;
+        float* o = d.out + 3 * (size_t)p;
+        st<kNtOut>(o + 0, a0 * rs);
+        st<kNtOut>(o + 1, a1 * rs);
+        st<kNtOut>(o + 2, a2 * rs);
+    }
+    return __popc(tk) + (tk ? 0x10000u : 0u) + (keep ? 0u : 0x1000000u);
+}
+
+template <int K, bool EQ7>
+__global__ __launch_bounds__(kBlock) void reproject_kernel(ReprojDesc r)
+{
+    const FrameDesc& d = r.f;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint32_t lane = tid & 63u;
+    const uint32_t tlog = d.tile_x_log2 + d.tile_y_log2;
+    const uint32_t waves_per_tile_log2 = tlog - 6u;
+    const uint32_t tiles_per_item_log2 = 8u - tlog;
+    const uint32_t tile = (blockIdx.x << tiles_per_item_log2) + (wave >> waves_per_tile_log2);
+    const uint32_t local = ((wave & ((1u << waves_per_tile_log2) - 1u)) << 6) | lane;
+    const uint32_t ty = tile / d.tiles_x;
+    const uint32_t tx = tile - ty * d.tiles_x;
+    const uint32_t x = (tx << d.tile_x_log2) + (local & ((1u << d.tile_x_log2) - 1u));
+    const uint32_t y = (ty << d.tile_y_log2) + (local >> d.tile_x_log2);
+    uint32_t n = 0u;
+    if (y < d.height && x < d.width) n = pixel_reproject<K, EQ7>(r, x, y);
+    if (d.stats) add_stats(d.stats, n);
+}
+
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, size_t n, uint32_t v)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -476,6 +630,27 @@ hipError_t launch_tick(const TickArgs& a, hipStream_t stream)
 {
     if (a.total == 0u) return hipSuccess;
     hipLaunchKernelGGL(tick_kernel, dim3(a.total), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reproject(const ReprojDesc& r, hipStream_t stream)
+{
+    const dim3 grid(r.f.items), block(kBlock);
+    const bool eq7 = r.f.bias == kBiasFull;
+    switch (r.f.k) {
+        case 4:
+            if (eq7) hipLaunchKernelGGL((reproject_kernel<4, true>), grid, block, 0, stream, r);
+            else hipLaunchKernelGGL((reproject_kernel<4, false>), grid, block, 0, stream, r);
+            break;
+        case 8:
+            if (eq7) hipLaunchKernelGGL((reproject_kernel<8, true>), grid, block, 0, stream, r);
+            else hipLaunchKernelGGL((reproject_kernel<8, false>), grid, block, 0, stream, r);
+            break;
+        default:
+            if (eq7) hipLaunchKernelGGL((reproject_kernel<0, true>), grid, block, 0, stream, r);
+            else hipLaunchKernelGGL((reproject_kernel<0, false>), grid, block, 0, stream, r);
+            break;
+    }
     return hipGetLastError();
 }
 

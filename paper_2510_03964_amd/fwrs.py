@@ -18,13 +18,15 @@ LIB_PATH = os.path.join(HERE, "libfwrs.so")
 
 OK, E_ARG, E_NOMEM, E_HIP, E_STATE = 0, 1, 2, 3, 4
 BIAS_NONE, BIAS_BERNOULLI, BIAS_FULL = 0, 1, 2
+FLAG_REPROJECT = 1
 MAX_K = 16
 
 #: every symbol include/fwrs.h declares
 EXPORTS = (
-    "fwrs_default_params", "fwrs_state_bytes", "fwrs_state_bytes_mode", "fwrs_state_host_bytes", "fwrs_create", "fwrs_create_ex",
+    "fwrs_default_params", "fwrs_state_bytes", "fwrs_state_bytes_params", "fwrs_state_host_bytes", "fwrs_create", "fwrs_create_ex",
     "fwrs_destroy", "fwrs_set_stream", "fwrs_reset", "fwrs_push_frame", "fwrs_resolve",
-    "fwrs_push_frame_resolve", "fwrs_push_frame_resolve_incremental", "fwrs_frame_index", "fwrs_get_state", "fwrs_download_state", "fwrs_get_stats",
+    "fwrs_push_frame_resolve", "fwrs_push_frame_resolve_incremental", "fwrs_push_frame_reproject",
+    "fwrs_frame_index", "fwrs_get_state", "fwrs_download_state", "fwrs_get_stats",
     "fwrs_set_tile", "fwrs_sync", "fwrs_strerror", "fwrs_engine_create", "fwrs_engine_tick",
     "fwrs_engine_set_tile", "fwrs_engine_destroy",
 )
@@ -49,6 +51,7 @@ class Params(C.Structure):
         ("a_k", C.c_float),
         ("r2k", C.c_float),
         ("rek", C.c_float),
+        ("flags", C.c_uint32),
     ]
 
 
@@ -65,6 +68,8 @@ class StateView(C.Structure):
         ("rec", C.c_void_p),
         ("idx", C.c_void_p),
         ("wsum_slots", C.c_int),
+        ("cnt", C.c_void_p),
+        ("depth", C.c_void_p),
     ]
 
 
@@ -97,7 +102,7 @@ def load(path: str | None = None):
     sig = {
         "fwrs_default_params": (i, [i, C.POINTER(Params)]),
         "fwrs_state_bytes": (sz, [i, i, i]),
-        "fwrs_state_bytes_mode": (sz, [i, i, i, u32]),
+        "fwrs_state_bytes_params": (sz, [i, i, i, C.POINTER(Params)]),
         "fwrs_state_host_bytes": (sz, [i, i, i]),
         "fwrs_create": (i, [i, i, i, C.POINTER(vp)]),
         "fwrs_create_ex": (i, [i, i, i, C.POINTER(Params), vp, vp, sz, C.POINTER(vp)]),
@@ -108,10 +113,12 @@ def load(path: str | None = None):
         "fwrs_resolve": (i, [vp, vp]),
         "fwrs_push_frame_resolve": (i, [vp, vp, vp, f, f, vp]),
         "fwrs_push_frame_resolve_incremental": (i, [vp, vp, vp, f, f, vp]),
+        "fwrs_push_frame_reproject": (i, [vp, vp, vp, vp, vp, f, f, f, vp]),
         "fwrs_frame_index": (i, [vp, C.POINTER(u32)]),
         "fwrs_get_state": (i, [vp, C.POINTER(StateView)]),
         "fwrs_download_state": (i, [vp, vp, sz]),
-        "fwrs_get_stats": (i, [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+        "fwrs_get_stats": (i, [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                               C.POINTER(C.c_uint64)]),
         "fwrs_set_tile": (i, [vp, i, i]),
         "fwrs_sync": (i, [vp]),
         "fwrs_strerror": (C.c_char_p, [i]),
@@ -149,11 +156,11 @@ def default_params(width: int, **overrides) -> Params:
     return p
 
 
-def state_bytes(width: int, height: int, k: int, bias_mode: int | None = None) -> int:
-    """Device bytes of a context's store (``bias_mode`` None: the NONE/BERNOULLI layout)."""
-    if bias_mode is None:
+def state_bytes(width: int, height: int, k: int, params: Params | None = None) -> int:
+    """Device bytes of a context's store (``params`` None: the defaults' layout)."""
+    if params is None:
         return int(load().fwrs_state_bytes(int(width), int(height), int(k)))
-    return int(load().fwrs_state_bytes_mode(int(width), int(height), int(k), int(bias_mode)))
+    return int(load().fwrs_state_bytes_params(int(width), int(height), int(k), C.byref(params)))
 
 
 def state_host_bytes(width: int, height: int, k: int) -> int:
@@ -188,7 +195,7 @@ class Reservoir:
     """A context: the k-slot reservoirs of every pixel of a width x height stream.
 
     ``arena`` may be a caller-owned device tensor (uint8, at least
-    ``state_bytes(width, height, k, params.bias_mode)`` bytes, 256-byte aligned) that holds the
+    ``state_bytes(width, height, k, params)`` bytes, 256-byte aligned) that holds the
     store; otherwise the library allocates it."""
 
     def __init__(self, width: int, height: int, k: int, params: Params | None = None, stream=None, arena=None):
@@ -273,6 +280,26 @@ class Reservoir:
                                                            float(gaze_y), _ptr(out)),
                "fwrs_push_frame_resolve_incremental")
 
+    def step_reproject(self, color, level, motion, depth, gaze_x: float, gaze_y: float, depth_tol: float,
+                       out=None) -> None:
+        """fwrs_push_frame_reproject: one frame with reverse reprojection by `motion` ([H, W, 2]
+        float32 pixels) and the depth flush (`depth` [H, W] float32), resolving into `out` if
+        given.  The context must have been created with FLAG_REPROJECT."""
+        self._check_frame(color, level)
+        H, W = self.height, self.width
+        if tuple(motion.shape) != (H, W, 2) or motion.dtype.itemsize != 4 or not motion.is_contiguous():
+            raise ValueError(f"motion must be contiguous float32 [{H}, {W}, 2]")
+        if tuple(depth.shape) != (H, W) or depth.dtype.itemsize != 4 or not depth.is_contiguous():
+            raise ValueError(f"depth must be contiguous float32 [{H}, {W}]")
+        if not (motion.is_cuda and depth.is_cuda):
+            raise ValueError("motion and depth must be device tensors")
+        if out is not None:
+            self._check_out(out)
+        _check(self._L.fwrs_push_frame_reproject(self._h, _ptr(color), _ptr(level), _ptr(motion), _ptr(depth),
+                                                 float(gaze_x), float(gaze_y), float(depth_tol),
+                                                 _ptr(out) if out is not None else None),
+               "fwrs_push_frame_reproject")
+
     @property
     def frame_index(self) -> int:
         t = C.c_uint32()
@@ -304,8 +331,14 @@ class Reservoir:
     def stats(self) -> tuple[int, int, int]:
         """(slot takes, pixel updates with a take, pixel updates) since creation or reset."""
         a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
-        _check(self._L.fwrs_get_stats(self._h, C.byref(a), C.byref(b), C.byref(c)), "fwrs_get_stats")
+        _check(self._L.fwrs_get_stats(self._h, C.byref(a), C.byref(b), C.byref(c), None), "fwrs_get_stats")
         return int(a.value), int(b.value), int(c.value)
+
+    def flushes(self) -> int:
+        """Reprojected pixel updates whose history was flushed, since creation or reset."""
+        a = C.c_uint64()
+        _check(self._L.fwrs_get_stats(self._h, None, None, None, C.byref(a)), "fwrs_get_stats")
+        return int(a.value)
 
     def sync(self) -> None:
         _check(self._L.fwrs_sync(self._h), "fwrs_sync")

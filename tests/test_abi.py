@@ -69,15 +69,22 @@ def test_default_params_and_sizes():
     assert p.bias_mode == fwrs.BIAS_BERNOULLI
     assert (p.a_k, p.r2k, p.rek) == (pytest.approx(0.9851), pytest.approx(1.058), pytest.approx(22.14))
     N = 3840 * 2160
-    assert fwrs.state_bytes(3840, 2160, 4) == 4 * N * (1 + 20) + 16384      # N is a multiple of 64
+    assert fwrs.state_bytes(3840, 2160, 4) == 4 * N * (1 + 20) + 24576      # N is a multiple of 64
     assert fwrs.state_host_bytes(3840, 2160, 4) == N * (8 + 96)
-    assert fwrs.state_bytes(13, 7, 3) == 4 * 128 * (1 + 15) + 16384        # pitch rounded up to 64
+    assert fwrs.state_bytes(13, 7, 3) == 4 * 128 * (1 + 15) + 24576        # pitch rounded up to 64
     # Eq. 7 keeps one w_sum per slot
+    def prm(**kw):
+        return fwrs.default_params(13, **kw)
     for mode in (fwrs.BIAS_NONE, fwrs.BIAS_BERNOULLI):
-        assert fwrs.state_bytes(13, 7, 3, mode) == fwrs.state_bytes(13, 7, 3)
-    assert fwrs.state_bytes(3840, 2160, 4, fwrs.BIAS_FULL) == 4 * N * (4 + 20) + 16384
-    assert fwrs.state_bytes(13, 7, 3, fwrs.BIAS_FULL) == 4 * 128 * (3 + 15) + 16384
-    assert fwrs.state_bytes(13, 7, 3, 3) == 0
+        assert fwrs.state_bytes(13, 7, 3, prm(bias_mode=mode)) == fwrs.state_bytes(13, 7, 3)
+    assert fwrs.state_bytes(3840, 2160, 4, prm(bias_mode=fwrs.BIAS_FULL)) == 4 * N * (4 + 20) + 24576
+    assert fwrs.state_bytes(13, 7, 3, prm(bias_mode=fwrs.BIAS_FULL)) == 4 * 128 * (3 + 15) + 24576
+    assert fwrs.state_bytes(13, 7, 3, prm(bias_mode=3)) == 0
+    # a reprojecting context keeps two banks, each with a count and a depth per pixel
+    assert fwrs.state_bytes(13, 7, 3, prm(flags=fwrs.FLAG_REPROJECT)) == 2 * 4 * 128 * (1 + 15 + 2) + 24576
+    assert fwrs.state_bytes(13, 7, 3, prm(flags=fwrs.FLAG_REPROJECT, bias_mode=fwrs.BIAS_FULL)) == \
+        2 * 4 * 128 * (3 + 15 + 2) + 24576
+    assert fwrs.state_bytes(13, 7, 3, prm(flags=2)) == 0
     for bad in [(0, 5, 4), (5, 0, 4), (5, 5, 0), (5, 5, 17), (65536, 65536, 1)]:
         assert fwrs.state_bytes(*bad) == 0
 
@@ -90,7 +97,7 @@ def test_invalid_arguments_are_rejected_before_any_gpu_work():
     assert L.fwrs_create(10, 10, 17, C.byref(h)) == fwrs.E_ARG
     assert L.fwrs_create(10, 10, 4, None) == fwrs.E_ARG
     for field, value in [("fov_deg", 0.0), ("fovea_radius_px", float("nan")), ("bias_mode", 7), ("a_k", 1.5),
-                         ("r_m", -1.0), ("rek", float("inf"))]:
+                         ("r_m", -1.0), ("rek", float("inf")), ("flags", 6)]:
         q = fwrs.default_params(64)
         setattr(q, field, value)
         assert L.fwrs_create_ex(64, 64, 4, C.byref(q), None, None, 0, C.byref(h)) == fwrs.E_ARG, field
@@ -102,6 +109,7 @@ def test_invalid_arguments_are_rejected_before_any_gpu_work():
     q.bias_mode = fwrs.BIAS_FULL
     assert L.fwrs_create_ex(64, 64, 4, C.byref(q), None, 256, fwrs.state_bytes(64, 64, 4), C.byref(h)) == fwrs.E_ARG
     assert L.fwrs_push_frame(None, None, None, 0.0, 0.0) == fwrs.E_ARG
+    assert L.fwrs_push_frame_reproject(None, None, None, None, None, 0.0, 0.0, 0.1, None) == fwrs.E_ARG
     assert L.fwrs_resolve(None, None) == fwrs.E_ARG
     assert L.fwrs_destroy(None) == fwrs.OK
     assert L.fwrs_engine_destroy(None) == fwrs.OK

@@ -418,7 +418,7 @@ def test_eq7_caller_arena_is_sized_by_mode(dev):
     small = torch.empty(fwrs.state_bytes(spec.width, spec.height, spec.k), dtype=torch.uint8, device=dev)
     with pytest.raises(fwrs.FwrsError):
         fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream(), arena=small)
-    arena = torch.full((fwrs.state_bytes(spec.width, spec.height, spec.k, fwrs.BIAS_FULL),), 0xAB,
+    arena = torch.full((fwrs.state_bytes(spec.width, spec.height, spec.k, p),), 0xAB,
                        dtype=torch.uint8, device=dev)
     res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream(), arena=arena)
     orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
