@@ -21,6 +21,8 @@ from . import build as _build
 BIAS_NONE = 0
 BIAS_BERNOULLI = 1
 BIAS_FULL = 2
+BIAS_MEMORYLESS = 3
+AES = 4
 
 _lib = None
 
@@ -38,6 +40,7 @@ class Params(C.Structure):
         ("a_k", C.c_float),
         ("r2k", C.c_float),
         ("rek", C.c_float),
+        ("lambda_decay", C.c_float),
     ]
 
 
@@ -102,6 +105,9 @@ def _bind(L):
                                              C.POINTER(C.c_float), C.c_float, C.c_float, C.c_float]
     L.fwrs_oracle_push_reproject.restype = C.c_int
     L.fwrs_oracle_depth.argtypes = [vp, C.POINTER(C.c_float)]
+    L.fwrs_oracle_log2u_many.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_float), C.c_size_t]
+    L.fwrs_oracle_decay.argtypes = [vp]
+    L.fwrs_oracle_decay.restype = C.c_float
     L.fwrs_oracle_flushes.argtypes = [vp]
     L.fwrs_oracle_flushes.restype = C.c_uint64
     return L
@@ -206,6 +212,10 @@ class Oracle:
         self._L.fwrs_oracle_slot_sums(self._h, _ptr(s.wslot, C.c_float))
         return s
 
+    @property
+    def decay(self) -> np.float32:
+        return np.float32(self._L.fwrs_oracle_decay(self._h))
+
     def constants(self) -> dict:
         out = np.empty(9, np.float32)
         self._L.fwrs_oracle_constants(self._h, _ptr(out, C.c_float))
@@ -240,6 +250,14 @@ def philox(keys: np.ndarray, ctrs: np.ndarray) -> np.ndarray:
     n = ctrs.shape[0]
     out = np.empty((n, 4), np.uint32)
     lib().fwrs_oracle_philox_many(_ptr(keys, C.c_uint32), _ptr(ctrs, C.c_uint32), _ptr(out, C.c_uint32), n)
+    return out
+
+
+def log2u(bits: np.ndarray) -> np.ndarray:
+    """log2 of the uniform variate ((bits >> 8) + 1) * 2^-24 (binary32), as A-ES uses it."""
+    bits = np.ascontiguousarray(bits, dtype=np.uint32)
+    out = np.empty(bits.shape, np.float32)
+    lib().fwrs_oracle_log2u_many(_ptr(bits, C.c_uint32), _ptr(out, C.c_float), bits.size)
     return out
 
 

@@ -21,6 +21,10 @@
  *                        the combine
  *   Sec. 4.3, Eq. 7      full temporal bias: Eq. 6 additionally scaled by
  *                        (1 - |dL|), dL from the CIE94 colour difference in Lab
+ *   Sec. 3.1             A-ES (Efraimidis and Spirakis): key rand^(1/w), the
+ *                        largest key is kept; the memory-less temporal bias
+ *                        f(j, i) = exp(-lambda (i - j)) (Aggarwal), both as
+ *                        the ablations Sec. 4.1 and 4.2 argue against
  *   Sec. 4.3             temporal reprojection by motion vectors; a depth
  *                        disagreement between frames (occlusion or
  *                        disocclusion) flushes the reservoir's history
@@ -56,6 +60,14 @@
  *     CIE94 difference (graphic-arts weights, the slot's sample as reference)
  *     of the two colours in CIE Lab (D65), the colours read as linear RGB.
  *     The factors apply left to right: (W1 * (1 - |dL|)) * (1 - w / (W1 + w)).
+ *   - memory-less bias (MEMORYLESS): every past candidate's weight decays by
+ *     exp(-lambda) per frame, so the accumulated w_sum is multiplied by
+ *     exp(-lambda) before the combine: W1' = W1 * exp(-lambda).
+ *   - A-ES (AES): each slot keeps the log2 of its sample's key,
+ *     log2(rand) / w (the logarithm orders keys like rand^(1/w) and does not
+ *     underflow); the candidate replaces the sample iff its key is larger; an
+ *     empty slot has key -infinity.  log2(rand) uses the rand of the slot's
+ *     Philox word, computed by the series below.
  *   - reprojection is reverse and nearest: pixel (x, y) continues the
  *     reservoir of the pixel that contains its centre moved back by its motion
  *     vector, (floor(x + 0.5 - mx), floor(y + 0.5 - my)); that history is kept
@@ -181,6 +193,37 @@ float fwrs_oracle_weight(const fwrs_oracle* o, int x, int y, uint8_t level, floa
 }
 
 /* ------------------------------------------------------------------------ */
+/* log2 of the uniform variate u = ((bits >> 8) + 1) * 2^-24, for A-ES keys.  */
+/* With m = (bits >> 8) + 1 = 2^e * f, f in [sqrt(1/2), sqrt(2)):             */
+/*   log2(u) = (e - 24) + log2(f),                                            */
+/*   log2(f) = (2 / ln 2) atanh(s) = sum_i 2 s^(2i+1) / ((2i+1) ln 2),        */
+/*   s = (f - 1) / (f + 1), |s| < 0.172, six terms.                           */
+/* ------------------------------------------------------------------------ */
+float fwrs_oracle_log2u(uint32_t bits)
+{
+    const uint32_t m = (bits >> 8) + 1u;                 /* 1 .. 2^24 */
+    int e = 0;
+    while ((m >> (e + 1)) != 0u) ++e;                    /* floor(log2 m) */
+    float f = (float)m;
+    for (int i = 0; i < e; ++i) f = f * 0.5f;            /* exact: f in [1, 2) */
+    if (f >= 0x1.6a09e6p+0f) {                           /* sqrt(2) rounded */
+        f = f * 0.5f;
+        e = e + 1;
+    }
+    const float s = (f - 1.0f) / (f + 1.0f);
+    const float z = s * s;
+    float p = 0x1.0c9a84p-2f;                            /* 2 / (11 ln 2) */
+    p = p * z + 0x1.484b14p-2f;                          /* 2 / (9 ln 2) */
+    p = p * z + 0x1.a61762p-2f;                          /* 2 / (7 ln 2) */
+    p = p * z + 0x1.2776c6p-1f;                          /* 2 / (5 ln 2) */
+    p = p * z + 0x1.ec709ep-1f;                          /* 2 / (3 ln 2) */
+    p = p * z + 0x1.715476p+1f;                          /* 2 / ln 2 */
+    return (float)(e - 24) + s * p;
+}
+
+float fwrs_oracle_decay(const fwrs_oracle* o) { return o->decay; }
+
+/* ------------------------------------------------------------------------ */
 /* Colour difference for Eq. 7.                                               */
 /* ------------------------------------------------------------------------ */
 /* Cube root for t > 0: a seed from the exponent bits (the bit pattern of     */
@@ -269,6 +312,7 @@ void fwrs_oracle_default_params(int width, fwrs_oracle_params* p)
     p->a_k = 0.9851f;      /* Sec. 4.1, parameters of Eq. 3 */
     p->r2k = 1.058f;
     p->rek = 22.14f;
+    p->lambda_decay = 0.0231f;   /* not given in the paper: a 30-frame half-life */
 }
 
 static void derive_constants(fwrs_oracle* o)
@@ -285,6 +329,13 @@ static void derive_constants(fwrs_oracle* o)
     float num, den;
     density_terms(o, o->rf, &num, &den);
     o->Drf = num / den;
+    o->decay = fwrs_oracle_exp2p(-(p->lambda_decay * 1.44269504088896341f));   /* exp(-lambda) */
+}
+
+/* The per-slot value of an empty slot: w_sum 0 (Eq. 7), key -infinity (A-ES). */
+static float empty_slot_sum(const fwrs_oracle* o)
+{
+    return o->prm.bias_mode == FWRS_ORACLE_AES ? -INFINITY : 0.0f;
 }
 
 fwrs_oracle* fwrs_oracle_create(int width, int height, int k, const fwrs_oracle_params* p)
@@ -302,15 +353,18 @@ fwrs_oracle* fwrs_oracle_create(int width, int height, int k, const fwrs_oracle_
     o->wt = (float*)calloc(n * (size_t)k, sizeof(float));
     o->idx = (uint32_t*)malloc(n * (size_t)k * sizeof(uint32_t));
     o->col = (float*)calloc(n * (size_t)k * 3, sizeof(float));
-    if (o->prm.bias_mode == FWRS_ORACLE_BIAS_FULL) o->wslot = (float*)calloc(n * (size_t)k, sizeof(float));
+    const int per_slot = o->prm.bias_mode == FWRS_ORACLE_BIAS_FULL || o->prm.bias_mode == FWRS_ORACLE_AES;
+    if (per_slot) o->wslot = (float*)malloc(n * (size_t)k * sizeof(float));
     o->depth = (float*)malloc(n * sizeof(float));
     if (!o->wsum || !o->cnt || !o->wt || !o->idx || !o->col || !o->depth ||
-        (o->prm.bias_mode == FWRS_ORACLE_BIAS_FULL && !o->wslot)) {
+        (per_slot && !o->wslot)) {
         fwrs_oracle_destroy(o);
         return NULL;
     }
     for (size_t i = 0; i < n * (size_t)k; ++i) o->idx[i] = 0xFFFFFFFFu;   /* empty slot */
     for (size_t i = 0; i < n; ++i) o->depth[i] = NAN;                     /* no previous frame */
+    if (per_slot)
+        for (size_t i = 0; i < n * (size_t)k; ++i) o->wslot[i] = empty_slot_sum(o);
     derive_constants(o);
     return o;
 }
@@ -336,6 +390,32 @@ static void update_pixel(const fwrs_oracle* o, int x, int y, uint32_t p, uint32_
 {
     const int k = o->k;
     float w = fwrs_oracle_weight(o, x, y, level, gx, gy);
+    if (o->prm.bias_mode == FWRS_ORACLE_AES) {
+        /* A-ES per slot: the larger key rand^(1/w) wins, compared as log2(rand) / w. */
+        uint32_t key[2] = {o->prm.seed, o->prm.stream_id};
+        uint32_t words[4];
+        int have_block = -1;
+        for (int j = 0; j < k; ++j) {
+            int b = j / 4;
+            if (b != have_block) {
+                uint32_t ctr[4] = {p, t, (uint32_t)b, 0u};
+                fwrs_oracle_philox(key, ctr, words);
+                have_block = b;
+            }
+            float kn = fwrs_oracle_log2u(words[j % 4]) / w;
+            if (kn > wslot[(size_t)j * n]) {
+                col[((size_t)j * 3 + 0) * n] = rgb[0];
+                col[((size_t)j * 3 + 1) * n] = rgb[1];
+                col[((size_t)j * 3 + 2) * n] = rgb[2];
+                wt[(size_t)j * n] = w;
+                idx[(size_t)j * n] = t;
+                wslot[(size_t)j * n] = kn;
+            }
+        }
+        *wsum = 0.0f;
+        *cnt = *cnt + 1u;
+        return;
+    }
     if (o->prm.bias_mode == FWRS_ORACLE_BIAS_FULL) {
         /* Eq. 7 per slot: the slot's own w_sum, biased by its colour difference
          * to the new pixel and by the survival probability; then Alg. 2. */
@@ -379,6 +459,8 @@ static void update_pixel(const fwrs_oracle* o, int x, int y, uint32_t p, uint32_
         float q = w / total;           /* chance that R2 replaces R1, Eq. 5 */
         float survive = 1.0f - q;      /* Eq. 5 */
         W1b = W1 * survive;            /* Eq. 6 */
+    } else if (o->prm.bias_mode == FWRS_ORACLE_BIAS_MEMORYLESS) {
+        W1b = W1 * o->decay;           /* every past weight times exp(-lambda) */
     }
     float s = W1b + w;                 /* Alg. 2: R_out.w_sum */
 
@@ -501,7 +583,7 @@ int fwrs_oracle_push_reproject(fwrs_oracle* o, const float* color, const uint8_t
                     wt[(size_t)j * n + p] = 0.0f;
                     idx[(size_t)j * n + p] = 0xFFFFFFFFu;
                     for (int c = 0; c < 3; ++c) col[((size_t)j * 3 + c) * n + p] = 0.0f;
-                    if (wslot) wslot[(size_t)j * n + p] = 0.0f;
+                    if (wslot) wslot[(size_t)j * n + p] = empty_slot_sum(o);
                 }
                 o->flushes += 1u;
             }
@@ -599,6 +681,11 @@ void fwrs_oracle_de94_many(const float* ref, const float* x, float* out, size_t 
     for (size_t i = 0; i < count; ++i) out[i] = fwrs_oracle_de94(ref + 3 * i, x + 3 * i);
 }
 
+void fwrs_oracle_log2u_many(const uint32_t* bits, float* out, size_t count)
+{
+    for (size_t i = 0; i < count; ++i) out[i] = fwrs_oracle_log2u(bits[i]);
+}
+
 void fwrs_oracle_exp2p_many(const float* y, float* out, size_t count)
 {
     for (size_t i = 0; i < count; ++i) out[i] = fwrs_oracle_exp2p(y[i]);
@@ -640,7 +727,7 @@ int fwrs_oracle_trials(int width, int height, int k, const fwrs_oracle_params* p
         o->wsum[0] = 0.0f;
         o->cnt[0] = 0u;
         for (int j = 0; j < k; ++j) {
-            if (o->wslot) o->wslot[j] = 0.0f;
+            if (o->wslot) o->wslot[j] = empty_slot_sum(o);
             o->wt[j] = 0.0f;
             o->idx[j] = 0xFFFFFFFFu;
             o->col[3 * j + 0] = o->col[3 * j + 1] = o->col[3 * j + 2] = 0.0f;

@@ -30,6 +30,8 @@ extern "C" {
 #define FWRS_ORACLE_BIAS_NONE 0u
 #define FWRS_ORACLE_BIAS_BERNOULLI 1u
 #define FWRS_ORACLE_BIAS_FULL 2u      /* Eq. 7: Eq. 6 times (1 - |dL|), per-slot w_sum */
+#define FWRS_ORACLE_BIAS_MEMORYLESS 3u   /* Sec. 3.1 memory-less bias: w_sum * exp(-lambda) per frame */
+#define FWRS_ORACLE_AES 4u            /* Sec. 3.1 A-ES: keys rand^(1/w), per-slot key, no w_sum */
 
 typedef struct fwrs_oracle_params {
     uint32_t seed;            /* Philox key word 0 */
@@ -38,6 +40,7 @@ typedef struct fwrs_oracle_params {
     float fovea_radius_px;    /* r_f in pixels */
     uint32_t bias_mode;       /* FWRS_ORACLE_BIAS_* */
     float r_m, a_k, r2k, rek; /* Eq. 3 parameters */
+    float lambda_decay;       /* memory-less bias rate per frame */
 } fwrs_oracle_params;
 
 typedef struct fwrs_oracle {
@@ -45,12 +48,13 @@ typedef struct fwrs_oracle {
     fwrs_oracle_params prm;
     uint32_t t;
     float A, B, IR2, IRM, C, ppd, iPPD, rf, Drf;
+    float decay;    /* exp(-lambda_decay), the memory-less factor per frame */
     float* wsum;
     uint32_t* cnt;
     float* wt;
     uint32_t* idx;
     float* col;
-    float* wslot;   /* [k][N] per-slot w_sum (BIAS_FULL only; NULL otherwise) */
+    float* wslot;   /* [k][N] per-slot w_sum (BIAS_FULL) or log2 key (AES); NULL otherwise */
     float* depth;   /* [N] previous reprojected frame's depth */
     uint64_t flushes;   /* reprojected pixel-updates that started from an empty reservoir */
 } fwrs_oracle;
@@ -72,6 +76,9 @@ int fwrs_oracle_push_reproject(fwrs_oracle* o, const float* color, const uint8_t
 void fwrs_oracle_depth(const fwrs_oracle* o, float* depth);
 uint64_t fwrs_oracle_flushes(const fwrs_oracle* o);
 
+float fwrs_oracle_log2u(uint32_t bits);
+void fwrs_oracle_log2u_many(const uint32_t* bits, float* out, size_t count);
+float fwrs_oracle_decay(const fwrs_oracle* o);
 float fwrs_oracle_cbrt(float t);
 void fwrs_oracle_lab(float r, float g, float b, float lab[3]);
 float fwrs_oracle_de94(const float ref[3], const float x[3]);

@@ -40,7 +40,8 @@ MUTANTS = {
     "stored_wsum_unbiased": ("*wsum = s;", "*wsum = W1 + w;"),
     "count_not_incremented": ("*cnt = *cnt + 1u;", "*cnt = *cnt;"),
     "colour_channels_mixed": ("col[((size_t)j * 3 + 1) * n] = rgb[1];", "col[((size_t)j * 3 + 1) * n] = rgb[0];"),
-    "stored_weight_is_wsum": ("wt[(size_t)j * n] = w;", "wt[(size_t)j * n] = s;"),
+    "stored_weight_is_wsum": ("            wt[(size_t)j * n] = w;\n            idx[(size_t)j * n] = t;\n        }\n    }",
+                              "            wt[(size_t)j * n] = s;\n            idx[(size_t)j * n] = t;\n        }\n    }"),
     "resolve_unnormalised": ("out[3 * p + c] = acc / total;", "out[3 * p + c] = acc;"),
     "resolve_wrong_slot_weight": ("acc += (double)o->wt[(size_t)j * n + p] *", "acc += (double)o->wt[p] *"),
     "eq7_colour_factor_dropped": ("float W1b = (W1 * (1.0f - dl)) * survive;", "float W1b = W1 * survive;"),
@@ -62,6 +63,15 @@ MUTANTS = {
     "flush_keeps_wsum": ("                wsum[p] = 0.0f;\n", "                wsum[p] = o->wsum[p];\n"),
     "history_from_own_pixel": ("wsum[p] = o->wsum[q];", "wsum[p] = o->wsum[p];"),
     "depth_not_stored": ("dnew[p] = depth[p];", "dnew[p] = o->depth[p];"),
+    "aes_key_times_weight": ("float kn = fwrs_oracle_log2u(words[j % 4]) / w;",
+                             "float kn = fwrs_oracle_log2u(words[j % 4]) * w;"),
+    "aes_empty_key_zero": ("return o->prm.bias_mode == FWRS_ORACLE_AES ? -INFINITY : 0.0f;",
+                           "return o->prm.bias_mode == FWRS_ORACLE_AES ? 0.0f : 0.0f;"),
+    "log2_series_coefficient": ("p = p * z + 0x1.ec709ep-1f;", "p = p * z + 0x1.ec709ep-2f;"),
+    "log2_range_reduction_exponent": ("        e = e + 1;\n", "        e = e + 0;\n"),
+    "memoryless_decay_twice": ("W1b = W1 * o->decay;", "W1b = (W1 * o->decay) * o->decay;"),
+    "decay_rate_not_natural": ("o->decay = fwrs_oracle_exp2p(-(p->lambda_decay * 1.44269504088896341f));",
+                               "o->decay = fwrs_oracle_exp2p(-(p->lambda_decay));"),
 }
 
 
@@ -79,7 +89,8 @@ def _run_mutant(name, tmpdir):
     env = dict(os.environ, FWRS_ORACLE_LIB=lib, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_oracle_eq7.py"),
-                        os.path.join(HERE, "test_oracle_reproject.py")],
+                        os.path.join(HERE, "test_oracle_reproject.py"),
+                        os.path.join(HERE, "test_oracle_ablations.py")],
                        cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=600)
     return name, r.returncode, r.stdout[-400:]
