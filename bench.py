@@ -284,6 +284,62 @@ def reprojection(dev, stream, spec, steps: int, warmup: int, ring: int, tile) ->
                          "frac": ach / HBM_PEAK_GBPS, "kernel_ms_avg": kern, "bytes_per_pixel_update": B}}
 
 
+ABLATION_MODES = (("none", 0), ("bernoulli", 1), ("full_eq7", 2), ("memoryless", 3), ("aes", 4))
+
+
+def ablations(dev, stream, spec, frames, tile, sample_every: int = 10) -> dict:
+    """The update rules side by side on the headline frames (4K, k = 4, static camera): A-Chao
+    without bias, with the Bernoulli bias (Eq. 6), with Eq. 7, with the memory-less bias, and
+    A-ES.  Per mode: the fused pass's time per frame (one pass, per-launch HIP events), and in a
+    second pass the retention of full-fidelity samples -- over the pixels that have been inside
+    the fovea at some frame but are outside it now, the fraction of slots still holding a
+    level-0 sample (weight 1) -- sampled every `sample_every` frames from the store in a
+    caller-owned arena."""
+    import numpy as np
+    import torch
+
+    from paper_2510_03964_amd import fwrs, synth
+
+    out = torch.empty((spec.height, spec.width, 3), dtype=torch.float32, device=dev)
+    N, k = spec.pixels, spec.k
+    result = {}
+    for name, mode in ABLATION_MODES:
+        p = fwrs.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED,
+                                bias_mode=mode)
+        arena = torch.empty(fwrs.state_bytes(spec.width, spec.height, k, p), dtype=torch.uint8, device=dev)
+        res = fwrs.Reservoir(spec.width, spec.height, k, p, stream=stream, arena=arena)
+        if tile:
+            res.set_tile(*tile)
+        total_ms, per = timed_run(res, frames, out, stream, res.step)
+        res.reset()
+        view = res.state_view()
+        ws = view.wsum_slots
+        wt = arena.view(torch.float32)[ws * view.pitch: ws * view.pitch + 4 * k * N].view(N, k, 4)[:, :, 0]
+        ever = torch.zeros(N, dtype=torch.bool, device=dev)
+        fracs = []
+        for t, (c, lev, gx, gy) in enumerate(frames):
+            res.step(c, lev, gx, gy, out)
+            l0 = lev.view(-1) == 0
+            ever |= l0
+            if (t + 1) % sample_every == 0:
+                sel = ever & ~l0
+                n_sel = int(sel.sum())
+                if n_sel:
+                    fracs.append(float((wt[sel] == 1.0).float().mean()))
+        torch.cuda.synchronize()
+        res.close()
+        del arena
+        result[name] = {"bias_mode": mode, "ms_per_frame": total_ms / len(frames),
+                        "kernel_ms_avg": float(per.mean()),
+                        "level0_retention_mean": float(np.mean(fracs)) if fracs else None,
+                        "level0_retention_last": fracs[-1] if fracs else None}
+        log(f"ablation {name}: {total_ms / len(frames):.4f} ms/frame, level-0 retention "
+            f"{result[name]['level0_retention_mean']:.4f}")
+    result["definition"] = ("fraction of slots holding a weight-1 (level-0) sample over the pixels that were "
+                            f"in the fovea earlier but are not now, sampled every {sample_every} frames")
+    return result
+
+
 def cpu_baseline(frames_host, spec, n_frames: int) -> dict:
     import oracle
 
@@ -328,6 +384,7 @@ def main() -> int:
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth reference")
     ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-resolve run")
     ap.add_argument("--no-eq7", action="store_true", help="skip the Eq. 7 (full temporal bias) run")
+    ap.add_argument("--no-ablations", action="store_true", help="skip the update-rule comparison")
     ap.add_argument("--no-reproject", action="store_true", help="skip the moving-camera (reprojection) run")
     ap.add_argument("--reproject-ring", type=int, default=240, help="distinct moving frames kept resident")
     ap.add_argument("--no-multistream", action="store_true", help="skip the batched-vs-plain runs")
@@ -446,6 +503,8 @@ def main() -> int:
                        "slot_takes_per_pixel_update": f_rbar}}
         log(f"eq7: {f_ms / K:.4f} ms/frame")
 
+    ablation = None if args.no_ablations else ablations(dev, stream, spec, frames, tile)
+
     copy_gbps = None if args.no_copy else copy_bandwidth(torch, dev)
 
     host = [(c.cpu().numpy(), lev.cpu().numpy(), gx, gy) for (c, lev, gx, gy) in frames[:args.cpu_frames]]
@@ -511,6 +570,7 @@ def main() -> int:
         "incremental": incremental,
         "eq7": eq7,
         "reproject": reproject,
+        "ablations": ablation,
         "multistream": multi,
         "serving": served,
         "copy_gbps": copy_gbps,

@@ -72,6 +72,16 @@ extern "C" {
  * CIE Lab (D65 white, linear sRGB primaries) between the slot's sample
  * (reference) and the new pixel. */
 #define FWRS_BIAS_FULL 2u
+/* Ablations the paper argues against (Sec. 3.1, 4.1, 4.2):
+ * memory-less bias: every past candidate's weight decays by exp(-lambda) per
+ * frame, i.e. R1.w_sum *= exp(-lambda_decay) before Alg. 2; */
+#define FWRS_BIAS_MEMORYLESS 3u
+/* A-ES (Efraimidis-Spirakis) instead of A-Chao: each slot keeps its sample's
+ * key rand^(1/w), stored as log2(rand) / w (-infinity when empty), and the
+ * candidate replaces it when its key is larger; there is no w_sum.  rand is
+ * the slot's variate above; log2 is a fixed binary32 series, so keys are
+ * reproducible bit for bit. */
+#define FWRS_AES 4u
 
 /* Largest slot count per pixel. */
 #define FWRS_MAX_K 16
@@ -92,6 +102,9 @@ extern "C" {
  *                     (Sec. 4.1 prints a_k = 0.9851, r_2,k = 1.058,
  *                     r_e,k = 22.14; r_m is not printed, default 41.03).
  *   flags             FWRS_FLAG_* (0 by default).
+ *   lambda_decay      the memory-less bias rate per frame (FWRS_BIAS_MEMORYLESS;
+ *                     not given in the paper; default 0.0231, a 30-frame
+ *                     half-life).
  */
 typedef struct fwrs_params {
     uint32_t seed;
@@ -104,6 +117,7 @@ typedef struct fwrs_params {
     float r2k;
     float rek;
     uint32_t flags;
+    float lambda_decay;
 } fwrs_params;
 
 typedef struct fwrs_ctx fwrs_ctx;
@@ -112,7 +126,8 @@ typedef struct fwrs_ctx fwrs_ctx;
  * p = y * width + x.
  *   wsum[p]                  float32  w_sum of the pixel's reservoir (Alg. 2);
  *                                     under FWRS_BIAS_FULL wsum[p*k + j] is
- *                                     slot j's own w_sum (wsum_slots = k)
+ *                                     slot j's own w_sum, under FWRS_AES its
+ *                                     key (wsum_slots = k)
  *   rec[(p*k + j)*4 + 0]     float32  render-time weight of slot j's sample
  *   rec[(p*k + j)*4 + 1..3]  float32  its colour (r, g, b)
  *   idx[p*k + j]             uint32   frame index of slot j's sample
@@ -136,7 +151,7 @@ typedef struct fwrs_state_view {
     float* wsum;
     float* rec;
     uint32_t* idx;
-    int wsum_slots;         /* 1, or k under FWRS_BIAS_FULL */
+    int wsum_slots;         /* 1, or k under FWRS_BIAS_FULL and FWRS_AES */
     uint32_t* cnt;
     float* depth;
 } fwrs_state_view;
@@ -153,8 +168,8 @@ int fwrs_default_params(int width, fwrs_params* p);
  * to size a caller-provided arena.  Returns 0 for invalid sizes. */
 size_t fwrs_state_bytes(int width, int height, int k);
 
-/* As fwrs_state_bytes for given parameters: FWRS_BIAS_FULL keeps one w_sum
- * per slot (4 * pitch * 6k), FWRS_FLAG_REPROJECT two banks, each with a
+/* As fwrs_state_bytes for given parameters: FWRS_BIAS_FULL and FWRS_AES keep
+ * one value per slot (4 * pitch * 6k), FWRS_FLAG_REPROJECT two banks, each with a
  * count and a depth per pixel (2 * 4 * pitch * (s + 5k + 2), s = 1 or k),
  * plus the statistics area.  Returns 0 for invalid sizes or parameters. */
 size_t fwrs_state_bytes_params(int width, int height, int k, const fwrs_params* params);
@@ -177,7 +192,8 @@ int fwrs_create(int width, int height, int k, fwrs_ctx** out);
  * NULL the library allocates.  The arena is cleared on the stream.
  * FWRS_E_ARG also for: params NULL, fov_deg or fovea_radius_px not finite and
  * > 0, bias_mode unknown, a_k outside (0, 1], r_m, r2k or rek not finite and
- * > 0, unknown flags, arena too small or misaligned. */
+ * > 0, lambda_decay negative or not finite, unknown flags, arena too small or
+ * misaligned. */
 int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void* hip_stream, void* arena,
                    size_t arena_bytes, fwrs_ctx** out);
 
@@ -258,8 +274,8 @@ int fwrs_get_state(const fwrs_ctx* ctx, fwrs_state_view* view);
 /* Synchronises the stream and copies the store to host memory, packed
  * without padding in the order wsum[N], cnt[N], wt[k][N], idx[k][N],
  * col[k][3][N], wslot[k][N] (N = width * height; cnt[p] = m = frame_index;
- * wslot[j][p] = slot j's w_sum: its own under FWRS_BIAS_FULL, where wsum[p]
- * is 0, else wsum[p] for every j).  `host_bytes` must equal
+ * wslot[j][p] = slot j's w_sum: its own under FWRS_BIAS_FULL, its key under
+ * FWRS_AES -- in both wsum[p] is 0 -- else wsum[p] for every j).  `host_bytes` must equal
  * fwrs_state_host_bytes(...). */
 int fwrs_download_state(fwrs_ctx* ctx, void* host, size_t host_bytes);
 

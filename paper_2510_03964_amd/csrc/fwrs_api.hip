@@ -43,8 +43,8 @@ bool params_ok(const fwrs_params* p)
 {
     if (!p) return false;
     if (!finite_pos(p->fov_deg) || !finite_pos(p->fovea_radius_px)) return false;
-    if (p->bias_mode != FWRS_BIAS_NONE && p->bias_mode != FWRS_BIAS_BERNOULLI && p->bias_mode != FWRS_BIAS_FULL)
-        return false;
+    if (p->bias_mode > FWRS_AES) return false;
+    if (!std::isfinite(p->lambda_decay) || p->lambda_decay < 0.0f) return false;
     if (!(p->a_k > 0.0f && p->a_k <= 1.0f)) return false;
     if ((p->flags & ~(uint32_t)FWRS_FLAG_REPROJECT) != 0u) return false;
     return finite_pos(p->r_m) && finite_pos(p->r2k) && finite_pos(p->rek);
@@ -55,7 +55,7 @@ bool params_ok(const fwrs_params* p)
 // reprojecting context the pixel counts and depths.
 size_t bank_elems(size_t pitch, size_t k, uint32_t bias_mode, uint32_t flags)
 {
-    const size_t ws = bias_mode == FWRS_BIAS_FULL ? k : 1;
+    const size_t ws = fwrs::per_slot_mode(bias_mode) ? k : 1;
     const size_t extra = (flags & FWRS_FLAG_REPROJECT) ? 2 : 0;
     return pitch * (ws + 5 * k + extra);
 }
@@ -75,6 +75,7 @@ fwrs::Consts derive(const fwrs_params& p, int width)
     float num, den;
     fwrs::density_terms(c, c.rf, num, den);
     c.Drf = num / den;
+    c.decay = fwrs::exp2_neg(-(p.lambda_decay * 1.44269504088896341f));   // exp(-lambda)
     return c;
 }
 
@@ -146,9 +147,12 @@ namespace {
 int clear_store(fwrs_ctx* x)
 {
     const size_t P = x->pitch, k = (size_t)x->k;
-    // wsum and the slot records are contiguous and start out zero; idx starts empty.
-    if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->wsum), P * (x->wsum_slots + 4 * k), 0u, x->stream) !=
-        hipSuccess)
+    // wsum and the slot records are contiguous and start out zero (A-ES keys:
+    // -infinity); idx starts empty.
+    const bool aes = x->prm.bias_mode == FWRS_AES;
+    if (fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->wsum), P * x->wsum_slots, aes ? 0xFF800000u : 0u,
+                              x->stream) != hipSuccess ||
+        fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->rec), P * 4 * k, 0u, x->stream) != hipSuccess)
         return FWRS_E_HIP;
     if (fwrs::launch_fill_u32(x->idx, P * k, 0xFFFFFFFFu, x->stream) != hipSuccess) return FWRS_E_HIP;
     if (x->reproject) {
@@ -243,6 +247,7 @@ int fwrs_default_params(int width, fwrs_params* p)
     p->r2k = 1.058f;
     p->rek = 22.14f;
     p->flags = 0u;
+    p->lambda_decay = 0.0231f;
     return FWRS_OK;
 }
 
@@ -283,7 +288,7 @@ int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void
     x->c = derive(*params, width);
     x->stream = (hipStream_t)hip_stream;
     x->pitch = pitch_for(width, height);
-    x->wsum_slots = params->bias_mode == FWRS_BIAS_FULL ? (size_t)k : 1;
+    x->wsum_slots = fwrs::per_slot_mode(params->bias_mode) ? (size_t)k : 1;
     x->reproject = (params->flags & FWRS_FLAG_REPROJECT) != 0u;
     if (arena) {
         x->arena = arena;
@@ -486,7 +491,7 @@ int fwrs_download_state(fwrs_ctx* x, void* host, size_t host_bytes)
     }
     // per-slot sums [k][N]: Eq. 7's own ([N][k] on the device; the shared
     // w_sum is then 0), else the shared w_sum repeated for every slot
-    const bool per_slot = x->prm.bias_mode == FWRS_BIAS_FULL;
+    const bool per_slot = fwrs::per_slot_mode(x->prm.bias_mode);
     for (size_t p = 0; p < N; ++p) wsum[p] = per_slot ? 0.0f : sums[p];
     for (size_t j = 0; j < k; ++j)
         for (size_t p = 0; p < N; ++p) wslot[j * N + p] = per_slot ? sums[p * k + j] : sums[p];

@@ -24,6 +24,7 @@ struct Consts {
     float iPPD;  // degrees per pixel = fov_deg / width (as 1 / (width / fov_deg))
     float rf;    // foveal radius in degrees = fovea_radius_px / ppd
     float Drf;   // density at r_f (normalisation of Eq. 4)
+    float decay; // exp(-lambda): the memory-less bias factor per frame
 };
 
 // Everything one frame of one context needs on the device.  Passed by value
@@ -66,6 +67,14 @@ constexpr int kStatSlots = 1024;        // spread of the slot-take counters
 constexpr uint32_t kBiasNone = 0u;
 constexpr uint32_t kBiasBernoulli = 1u;
 constexpr uint32_t kBiasFull = 2u;      // Eq. 7: per-slot w_sum scaled by (1 - |dL|) and Eq. 6
+constexpr uint32_t kBiasMemoryless = 3u;  // w_sum * exp(-lambda) per frame (Sec. 3.1)
+constexpr uint32_t kAes = 4u;           // A-ES keys (Sec. 3.1), one per slot, no w_sum
+
+// Modes that keep one value per slot instead of one w_sum per pixel.
+__host__ __device__ __forceinline__ bool per_slot_mode(uint32_t mode)
+{
+    return mode == kBiasFull || mode == kAes;
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11).  Counter (x0..x3),
@@ -162,13 +171,39 @@ __device__ __forceinline__ float weight_eq4(const Consts& c, float dist2, uint32
     return select_eq4(c, o, e, level);
 }
 
-// Eq. 5-6: R1.w_sum scaled by the survival probability 1 - w / (R1.w_sum + w).
-__device__ __forceinline__ float bias_eq6(float W1, float w, uint32_t mode)
+// The bias of a shared w_sum: Eq. 5-6 scale R1.w_sum by the survival
+// probability 1 - w / (R1.w_sum + w) (BERNOULLI); the memory-less bias by
+// exp(-lambda) (MEMORYLESS); NONE leaves it.
+__device__ __forceinline__ float bias_shared(float W1, float w, uint32_t mode, float decay)
 {
+    if (mode == kBiasMemoryless) return W1 * decay;
     const float total = W1 + w;
     const float q = w / total;
     const float survive = 1.0f - q;
     return mode == kBiasBernoulli ? W1 * survive : W1;
+}
+
+// log2 of the variate ((bits >> 8) + 1) 2^-24 for A-ES keys: m = (bits >> 8) + 1
+// = 2^e f with f in [sqrt(1/2), sqrt(2)); log2 f = (2 / ln 2) atanh(s),
+// s = (f - 1) / (f + 1), as the odd series to s^11 (|s| < 0.172).
+__device__ __forceinline__ float log2_unit(uint32_t bits)
+{
+    const uint32_t m = (bits >> 8) + 1u;
+    int e = 31 - __clz(m);
+    float f = ldexpf((float)m, -e);              // exact, [1, 2)
+    if (f >= 0x1.6a09e6p+0f) {
+        f = f * 0.5f;
+        e = e + 1;
+    }
+    const float s = (f - 1.0f) / (f + 1.0f);
+    const float z = s * s;
+    float p = 0x1.0c9a84p-2f;                    // 2 / (11 ln 2)
+    p = p * z + 0x1.484b14p-2f;                  // 2 / (9 ln 2)
+    p = p * z + 0x1.a61762p-2f;                  // 2 / (7 ln 2)
+    p = p * z + 0x1.2776c6p-1f;                  // 2 / (5 ln 2)
+    p = p * z + 0x1.ec709ep-1f;                  // 2 / (3 ln 2)
+    p = p * z + 0x1.715476p+1f;                  // 2 / ln 2
+    return (float)(e - 24) + s * p;
 }
 
 // ---------------------------------------------------------------------------

@@ -184,7 +184,7 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
     float w = 0.f;
     if (kUpdates) {
         w = select_eq4(d.c, outside, e, lv);
-        const float W1b = bias_eq6(W1, w, d.bias);
+        const float W1b = bias_shared(W1, w, d.bias, d.c.decay);
         const float s = W1b + w;
         tk = K ? decide_words<K ? K : 1>(words, W1b, s) : decide_any(d, p, W1b, s);
         st<kNtWsumSt>(d.wsum + p, s);
@@ -258,14 +258,16 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
 }
 
 // ---------------------------------------------------------------------------
-// One pixel under Eq. 7 (bias mode FULL): every slot keeps its own w_sum,
-// wslot[p * k + j], biased by the slot's colour difference to the new pixel
-// before its Alg. 2 decision.  Needs the new colour for every pixel (each slot
-// compares against it) and every slot's colour, so the records are read by
-// every op that updates.  Same store layout otherwise.
+// One pixel under a per-slot mode, one value per slot in wslot[p * k + j]:
+//  - Eq. 7 (FULL): the slot's own w_sum, biased by the slot's colour
+//    difference to the new pixel before its Alg. 2 decision;
+//  - A-ES: the log2 key of the slot's sample; the candidate's key log2(u) / w
+//    replaces it when larger (Sec. 3.1).
+// Needs the new colour for every pixel and every slot's record, so the records
+// are read by every op that updates.  Same store layout otherwise.
 // ---------------------------------------------------------------------------
 template <int K, int OP>
-__device__ __forceinline__ uint32_t pixel_eq7(const FrameDesc& d, uint32_t x, uint32_t y)
+__device__ __forceinline__ uint32_t pixel_per_slot(const FrameDesc& d, uint32_t x, uint32_t y)
 {
     const uint32_t p = y * d.width + x;
     const int kk = K ? K : (int)d.k;
@@ -304,7 +306,9 @@ __device__ __forceinline__ uint32_t pixel_eq7(const FrameDesc& d, uint32_t x, ui
     const float dx = ((float)x + 0.5f) - d.gx;
     const float dy = ((float)y + 0.5f) - d.gy;
     const float w = weight_eq4(d.c, dx * dx + dy * dy, lv);
-    const float3 lab_new = rgb_to_lab(c0, c1, c2);
+    const bool aes = d.bias == kAes;
+    float3 lab_new = make_float3(0.f, 0.f, 0.f);
+    if (!aes) lab_new = rgb_to_lab(c0, c1, c2);
     const float4 fresh = make_float4(w, c0, c1, c2);
 
     float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
@@ -316,11 +320,21 @@ __device__ __forceinline__ uint32_t pixel_eq7(const FrameDesc& d, uint32_t x, ui
         const float W1 = K ? W[K ? j : 0] : ld<kNtWsumLd>(wslot + j);
         if ((j & 3) == 0) words = philox4x32_10(p, d.t, (uint32_t)(j >> 2), 0u, d.seed, d.stream_id);
         const uint32_t word = (j & 3) == 0 ? words.x : (j & 3) == 1 ? words.y : (j & 3) == 2 ? words.z : words.w;
-        // Eq. 7 against this slot's sample, then the slot's Alg. 2 decision
-        const float dl = fminf(1.0f, cie94(rgb_to_lab(v.y, v.z, v.w), lab_new) / 100.0f);
-        const float W1b = bias_eq7(W1, w, dl);
-        const float s = W1b + w;
-        if (unit_variate(word) * s > W1b) {
+        bool take;
+        float s;
+        if (aes) {
+            // A-ES: the larger key log2(u) / w wins; the slot keeps its sample's key
+            const float kn = log2_unit(word) / w;
+            take = kn > W1;
+            s = take ? kn : W1;
+        } else {
+            // Eq. 7 against this slot's sample, then the slot's Alg. 2 decision
+            const float dl = fminf(1.0f, cie94(rgb_to_lab(v.y, v.z, v.w), lab_new) / 100.0f);
+            const float W1b = bias_eq7(W1, w, dl);
+            s = W1b + w;
+            take = unit_variate(word) * s > W1b;
+        }
+        if (take) {
             tk |= 1u << j;
             v = fresh;
             st4<kNtRecSt>(rec + j, fresh);
@@ -359,7 +373,7 @@ __device__ __forceinline__ uint32_t pixel_eq7(const FrameDesc& d, uint32_t x, ui
 // One work item (256 pixels).  The wave index is made explicit as a uniform
 // value so the tile arithmetic runs on the scalar unit.
 // ---------------------------------------------------------------------------
-template <int K, int OP, bool EQ7 = false>
+template <int K, int OP, bool PER_SLOT = false>
 __device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t item)
 {
     const uint32_t tid = threadIdx.x;
@@ -375,7 +389,7 @@ __device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t it
     const uint32_t x = (tx << d.tile_x_log2) + (local & ((1u << d.tile_x_log2) - 1u));
     const uint32_t y = (ty << d.tile_y_log2) + (local >> d.tile_x_log2);
     if (y >= d.height || x >= d.width) return 0u;
-    if constexpr (EQ7) return pixel_eq7<K, OP>(d, x, y);
+    if constexpr (PER_SLOT) return pixel_per_slot<K, OP>(d, x, y);
     return pixel<K, OP>(d, x, y);
 }
 
@@ -394,10 +408,10 @@ __device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t v)
     }
 }
 
-template <int K, int OP, bool EQ7 = false>
+template <int K, int OP, bool PER_SLOT = false>
 __global__ __launch_bounds__(kBlock) void frame_kernel(FrameDesc d)
 {
-    const uint32_t n = process_item<K, OP, EQ7>(d, blockIdx.x);
+    const uint32_t n = process_item<K, OP, PER_SLOT>(d, blockIdx.x);
     if ((OP == kPush || OP == kFused || OP == kIncremental) && d.stats) add_stats(d.stats, n);
 }
 
@@ -420,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void tick_kernel(const TickArgs a)
     const FrameDesc& d = a.descs[lo];
     const uint32_t local = item - a.begins[lo];
     uint32_t n;
-    if (d.bias == kBiasFull) {
+    if (per_slot_mode(d.bias)) {
         n = process_item<0, kFused, true>(d, local);
         if (d.stats) add_stats(d.stats, n);
         return;
@@ -447,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void tick_kernel(const TickArgs a)
 // written densely to this frame's bank, and the resolve.  A gather from the
 // previous bank, so the banks alternate; every slot is rewritten.
 // ---------------------------------------------------------------------------
-template <int K, bool EQ7>
+template <int K, bool PER_SLOT>
 __device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_t x, uint32_t y)
 {
     const FrameDesc& d = r.f;
@@ -477,18 +491,20 @@ __device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_
     uint32_t iv[R];
     float W[R];
     const float4 empty = make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool aes = d.bias == kAes;
+    const float empty_slot = aes ? -INFINITY : 0.f;      // A-ES key / Eq. 7 sum of an empty slot
     if (K) {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             rv[j] = keep ? src[j] : empty;
             iv[j] = keep ? sidx[j] : 0xFFFFFFFFu;
-            if (EQ7) W[j] = keep ? r.src_wsum[(size_t)q * (size_t)kk + j] : 0.f;
+            if (PER_SLOT) W[j] = keep ? r.src_wsum[(size_t)q * (size_t)kk + j] : empty_slot;
         }
     }
     float W1 = 0.f;
     uint32_t m = 0u;
     if (keep) {
-        if (!EQ7) W1 = r.src_wsum[q];
+        if (!PER_SLOT) W1 = r.src_wsum[q];
         m = r.src_cnt[q];
     }
 
@@ -503,8 +519,8 @@ __device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_
     const float w = weight_eq4(d.c, dx * dx + dy * dy, lv);
     const float4 fresh = make_float4(w, c0, c1, c2);
     float3 lab_new = make_float3(0.f, 0.f, 0.f);
-    if (EQ7) lab_new = rgb_to_lab(c0, c1, c2);
-    const float W1b = EQ7 ? 0.f : bias_eq6(W1, w, d.bias);
+    if (PER_SLOT && !aes) lab_new = rgb_to_lab(c0, c1, c2);
+    const float W1b = PER_SLOT ? 0.f : bias_shared(W1, w, d.bias, d.c.decay);
     const float s = W1b + w;
 
     // 4. Alg. 2 per slot, dense stores to this frame's bank, resolve sums
@@ -521,22 +537,30 @@ __device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_
         if (K) {
             v = rv[K ? j : 0];
             vi = iv[K ? j : 0];
-            if (EQ7) Wj = W[K ? j : 0];
+            if (PER_SLOT) Wj = W[K ? j : 0];
         } else {
             v = keep ? src[j] : empty;
             vi = keep ? sidx[j] : 0xFFFFFFFFu;
-            if (EQ7) Wj = keep ? r.src_wsum[(size_t)q * (size_t)kk + j] : 0.f;
+            if (PER_SLOT) Wj = keep ? r.src_wsum[(size_t)q * (size_t)kk + j] : empty_slot;
         }
         if ((j & 3) == 0) words = philox4x32_10(p, d.t, (uint32_t)(j >> 2), 0u, d.seed, d.stream_id);
         const uint32_t word = (j & 3) == 0 ? words.x : (j & 3) == 1 ? words.y : (j & 3) == 2 ? words.z : words.w;
         float W1j = W1b, sj = s;
-        if (EQ7) {
-            const float dl = fminf(1.0f, cie94(rgb_to_lab(v.y, v.z, v.w), lab_new) / 100.0f);
-            W1j = bias_eq7(Wj, w, dl);
-            sj = W1j + w;
-            st<kNtWsumSt>(d.wsum + (size_t)p * (size_t)kk + j, sj);
+        bool take;
+        if (PER_SLOT && aes) {
+            const float kn = log2_unit(word) / w;
+            take = kn > Wj;
+            st<kNtWsumSt>(d.wsum + (size_t)p * (size_t)kk + j, take ? kn : Wj);
+        } else {
+            if (PER_SLOT) {
+                const float dl = fminf(1.0f, cie94(rgb_to_lab(v.y, v.z, v.w), lab_new) / 100.0f);
+                W1j = bias_eq7(Wj, w, dl);
+                sj = W1j + w;
+                st<kNtWsumSt>(d.wsum + (size_t)p * (size_t)kk + j, sj);
+            }
+            take = unit_variate(word) * sj > W1j;
         }
-        if (unit_variate(word) * sj > W1j) {
+        if (take) {
             tk |= 1u << j;
             v = fresh;
             vi = d.t;
@@ -548,7 +572,7 @@ __device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_
         a1 = a1 + v.x * v.z;
         a2 = a2 + v.x * v.w;
     }
-    if (!EQ7) st<kNtWsumSt>(d.wsum + p, s);
+    if (!PER_SLOT) st<kNtWsumSt>(d.wsum + p, s);
     st<kNtWsumSt>(r.cnt + p, m + 1u);
     st<kNtWsumSt>(r.depth_out + p, dc);
     if (d.out) {
@@ -561,7 +585,7 @@ __device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_
     return __popc(tk) + (tk ? 0x10000u : 0u) + (keep ? 0u : 0x1000000u);
 }
 
-template <int K, bool EQ7>
+template <int K, bool PER_SLOT>
 __global__ __launch_bounds__(kBlock) void reproject_kernel(ReprojDesc r)
 {
     const FrameDesc& d = r.f;
@@ -578,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void reproject_kernel(ReprojDesc r)
     const uint32_t x = (tx << d.tile_x_log2) + (local & ((1u << d.tile_x_log2) - 1u));
     const uint32_t y = (ty << d.tile_y_log2) + (local >> d.tile_x_log2);
     uint32_t n = 0u;
-    if (y < d.height && x < d.width) n = pixel_reproject<K, EQ7>(r, x, y);
+    if (y < d.height && x < d.width) n = pixel_reproject<K, PER_SLOT>(r, x, y);
     if (d.stats) add_stats(d.stats, n);
 }
 
@@ -596,7 +620,7 @@ static hipError_t launch_frame_op(const FrameDesc& d, hipStream_t stream)
 {
     const dim3 grid(d.items), block(kBlock);
     if constexpr (OP != kResolve) {
-        if (d.bias == kBiasFull) {
+        if (per_slot_mode(d.bias)) {
             switch (d.k) {
                 case 4: hipLaunchKernelGGL((frame_kernel<4, OP, true>), grid, block, 0, stream, d); break;
                 case 8: hipLaunchKernelGGL((frame_kernel<8, OP, true>), grid, block, 0, stream, d); break;
@@ -636,7 +660,7 @@ hipError_t launch_tick(const TickArgs& a, hipStream_t stream)
 hipError_t launch_reproject(const ReprojDesc& r, hipStream_t stream)
 {
     const dim3 grid(r.f.items), block(kBlock);
-    const bool eq7 = r.f.bias == kBiasFull;
+    const bool eq7 = per_slot_mode(r.f.bias);
     switch (r.f.k) {
         case 4:
             if (eq7) hipLaunchKernelGGL((reproject_kernel<4, true>), grid, block, 0, stream, r);

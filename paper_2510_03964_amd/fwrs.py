@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfwrs.so")
 
 OK, E_ARG, E_NOMEM, E_HIP, E_STATE = 0, 1, 2, 3, 4
-BIAS_NONE, BIAS_BERNOULLI, BIAS_FULL = 0, 1, 2
+BIAS_NONE, BIAS_BERNOULLI, BIAS_FULL, BIAS_MEMORYLESS, AES = 0, 1, 2, 3, 4
 FLAG_REPROJECT = 1
 MAX_K = 16
 
@@ -52,6 +52,7 @@ class Params(C.Structure):
         ("r2k", C.c_float),
         ("rek", C.c_float),
         ("flags", C.c_uint32),
+        ("lambda_decay", C.c_float),
     ]
 
 

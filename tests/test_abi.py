@@ -67,6 +67,7 @@ def test_default_params_and_sizes():
     p = fwrs.default_params(3840)
     assert p.fov_deg == 70.0 and p.fovea_radius_px == pytest.approx(192.0)
     assert p.bias_mode == fwrs.BIAS_BERNOULLI
+    assert p.flags == 0 and p.lambda_decay == pytest.approx(0.0231)
     assert (p.a_k, p.r2k, p.rek) == (pytest.approx(0.9851), pytest.approx(1.058), pytest.approx(22.14))
     N = 3840 * 2160
     assert fwrs.state_bytes(3840, 2160, 4) == 4 * N * (1 + 20) + 24576      # N is a multiple of 64
@@ -79,7 +80,9 @@ def test_default_params_and_sizes():
         assert fwrs.state_bytes(13, 7, 3, prm(bias_mode=mode)) == fwrs.state_bytes(13, 7, 3)
     assert fwrs.state_bytes(3840, 2160, 4, prm(bias_mode=fwrs.BIAS_FULL)) == 4 * N * (4 + 20) + 24576
     assert fwrs.state_bytes(13, 7, 3, prm(bias_mode=fwrs.BIAS_FULL)) == 4 * 128 * (3 + 15) + 24576
-    assert fwrs.state_bytes(13, 7, 3, prm(bias_mode=3)) == 0
+    assert fwrs.state_bytes(13, 7, 3, prm(bias_mode=fwrs.BIAS_MEMORYLESS)) == fwrs.state_bytes(13, 7, 3)
+    assert fwrs.state_bytes(13, 7, 3, prm(bias_mode=fwrs.AES)) == 4 * 128 * (3 + 15) + 24576
+    assert fwrs.state_bytes(13, 7, 3, prm(bias_mode=5)) == 0
     # a reprojecting context keeps two banks, each with a count and a depth per pixel
     assert fwrs.state_bytes(13, 7, 3, prm(flags=fwrs.FLAG_REPROJECT)) == 2 * 4 * 128 * (1 + 15 + 2) + 24576
     assert fwrs.state_bytes(13, 7, 3, prm(flags=fwrs.FLAG_REPROJECT, bias_mode=fwrs.BIAS_FULL)) == \
@@ -97,7 +100,8 @@ def test_invalid_arguments_are_rejected_before_any_gpu_work():
     assert L.fwrs_create(10, 10, 17, C.byref(h)) == fwrs.E_ARG
     assert L.fwrs_create(10, 10, 4, None) == fwrs.E_ARG
     for field, value in [("fov_deg", 0.0), ("fovea_radius_px", float("nan")), ("bias_mode", 7), ("a_k", 1.5),
-                         ("r_m", -1.0), ("rek", float("inf")), ("flags", 6)]:
+                         ("r_m", -1.0), ("rek", float("inf")), ("flags", 6), ("bias_mode", 5),
+                         ("lambda_decay", -0.5), ("lambda_decay", float("nan"))]:
         q = fwrs.default_params(64)
         setattr(q, field, value)
         assert L.fwrs_create_ex(64, 64, 4, C.byref(q), None, None, 0, C.byref(h)) == fwrs.E_ARG, field

@@ -362,30 +362,36 @@ def test_engine_rejects_bad_ticks(dev):
 # ---------------------------------------------------------------------------
 # Full temporal bias (Eq. 7): per-slot w_sum and the CIE94 colour difference
 # ---------------------------------------------------------------------------
-def test_eq7_small_workload_every_frame(dev):
+@pytest.mark.parametrize("bias", [fwrs.BIAS_FULL, fwrs.AES, fwrs.BIAS_MEMORYLESS])
+def test_modes_small_workload_every_frame(dev, bias):
+    """Eq. 7 and the two ablations (A-ES, memory-less bias) on the 256x256 trace, every frame."""
     spec = synth.spec_small()
-    res, _, _ = _run_pair(dev, spec, spec.frames, bias=fwrs.BIAS_FULL)
-    assert res.state_view().wsum_slots == spec.k
+    res, _, _ = _run_pair(dev, spec, spec.frames, bias=bias)
+    per_slot = bias in (fwrs.BIAS_FULL, fwrs.AES)
+    assert res.state_view().wsum_slots == (spec.k if per_slot else 1)
     st = res.download()
-    assert np.all(st.wsum == 0.0)
+    if per_slot:
+        assert np.all(st.wsum == 0.0)
 
 
 @pytest.mark.parametrize("w,h,k,frames", [
     (1, 1, 1, 4), (3, 2, 16, 4), (13, 7, 3, 5), (100, 37, 5, 4), (64, 64, 8, 5), (96, 40, 4, 4), (255, 3, 2, 4),
     (1367, 769, 4, 3),
 ])
-def test_eq7_sizes_and_slot_counts(dev, w, h, k, frames):
+@pytest.mark.parametrize("bias", [fwrs.BIAS_FULL, fwrs.AES, fwrs.BIAS_MEMORYLESS])
+def test_modes_sizes_and_slot_counts(dev, w, h, k, frames, bias):
     spec = synth.StreamSpec(w, h, k, frames, max(1.0, 0.1 * w), max(2.5, 0.25 * w), 0.2 * w + 0.5, 2, 0.3 * w + 1,
                             stream_id=k)
-    _run_pair(dev, spec, frames, bias=fwrs.BIAS_FULL)
+    _run_pair(dev, spec, frames, bias=bias)
 
 
 @pytest.mark.parametrize("k", [4, 3, 8])
-def test_eq7_split_and_incremental_equal_fused(dev, k):
+@pytest.mark.parametrize("bias", [fwrs.BIAS_FULL, fwrs.AES, fwrs.BIAS_MEMORYLESS])
+def test_modes_split_and_incremental_equal_fused(dev, k, bias):
     spec = synth.StreamSpec(160, 96, k, 12, 16.0, 40.0, 3.0, 4, 8.0)
-    _, _, out_f = _run_pair(dev, spec, 12, bias=fwrs.BIAS_FULL, every=4)
-    _, _, out_s = _run_pair(dev, spec, 12, mode="split", bias=fwrs.BIAS_FULL, every=12)
-    _, _, out_i = _run_pair(dev, spec, 12, mode="incremental", bias=fwrs.BIAS_FULL, every=3)
+    _, _, out_f = _run_pair(dev, spec, 12, bias=bias, every=4)
+    _, _, out_s = _run_pair(dev, spec, 12, mode="split", bias=bias, every=12)
+    _, _, out_i = _run_pair(dev, spec, 12, mode="incremental", bias=bias, every=3)
     assert torch.equal(out_f, out_s)
     assert torch.equal(out_f, out_i)
 
@@ -435,9 +441,9 @@ def test_eq7_caller_arena_is_sized_by_mode(dev):
 
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_eq7_engine_mixes_bias_modes(dev, use_graph):
-    """One batched tick over contexts of all three bias modes matches the oracle per context."""
+    """One batched tick over contexts of every mode matches the oracle per context."""
     specs = _mix_specs()
-    modes = [fwrs.BIAS_FULL, fwrs.BIAS_BERNOULLI, fwrs.BIAS_FULL, fwrs.BIAS_NONE, fwrs.BIAS_FULL]
+    modes = [fwrs.BIAS_FULL, fwrs.BIAS_BERNOULLI, fwrs.AES, fwrs.BIAS_NONE, fwrs.BIAS_MEMORYLESS]
     stream = torch.cuda.current_stream()
     srcs = [synth.FrameSource(s, device=dev) for s in specs]
     eng = fwrs.Engine(len(specs), stream=stream, use_graph=use_graph)

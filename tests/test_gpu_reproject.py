@@ -65,7 +65,8 @@ def _run(dev, spec, n, bias=fwrs.BIAS_BERNOULLI, frames=None, every=1, tile=None
     return res, orc, out
 
 
-@pytest.mark.parametrize("bias", [fwrs.BIAS_BERNOULLI, fwrs.BIAS_NONE, fwrs.BIAS_FULL])
+@pytest.mark.parametrize("bias", [fwrs.BIAS_BERNOULLI, fwrs.BIAS_NONE, fwrs.BIAS_FULL, fwrs.AES,
+                                  fwrs.BIAS_MEMORYLESS])
 def test_moving_workload_every_frame(dev, bias):
     """Panning camera and a moving occluder: 192x108, k = 4, 16 frames, every frame compared."""
     spec = synth.StreamSpec(192, 108, 4, 16, 9.6, 24.0, 1.0, 6, 3.0, stream_id=3)
@@ -78,7 +79,7 @@ def test_moving_workload_every_frame(dev, bias):
 @pytest.mark.parametrize("w,h,k,frames", [
     (1, 1, 1, 3), (3, 2, 16, 3), (13, 7, 3, 4), (100, 37, 5, 4), (64, 64, 8, 4), (255, 3, 2, 3), (96, 40, 1, 3),
 ])
-@pytest.mark.parametrize("bias", [fwrs.BIAS_BERNOULLI, fwrs.BIAS_FULL])
+@pytest.mark.parametrize("bias", [fwrs.BIAS_BERNOULLI, fwrs.BIAS_FULL, fwrs.AES])
 def test_sizes_and_slot_counts(dev, w, h, k, frames, bias):
     spec = synth.StreamSpec(w, h, k, frames, max(1.0, 0.1 * w), max(2.5, 0.25 * w), 0.2 * w + 0.5, 2,
                             0.3 * w + 1, stream_id=k)
@@ -142,9 +143,11 @@ def test_reset_flushes_the_next_frame(dev):
     _compare(res, orc, out, "after reset")
 
 
-def test_caller_arena(dev):
+@pytest.mark.parametrize("bias", [fwrs.BIAS_FULL, fwrs.AES])
+def test_caller_arena(dev, bias):
+    """A caller arena full of garbage is cleared to the empty state (A-ES keys to -infinity)."""
     spec = synth.StreamSpec(96, 64, 8, 4, 8.0, 20.0, 1.0, 3, 3.0)
-    p, q = _params(spec, fwrs.BIAS_FULL)
+    p, q = _params(spec, bias)
     need = fwrs.state_bytes(spec.width, spec.height, spec.k, p)
     with pytest.raises(fwrs.FwrsError):
         fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream(),
