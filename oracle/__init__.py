@@ -105,6 +105,14 @@ def _bind(L):
                                              C.POINTER(C.c_float), C.c_float, C.c_float, C.c_float]
     L.fwrs_oracle_push_reproject.restype = C.c_int
     L.fwrs_oracle_depth.argtypes = [vp, C.POINTER(C.c_float)]
+    fp = C.POINTER(C.c_float)
+    L.fwrs_oracle_foveate.argtypes = [fp, C.c_int, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, C.c_uint32,
+                                      fp, C.POINTER(C.c_uint8)]
+    L.fwrs_oracle_foveate.restype = C.c_int
+    L.fwrs_oracle_mip_down.argtypes = [fp, C.c_int, C.c_int, fp]
+    L.fwrs_oracle_gauss_weights.argtypes = [C.c_float, fp]
+    L.fwrs_oracle_gauss_weights.restype = C.c_int
+    L.fwrs_oracle_blur.argtypes = [fp, C.c_int, C.c_int, C.c_float, fp, fp]
     L.fwrs_oracle_log2u_many.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_float), C.c_size_t]
     L.fwrs_oracle_decay.argtypes = [vp]
     L.fwrs_oracle_decay.restype = C.c_float
@@ -250,6 +258,49 @@ def philox(keys: np.ndarray, ctrs: np.ndarray) -> np.ndarray:
     n = ctrs.shape[0]
     out = np.empty((n, 4), np.uint32)
     lib().fwrs_oracle_philox_many(_ptr(keys, C.c_uint32), _ptr(ctrs, C.c_uint32), _ptr(out, C.c_uint32), n)
+    return out
+
+
+FOV_MIP = 0
+FOV_GAUSS = 1
+
+
+def foveate(full: np.ndarray, gx: float, gy: float, r0: float, r1: float, mode: int = FOV_MIP):
+    """Foveated frame [H, W, 3] float32 and level map [H, W] uint8 from a full frame [H, W, 3]."""
+    full = np.ascontiguousarray(full, dtype=np.float32)
+    H, W, _ = full.shape
+    color = np.empty_like(full)
+    level = np.empty((H, W), np.uint8)
+    rc = lib().fwrs_oracle_foveate(_ptr(full, C.c_float), W, H, C.c_float(gx), C.c_float(gy), C.c_float(r0),
+                                   C.c_float(r1), int(mode), _ptr(color, C.c_float), _ptr(level, C.c_uint8))
+    if rc != 0:
+        raise ValueError(f"oracle foveate failed ({rc})")
+    return color, level
+
+
+def mip_down(img: np.ndarray) -> np.ndarray:
+    img = np.ascontiguousarray(img, dtype=np.float32)
+    H, W, _ = img.shape
+    out = np.empty(((H + 1) // 2, (W + 1) // 2, 3), np.float32)
+    lib().fwrs_oracle_mip_down(_ptr(img, C.c_float), W, H, _ptr(out, C.c_float))
+    return out
+
+
+def gauss_weights(sigma: float) -> np.ndarray:
+    w = np.empty(65, np.float32)
+    R = lib().fwrs_oracle_gauss_weights(C.c_float(sigma), _ptr(w, C.c_float))
+    if R < 0:
+        raise ValueError("radius too large")
+    return w[:2 * R + 1].copy()
+
+
+def blur(img: np.ndarray, sigma: float) -> np.ndarray:
+    img = np.ascontiguousarray(img, dtype=np.float32)
+    H, W, _ = img.shape
+    tmp = np.empty_like(img)
+    out = np.empty_like(img)
+    lib().fwrs_oracle_blur(_ptr(img, C.c_float), W, H, C.c_float(sigma), _ptr(tmp, C.c_float),
+                           _ptr(out, C.c_float))
     return out
 
 

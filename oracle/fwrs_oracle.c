@@ -25,6 +25,9 @@
  *                        largest key is kept; the memory-less temporal bias
  *                        f(j, i) = exp(-lambda (i - j)) (Aggarwal), both as
  *                        the ablations Sec. 4.1 and 4.2 argue against
+ *   Sec. 4.3             foveated rendering simulated as a post-process on the
+ *                        full frame: mipmapping with bilinear filtering, or a
+ *                        Gaussian blur that grows with eccentricity
  *   Sec. 4.3             temporal reprojection by motion vectors; a depth
  *                        disagreement between frames (occlusion or
  *                        disocclusion) flushes the reservoir's history
@@ -68,6 +71,14 @@
  *     underflow); the candidate replaces the sample iff its key is larger; an
  *     empty slot has key -infinity.  log2(rand) uses the rand of the slot's
  *     Philox word, computed by the series below.
+ *   - foveation levels are rings around the gaze: level 0 within r0 (full
+ *     resolution), 1 within r1, 2 beyond (squared distance of the pixel centre
+ *     in binary32).  MIP: mip l is the 2x2 box mean of mip l-1 (edge texels
+ *     average the texels that exist); level l samples mip l bilinearly at the
+ *     pixel centre (texel centres at (i + 0.5) 2^l, clamp to edge, a + f (b - a)
+ *     interpolation).  GAUSS: level l is the frame blurred by a separable
+ *     Gaussian of sigma 2^(l-1) pixels, radius ceil(3 sigma), weights
+ *     normalised to sum 1, clamp to edge.
  *   - reprojection is reverse and nearest: pixel (x, y) continues the
  *     reservoir of the pixel that contains its centre moved back by its motion
  *     vector, (floor(x + 0.5 - mx), floor(y + 0.5 - my)); that history is kept
@@ -222,6 +233,158 @@ float fwrs_oracle_log2u(uint32_t bits)
 }
 
 float fwrs_oracle_decay(const fwrs_oracle* o) { return o->decay; }
+
+/* ------------------------------------------------------------------------ */
+/* Foveation generator (Sec. 4.3).  The paper renders the full frame and then */
+/* degrades it away from the gaze, either by mipmapping with bilinear         */
+/* filtering or by a progressively stronger Gaussian blur; the degraded frame */
+/* and its level map are the candidates of the reservoir pass.                */
+/* ------------------------------------------------------------------------ */
+/* One mip level down: dst[(j * ceil(W/2) + i) * 3 + c] = mean of the texels  */
+/* (2i + dx, 2j + dy), dx, dy in {0, 1}, that lie in the source, summed in    */
+/* row-major order.                                                           */
+void fwrs_oracle_mip_down(const float* src, int width, int height, float* dst)
+{
+    const int w2 = (width + 1) / 2, h2 = (height + 1) / 2;
+    for (int j = 0; j < h2; ++j)
+        for (int i = 0; i < w2; ++i)
+            for (int c = 0; c < 3; ++c) {
+                float s = 0.0f;
+                int n = 0;
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const int x = 2 * i + dx, y = 2 * j + dy;
+                        if (x < width && y < height) {
+                            s = s + src[((size_t)y * (size_t)width + (size_t)x) * 3 + (size_t)c];
+                            n = n + 1;
+                        }
+                    }
+                dst[((size_t)j * (size_t)w2 + (size_t)i) * 3 + (size_t)c] = s / (float)n;
+            }
+}
+
+/* Bilinear sample of channel c of a w x h level at the centre of full-res */
+/* pixel (x, y), the level being 1/scale of the full resolution.           */
+static float bilinear(const float* lv, int w, int h, int x, int y, float inv_scale, int c)
+{
+    const float u = ((float)x + 0.5f) * inv_scale - 0.5f;
+    const float v = ((float)y + 0.5f) * inv_scale - 0.5f;
+    const float fu = floorf(u), fv = floorf(v);
+    const float fx = u - fu, fy = v - fv;
+    int i0 = (int)fu, j0 = (int)fv;
+    int i1 = i0 + 1, j1 = j0 + 1;
+    if (i0 < 0) i0 = 0;
+    if (j0 < 0) j0 = 0;
+    if (i1 > w - 1) i1 = w - 1;
+    if (j1 > h - 1) j1 = h - 1;
+    if (i0 > w - 1) i0 = w - 1;
+    if (j0 > h - 1) j0 = h - 1;
+    const float t00 = lv[((size_t)j0 * (size_t)w + (size_t)i0) * 3 + (size_t)c];
+    const float t10 = lv[((size_t)j0 * (size_t)w + (size_t)i1) * 3 + (size_t)c];
+    const float t01 = lv[((size_t)j1 * (size_t)w + (size_t)i0) * 3 + (size_t)c];
+    const float t11 = lv[((size_t)j1 * (size_t)w + (size_t)i1) * 3 + (size_t)c];
+    const float top = t00 + fx * (t10 - t00);
+    const float bot = t01 + fx * (t11 - t01);
+    return top + fy * (bot - top);
+}
+
+/* Normalised Gaussian weights w[0 .. 2R] for offsets -R .. R, R = ceil(3 sigma): */
+/* g(d) = exp(-d^2 / (2 sigma^2)) by the project's exp2, divided by their sum     */
+/* taken in offset order.  Returns R, or -1 if R exceeds 32.                      */
+int fwrs_oracle_gauss_weights(float sigma, float* w)
+{
+    const int R = (int)ceilf(3.0f * sigma);
+    if (R < 0 || R > 32) return -1;
+    const float inv = 1.0f / (2.0f * sigma * sigma);
+    float S = 0.0f;
+    for (int d = -R; d <= R; ++d) {
+        const float a = (float)(d * d) * inv;
+        w[d + R] = fwrs_oracle_exp2p(-(a * 1.44269504088896341f));
+        S = S + w[d + R];
+    }
+    for (int d = -R; d <= R; ++d) w[d + R] = w[d + R] / S;
+    return R;
+}
+
+/* Separable Gaussian blur, clamp to edge: a horizontal pass into tmp, then a */
+/* vertical pass into dst; each output accumulates w[d] * sample in offset    */
+/* order from 0.                                                              */
+void fwrs_oracle_blur(const float* src, int width, int height, float sigma, float* tmp, float* dst)
+{
+    float w[65];
+    const int R = fwrs_oracle_gauss_weights(sigma, w);
+    if (R < 0) return;
+    for (int y = 0; y < height; ++y)
+        for (int x = 0; x < width; ++x)
+            for (int c = 0; c < 3; ++c) {
+                float acc = 0.0f;
+                for (int d = -R; d <= R; ++d) {
+                    int xx = x + d;
+                    if (xx < 0) xx = 0;
+                    if (xx > width - 1) xx = width - 1;
+                    acc = acc + w[d + R] * src[((size_t)y * (size_t)width + (size_t)xx) * 3 + (size_t)c];
+                }
+                tmp[((size_t)y * (size_t)width + (size_t)x) * 3 + (size_t)c] = acc;
+            }
+    for (int y = 0; y < height; ++y)
+        for (int x = 0; x < width; ++x)
+            for (int c = 0; c < 3; ++c) {
+                float acc = 0.0f;
+                for (int d = -R; d <= R; ++d) {
+                    int yy = y + d;
+                    if (yy < 0) yy = 0;
+                    if (yy > height - 1) yy = height - 1;
+                    acc = acc + w[d + R] * tmp[((size_t)yy * (size_t)width + (size_t)x) * 3 + (size_t)c];
+                }
+                dst[((size_t)y * (size_t)width + (size_t)x) * 3 + (size_t)c] = acc;
+            }
+}
+
+/* The foveated frame and its level map from the full frame and the gaze.     */
+/* Returns 0, 1 for an unknown mode, 2 if memory is short.                    */
+int fwrs_oracle_foveate(const float* full, int width, int height, float gx, float gy, float r0, float r1,
+                        uint32_t mode, float* color, uint8_t* level)
+{
+    if (mode != FWRS_ORACLE_FOV_MIP && mode != FWRS_ORACLE_FOV_GAUSS) return 1;
+    const size_t n = (size_t)width * (size_t)height;
+    const int w1 = (width + 1) / 2, h1 = (height + 1) / 2;
+    const int w2 = (w1 + 1) / 2, h2 = (h1 + 1) / 2;
+    float *a = NULL, *b = NULL, *tmp = NULL;
+    if (mode == FWRS_ORACLE_FOV_MIP) {
+        a = (float*)malloc((size_t)w1 * (size_t)h1 * 3 * sizeof(float));
+        b = (float*)malloc((size_t)w2 * (size_t)h2 * 3 * sizeof(float));
+        if (!a || !b) { free(a); free(b); return 2; }
+        fwrs_oracle_mip_down(full, width, height, a);
+        fwrs_oracle_mip_down(a, w1, h1, b);
+    } else {
+        a = (float*)malloc(n * 3 * sizeof(float));
+        b = (float*)malloc(n * 3 * sizeof(float));
+        tmp = (float*)malloc(n * 3 * sizeof(float));
+        if (!a || !b || !tmp) { free(a); free(b); free(tmp); return 2; }
+        fwrs_oracle_blur(full, width, height, 1.0f, tmp, a);
+        fwrs_oracle_blur(full, width, height, 2.0f, tmp, b);
+    }
+    const float r0sq = r0 * r0, r1sq = r1 * r1;
+    for (int y = 0; y < height; ++y)
+        for (int x = 0; x < width; ++x) {
+            const size_t p = (size_t)y * (size_t)width + (size_t)x;
+            const float dx = ((float)x + 0.5f) - gx;
+            const float dy = ((float)y + 0.5f) - gy;
+            const float d2 = dx * dx + dy * dy;
+            const uint8_t lv = d2 <= r0sq ? 0 : (d2 <= r1sq ? 1 : 2);
+            level[p] = lv;
+            for (int c = 0; c < 3; ++c) {
+                float v;
+                if (lv == 0) v = full[p * 3 + (size_t)c];
+                else if (mode == FWRS_ORACLE_FOV_GAUSS) v = (lv == 1 ? a : b)[p * 3 + (size_t)c];
+                else if (lv == 1) v = bilinear(a, w1, h1, x, y, 0.5f, c);
+                else v = bilinear(b, w2, h2, x, y, 0.25f, c);
+                color[p * 3 + (size_t)c] = v;
+            }
+        }
+    free(a); free(b); free(tmp);
+    return 0;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Colour difference for Eq. 7.                                               */

@@ -76,6 +76,13 @@ int fwrs_oracle_push_reproject(fwrs_oracle* o, const float* color, const uint8_t
 void fwrs_oracle_depth(const fwrs_oracle* o, float* depth);
 uint64_t fwrs_oracle_flushes(const fwrs_oracle* o);
 
+#define FWRS_ORACLE_FOV_MIP 0u     /* mipmap + bilinear filtering */
+#define FWRS_ORACLE_FOV_GAUSS 1u   /* Gaussian blur growing with the level */
+int fwrs_oracle_foveate(const float* full, int width, int height, float gx, float gy, float r0, float r1,
+                        uint32_t mode, float* color, uint8_t* level);
+void fwrs_oracle_mip_down(const float* src, int width, int height, float* dst);
+int fwrs_oracle_gauss_weights(float sigma, float* w);
+void fwrs_oracle_blur(const float* src, int width, int height, float sigma, float* tmp, float* dst);
 float fwrs_oracle_log2u(uint32_t bits);
 void fwrs_oracle_log2u_many(const uint32_t* bits, float* out, size_t count);
 float fwrs_oracle_decay(const fwrs_oracle* o);

@@ -70,6 +70,14 @@ MUTANTS = {
     "log2_series_coefficient": ("p = p * z + 0x1.ec709ep-1f;", "p = p * z + 0x1.ec709ep-2f;"),
     "log2_range_reduction_exponent": ("        e = e + 1;\n", "        e = e + 0;\n"),
     "memoryless_decay_twice": ("W1b = W1 * o->decay;", "W1b = (W1 * o->decay) * o->decay;"),
+    "mip_divisor_fixed": ("= s / (float)n;", "= s / 4.0f;"),
+    "bilinear_no_half_texel": ("* inv_scale - 0.5f;", "* inv_scale;"),
+    "bilinear_axes_mixed": ("const float top = t00 + fx * (t10 - t00);", "const float top = t00 + fy * (t10 - t00);"),
+    "fovea_ring_not_squared": ("const float r0sq = r0 * r0, r1sq = r1 * r1;", "const float r0sq = r0, r1sq = r1 * r1;"),
+    "gauss_sigma_not_squared": ("const float inv = 1.0f / (2.0f * sigma * sigma);", "const float inv = 1.0f / (2.0f * sigma);"),
+    "gauss_unnormalised": ("for (int d = -R; d <= R; ++d) w[d + R] = w[d + R] / S;", "for (int d = -R; d <= R; ++d) w[d + R] = w[d + R];"),
+    "blur_vertical_reads_source": ("acc = acc + w[d + R] * tmp[", "acc = acc + w[d + R] * src["),
+    "gauss_levels_swapped": ("v = (lv == 1 ? a : b)", "v = (lv == 1 ? b : a)"),
     "decay_rate_not_natural": ("o->decay = fwrs_oracle_exp2p(-(p->lambda_decay * 1.44269504088896341f));",
                                "o->decay = fwrs_oracle_exp2p(-(p->lambda_decay));"),
 }
@@ -90,7 +98,8 @@ def _run_mutant(name, tmpdir):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(HERE, "test_oracle_pins.py"), os.path.join(HERE, "test_oracle_eq7.py"),
                         os.path.join(HERE, "test_oracle_reproject.py"),
-                        os.path.join(HERE, "test_oracle_ablations.py")],
+                        os.path.join(HERE, "test_oracle_ablations.py"),
+                        os.path.join(HERE, "test_oracle_foveate.py")],
                        cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=600)
     return name, r.returncode, r.stdout[-400:]
