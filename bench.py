@@ -340,6 +340,55 @@ def ablations(dev, stream, spec, frames, tile, sample_every: int = 10) -> dict:
     return result
 
 
+def foveated(dev, stream, spec, steps: int, tile) -> dict:
+    """The foveation generator ahead of the reservoir pass at the headline size: the full-resolution
+    scene frame, degraded per gaze sample by mipmap + bilinear filtering (and by the Gaussian
+    levels), timed (a) as the generator writing a frame + level map followed by the plain fused
+    pass, and (b) as the fused form, where the reservoir pass samples the level images directly."""
+    import numpy as np
+    import torch
+
+    from paper_2510_03964_amd import fwrs, synth
+
+    full = synth.scene(spec.width, spec.height, spec.stream_id, device=dev)
+    gaze = synth.gaze_trace(spec, steps)
+    p = fwrs.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED)
+    out = torch.empty((spec.height, spec.width, 3), dtype=torch.float32, device=dev)
+    col = torch.empty_like(out)
+    lev = torch.empty((spec.height, spec.width), dtype=torch.uint8, device=dev)
+    result = {}
+    for name, mode in (("mip_bilinear", fwrs.FOV_MIP), ("gaussian", fwrs.FOV_GAUSS)):
+        fov = fwrs.Foveator(spec.width, spec.height, spec.fovea_radius_px, spec.ring_radius_px, mode, stream=stream)
+        runs = {}
+        for form in ("separate", "fused"):
+            res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=stream)
+            if tile:
+                res.set_tile(*tile)
+
+            def step(gx, gy, o, _res=res, _fov=fov, _form=form):
+                if _form == "fused":
+                    _res.step_foveated(_fov, full, gx, gy, o)
+                else:
+                    _fov.foveate(full, gx, gy, col, lev)
+                    _res.step(col, lev, gx, gy, o)
+            for t in range(3):
+                step(float(gaze[t, 0]), float(gaze[t, 1]), out)
+            res.reset()
+            total_ms, per = timed_run(res, [(float(g[0]), float(g[1])) for g in gaze], out, stream, step)
+            runs[form] = {"ms_per_frame": total_ms / steps, "ms_per_frame_p50": float(np.percentile(per, 50)),
+                          "value": spec.pixels * steps / (total_ms / 1e3) / 1e9}
+            res.close()
+        fov.close()
+        runs["unit"] = "Gpixel-updates/s"
+        runs["fused_speedup"] = runs["separate"]["ms_per_frame"] / runs["fused"]["ms_per_frame"]
+        result[name] = runs
+        log(f"foveated {name}: separate {runs['separate']['ms_per_frame']:.4f} ms, "
+            f"fused {runs['fused']['ms_per_frame']:.4f} ms/frame")
+    result["workload"] = (f"{spec.width}x{spec.height} k={spec.k} full-resolution scene frame, {steps}-frame gaze "
+                          f"trace, rings {spec.fovea_radius_px:g}/{spec.ring_radius_px:g} px, Bernoulli bias")
+    return result
+
+
 def cpu_baseline(frames_host, spec, n_frames: int) -> dict:
     import oracle
 
@@ -385,6 +434,7 @@ def main() -> int:
     ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-resolve run")
     ap.add_argument("--no-eq7", action="store_true", help="skip the Eq. 7 (full temporal bias) run")
     ap.add_argument("--no-ablations", action="store_true", help="skip the update-rule comparison")
+    ap.add_argument("--no-foveated", action="store_true", help="skip the foveation-generator runs")
     ap.add_argument("--no-reproject", action="store_true", help="skip the moving-camera (reprojection) run")
     ap.add_argument("--reproject-ring", type=int, default=240, help="distinct moving frames kept resident")
     ap.add_argument("--no-multistream", action="store_true", help="skip the batched-vs-plain runs")
@@ -512,6 +562,8 @@ def main() -> int:
     del frames
     torch.cuda.empty_cache()
 
+    fov = None if args.no_foveated else foveated(dev, stream, spec, K, tile)
+
     reproject = None
     if not args.no_reproject:
         reproject = reprojection(dev, stream, spec, K, W, args.reproject_ring, tile)
@@ -571,6 +623,7 @@ def main() -> int:
         "eq7": eq7,
         "reproject": reproject,
         "ablations": ablation,
+        "foveated": fov,
         "multistream": multi,
         "serving": served,
         "copy_gbps": copy_gbps,

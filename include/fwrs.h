@@ -337,6 +337,54 @@ int fwrs_engine_set_tile(fwrs_engine* eng, long long min_pixels, int tile_x, int
 /* Waits for the engine's stream, then frees the engine. */
 int fwrs_engine_destroy(fwrs_engine* eng);
 
+/* ---- foveation generator (Sec. 4.3) -------------------------------------
+ * The paper simulates foveated rendering as a post-process on the full
+ * frame: mipmapping with bilinear filtering, or a Gaussian blur that grows
+ * with eccentricity.  A foveator turns a full-resolution frame ([height]
+ * [width][3] float32, device) into the candidates of the reservoir pass: a
+ * level per pixel by its distance d to the gaze (0 if d <= fovea_radius_px,
+ * 1 if d <= ring_radius_px, 2 beyond; squared distances of pixel centres in
+ * binary32) and a colour
+ *   level 0: the frame's own pixel;
+ *   FWRS_FOV_MIP:   level l samples mip l (mip l = 2x2 box mean of mip l-1;
+ *                   edge texels average the texels that exist) bilinearly at
+ *                   the pixel centre, texel centres at (i + 0.5) 2^l, clamp
+ *                   to edge;
+ *   FWRS_FOV_GAUSS: level l is the frame blurred by a separable Gaussian of
+ *                   sigma 2^(l-1) pixels (radius ceil(3 sigma), weights
+ *                   normalised, clamp to edge) at the pixel.
+ * Every operation is binary32 in a fixed order, so results are reproducible
+ * bit for bit.  The foveator owns the level images (mip: N/4 + N/16 texels;
+ * Gaussian: 3N), reused by every call: calls on one foveator must be ordered
+ * on one stream. */
+#define FWRS_FOV_MIP 0u
+#define FWRS_FOV_GAUSS 1u
+
+typedef struct fwrs_foveator fwrs_foveator;
+
+/* FWRS_E_ARG: sizes as fwrs_create, radii not finite, fovea_radius_px < 0 or
+ * ring_radius_px < fovea_radius_px, unknown mode.  FWRS_E_NOMEM. */
+int fwrs_foveator_create(int width, int height, float fovea_radius_px, float ring_radius_px, uint32_t mode,
+                         void* hip_stream, fwrs_foveator** out);
+
+/* Enqueues the degraded frame into `color` ([height][width][3] float32) and
+ * the level map into `level_map` ([height][width] uint8), on the foveator's
+ * stream.  FWRS_E_ARG: NULL pointers, non-finite gaze. */
+int fwrs_foveate(fwrs_foveator* fov, const float* full, float gaze_x, float gaze_y, float* color,
+                 uint8_t* level_map);
+
+/* fwrs_foveate followed by fwrs_push_frame_resolve (or fwrs_push_frame if
+ * `out` is NULL) without the intermediate frame: the level images are built,
+ * then one reservoir pass samples its candidates from them directly.  Runs on
+ * the context's stream; results are bit-identical to the two calls.
+ * FWRS_E_ARG: NULL ctx, fov or full, non-finite gaze, sizes differ.
+ * FWRS_E_STATE: as fwrs_push_frame (a reprojecting context is refused). */
+int fwrs_push_frame_foveated(fwrs_ctx* ctx, fwrs_foveator* fov, const float* full, float gaze_x, float gaze_y,
+                             float* out);
+
+/* Waits for the foveator's stream, then frees it.  NULL is accepted. */
+int fwrs_foveator_destroy(fwrs_foveator* fov);
+
 #ifdef __cplusplus
 }
 #endif

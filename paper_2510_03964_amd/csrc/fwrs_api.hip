@@ -766,3 +766,167 @@ int fwrs_engine_destroy(fwrs_engine* e)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Foveation generator
+// ---------------------------------------------------------------------------
+struct fwrs_foveator {
+    int width = 0, height = 0, device = 0;
+    uint32_t mode = FWRS_FOV_MIP;
+    float r0 = 0.f, r1 = 0.f;
+    hipStream_t stream = nullptr;
+    float* buf = nullptr;                  // one allocation for the level images
+    float* l1 = nullptr;
+    float* l2 = nullptr;
+    float* tmp = nullptr;                  // Gaussian only: the horizontal pass
+    uint32_t w1 = 0, h1 = 0, w2 = 0, h2 = 0;
+    int radius[2] = {0, 0};
+    float wt[2][2 * fwrs::kMaxBlurRadius + 1] = {};
+};
+
+namespace {
+
+// Normalised Gaussian weights for offsets -R..R, R = ceil(3 sigma), with the
+// library's binary32 exp2; the sum is taken in offset order.
+int gauss_weights(float sigma, float* w)
+{
+    const int R = (int)ceilf(3.0f * sigma);
+    const float inv = 1.0f / (2.0f * sigma * sigma);
+    float S = 0.0f;
+    for (int d = -R; d <= R; ++d) {
+        const float a = (float)(d * d) * inv;
+        w[d + R] = fwrs::exp2_neg(-(a * 1.44269504088896341f));
+        S = S + w[d + R];
+    }
+    for (int d = -R; d <= R; ++d) w[d + R] = w[d + R] / S;
+    return R;
+}
+
+fwrs::FovSrc build_levels(fwrs_foveator* f, const float* full, hipStream_t stream, hipError_t& err)
+{
+    fwrs::FovSrc s{};
+    s.full = full;
+    s.l1 = f->l1;
+    s.l2 = f->l2;
+    s.w1 = f->w1;
+    s.h1 = f->h1;
+    s.w2 = f->w2;
+    s.h2 = f->h2;
+    s.r0sq = f->r0 * f->r0;
+    s.r1sq = f->r1 * f->r1;
+    s.mode = f->mode;
+    if (f->mode == FWRS_FOV_MIP) {
+        err = fwrs::launch_mips(full, f->l1, f->l2, (uint32_t)f->width, (uint32_t)f->height, stream);
+    } else {
+        err = fwrs::launch_blur(full, f->tmp, f->l1, (uint32_t)f->width, (uint32_t)f->height, f->radius[0],
+                                f->wt[0], stream);
+        if (err == hipSuccess)
+            err = fwrs::launch_blur(full, f->tmp, f->l2, (uint32_t)f->width, (uint32_t)f->height, f->radius[1],
+                                    f->wt[1], stream);
+    }
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwrs_foveator_create(int width, int height, float fovea_radius_px, float ring_radius_px, uint32_t mode,
+                         void* hip_stream, fwrs_foveator** out)
+{
+    if (!out || !sizes_ok(width, height, 1)) return FWRS_E_ARG;
+    if (!std::isfinite(fovea_radius_px) || !std::isfinite(ring_radius_px) || fovea_radius_px < 0.0f ||
+        ring_radius_px < fovea_radius_px)
+        return FWRS_E_ARG;
+    if (mode != FWRS_FOV_MIP && mode != FWRS_FOV_GAUSS) return FWRS_E_ARG;
+    *out = nullptr;
+    fwrs_foveator* f = new (std::nothrow) fwrs_foveator();
+    if (!f) return FWRS_E_NOMEM;
+    if (hipGetDevice(&f->device) != hipSuccess) { delete f; return FWRS_E_HIP; }
+    f->width = width;
+    f->height = height;
+    f->mode = mode;
+    f->r0 = fovea_radius_px;
+    f->r1 = ring_radius_px;
+    f->stream = (hipStream_t)hip_stream;
+    f->w1 = ((uint32_t)width + 1) / 2;
+    f->h1 = ((uint32_t)height + 1) / 2;
+    f->w2 = (f->w1 + 1) / 2;
+    f->h2 = (f->h1 + 1) / 2;
+    const size_t n = (size_t)width * (size_t)height * 3;
+    // level images at 256-byte boundaries
+    auto up = [](size_t v) { return (v + 63) / 64 * 64; };
+    size_t s1, s2, st = 0;
+    if (mode == FWRS_FOV_MIP) {
+        s1 = up((size_t)f->w1 * f->h1 * 3);
+        s2 = up((size_t)f->w2 * f->h2 * 3);
+    } else {
+        s1 = s2 = st = up(n);
+        f->radius[0] = gauss_weights(1.0f, f->wt[0]);
+        f->radius[1] = gauss_weights(2.0f, f->wt[1]);
+    }
+    if (hipMalloc(&f->buf, 4 * (s1 + s2 + st)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete f;
+        return FWRS_E_NOMEM;
+    }
+    f->l1 = f->buf;
+    f->l2 = f->buf + s1;
+    f->tmp = st ? f->buf + s1 + s2 : nullptr;
+    *out = f;
+    return FWRS_OK;
+}
+
+int fwrs_foveate(fwrs_foveator* f, const float* full, float gaze_x, float gaze_y, float* color, uint8_t* level_map)
+{
+    if (!f || !full || !color || !level_map || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
+    DeviceGuard g(f->device);
+    if (!g.ok) return FWRS_E_HIP;
+    hipError_t err = hipSuccess;
+    const fwrs::FovSrc s = build_levels(f, full, f->stream, err);
+    if (err != hipSuccess) return FWRS_E_HIP;
+    if (fwrs::launch_foveate(s, color, level_map, (uint32_t)f->width, (uint32_t)f->height, gaze_x, gaze_y,
+                             f->stream) != hipSuccess)
+        return FWRS_E_HIP;
+    return FWRS_OK;
+}
+
+int fwrs_push_frame_foveated(fwrs_ctx* x, fwrs_foveator* f, const float* full, float gaze_x, float gaze_y, float* out)
+{
+    if (!x || !f || !full || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
+    if (f->width != x->width || f->height != x->height || f->device != x->device) return FWRS_E_ARG;
+    if (x->t == 0xFFFFFFFFu || x->reproject) return FWRS_E_STATE;
+    DeviceGuard g(x->device);
+    if (!g.ok) return FWRS_E_HIP;
+    hipError_t err = hipSuccess;
+    fwrs::FovDesc fd{};
+    fd.s = build_levels(f, full, x->stream, err);
+    if (err != hipSuccess) return FWRS_E_HIP;
+    fd.f = make_desc(x, nullptr, nullptr, gaze_x, gaze_y, out, x->tile_x, x->tile_y);
+    if (fwrs::launch_foveated(fd, out != nullptr, x->stream) != hipSuccess) return FWRS_E_HIP;
+    x->t += 1u;
+    x->pixel_updates += (uint64_t)x->width * (uint64_t)x->height;
+    if (out) {
+        x->resolved_out = out;
+        x->resolved_at = x->t;
+        x->resolved = true;
+    } else {
+        x->resolved = false;
+    }
+    return FWRS_OK;
+}
+
+int fwrs_foveator_destroy(fwrs_foveator* f)
+{
+    if (!f) return FWRS_OK;
+    int rc = FWRS_OK;
+    {
+        DeviceGuard g(f->device);
+        if (hipStreamSynchronize(f->stream) != hipSuccess) rc = FWRS_E_HIP;
+        if (f->buf && hipFree(f->buf) != hipSuccess) rc = FWRS_E_HIP;
+    }
+    delete f;
+    return rc;
+}
+
+}  // extern "C"

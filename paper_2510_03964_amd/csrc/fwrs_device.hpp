@@ -61,6 +61,25 @@ struct alignas(8) ReprojDesc {
     float tol;                  // relative depth tolerance
 };
 
+// Foveation generator sources (Sec. 4.3): the full frame and the two reduced
+// levels -- mip 1 and mip 2 (bilinear sampling) or the frame blurred with
+// sigma 1 and 2 px (sampled at the pixel) -- and the rings that pick a level.
+constexpr uint32_t kFovMip = 0u;
+constexpr uint32_t kFovGauss = 1u;
+struct FovSrc {
+    const float* full;          // [H][W][3]
+    const float* l1;            // mip 1 [h1][w1][3], or the sigma-1 blur [H][W][3]
+    const float* l2;            // mip 2 [h2][w2][3], or the sigma-2 blur [H][W][3]
+    uint32_t w1, h1, w2, h2;
+    float r0sq, r1sq;           // squared ring radii (level 0 within r0, 1 within r1)
+    uint32_t mode;              // kFovMip / kFovGauss
+};
+
+struct alignas(8) FovDesc {
+    FrameDesc f;
+    FovSrc s;
+};
+
 constexpr int kBlock = 256;             // threads per block
 constexpr int kTickFrames = 24;         // frames per batched launch (descriptors travel as kernel arguments)
 constexpr int kStatSlots = 1024;        // spread of the slot-take counters
@@ -204,6 +223,54 @@ __device__ __forceinline__ float log2_unit(uint32_t bits)
     p = p * z + 0x1.ec709ep-1f;                  // 2 / (3 ln 2)
     p = p * z + 0x1.715476p+1f;                  // 2 / ln 2
     return (float)(e - 24) + s * p;
+}
+
+// ---------------------------------------------------------------------------
+// Foveation: the level ring of a pixel and its degraded colour.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fov_level(const FovSrc& s, float gx, float gy, uint32_t x, uint32_t y)
+{
+    const float dx = ((float)x + 0.5f) - gx;
+    const float dy = ((float)y + 0.5f) - gy;
+    const float d2 = dx * dx + dy * dy;
+    return d2 <= s.r0sq ? 0u : (d2 <= s.r1sq ? 1u : 2u);
+}
+
+// Bilinear sample of a w x h level (1/scale of full resolution) at the centre
+// of full-resolution pixel (x, y): texel centres at (i + 0.5) scale, clamp to
+// edge, interpolation a + f (b - a) along x, then along y.
+__device__ __forceinline__ float3 bilinear(const float* lv, uint32_t w, uint32_t h, uint32_t x, uint32_t y,
+                                           float inv_scale)
+{
+    const float u = ((float)x + 0.5f) * inv_scale - 0.5f;
+    const float v = ((float)y + 0.5f) * inv_scale - 0.5f;
+    const float fu = floorf(u), fv = floorf(v);
+    const float fx = u - fu, fy = v - fv;
+    const int iw = (int)w - 1, ih = (int)h - 1;
+    const int i0 = min(max((int)fu, 0), iw), j0 = min(max((int)fv, 0), ih);
+    const int i1 = min((int)fu + 1, iw), j1 = min((int)fv + 1, ih);
+    const float* r0 = lv + (size_t)j0 * w * 3;
+    const float* r1 = lv + (size_t)j1 * w * 3;
+    float out[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float t00 = r0[3 * i0 + c], t10 = r0[3 * i1 + c];
+        const float t01 = r1[3 * i0 + c], t11 = r1[3 * i1 + c];
+        const float top = t00 + fx * (t10 - t00);
+        const float bot = t01 + fx * (t11 - t01);
+        out[c] = top + fy * (bot - top);
+    }
+    return make_float3(out[0], out[1], out[2]);
+}
+
+__device__ __forceinline__ float3 fov_colour(const FovSrc& s, uint32_t x, uint32_t y, uint32_t p, uint32_t level)
+{
+    const float* src = level == 0u ? s.full : (level == 1u ? s.l1 : s.l2);
+    if (level == 0u || s.mode == kFovGauss) {
+        const float* c = src + 3 * (size_t)p;
+        return make_float3(c[0], c[1], c[2]);
+    }
+    return level == 1u ? bilinear(s.l1, s.w1, s.h1, x, y, 0.5f) : bilinear(s.l2, s.w2, s.h2, x, y, 0.25f);
 }
 
 // ---------------------------------------------------------------------------

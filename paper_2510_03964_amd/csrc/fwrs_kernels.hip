@@ -143,8 +143,8 @@ __device__ __forceinline__ uint32_t decide_any(const FrameDesc& d, uint32_t p, f
 // (any slot count up to kMaxK) streams the record one slot at a time.
 // Returns the number of slots replaced plus 2^16 if there was any.
 // ---------------------------------------------------------------------------
-template <int K, int OP>
-__device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32_t y)
+template <int K, int OP, bool FOV = false>
+__device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32_t y, const FovSrc* fs = nullptr)
 {
     const uint32_t p = y * d.width + x;
     const int kk = K ? K : (int)d.k;
@@ -160,7 +160,8 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
     uint32_t lv = 0u;
     float W1 = 0.f;
     if (kUpdates) {
-        lv = ld<kNtLevel>(d.level + p);
+        if constexpr (FOV) lv = fov_level(*fs, d.gx, d.gy, x, y);
+        else lv = ld<kNtLevel>(d.level + p);
         W1 = ld<kNtWsumLd>(d.wsum + p);
     }
     float4 r[K ? K : 1];
@@ -193,9 +194,16 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
     // 3. the new colour where some slot takes it, then the replaced slots
     float c0 = 0.f, c1 = 0.f, c2 = 0.f;
     if (tk) {
-        c0 = ld<kNtColor>(color + 0);
-        c1 = ld<kNtColor>(color + 1);
-        c2 = ld<kNtColor>(color + 2);
+        if constexpr (FOV) {
+            const float3 c = fov_colour(*fs, x, y, p, lv);
+            c0 = c.x;
+            c1 = c.y;
+            c2 = c.z;
+        } else {
+            c0 = ld<kNtColor>(color + 0);
+            c1 = ld<kNtColor>(color + 1);
+            c2 = ld<kNtColor>(color + 2);
+        }
     }
     const float4 fresh = make_float4(w, c0, c1, c2);
     if (K && OP == kIncremental && tk) {
@@ -266,8 +274,9 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
 // Needs the new colour for every pixel and every slot's record, so the records
 // are read by every op that updates.  Same store layout otherwise.
 // ---------------------------------------------------------------------------
-template <int K, int OP>
-__device__ __forceinline__ uint32_t pixel_per_slot(const FrameDesc& d, uint32_t x, uint32_t y)
+template <int K, int OP, bool FOV = false>
+__device__ __forceinline__ uint32_t pixel_per_slot(const FrameDesc& d, uint32_t x, uint32_t y,
+                                                   const FovSrc* fs = nullptr)
 {
     const uint32_t p = y * d.width + x;
     const int kk = K ? K : (int)d.k;
@@ -298,11 +307,21 @@ __device__ __forceinline__ uint32_t pixel_per_slot(const FrameDesc& d, uint32_t 
             for (int j = 0; j < R; ++j) W[j] = ld<kNtWsumLd>(wslot + j);
         }
     }
-    const uint32_t lv = ld<kNtLevel>(d.level + p);
-    const float* color = d.color + 3 * (size_t)p;
-    const float c0 = ld<kNtColor>(color + 0);
-    const float c1 = ld<kNtColor>(color + 1);
-    const float c2 = ld<kNtColor>(color + 2);
+    uint32_t lv;
+    float c0, c1, c2;
+    if constexpr (FOV) {
+        lv = fov_level(*fs, d.gx, d.gy, x, y);
+        const float3 c = fov_colour(*fs, x, y, p, lv);
+        c0 = c.x;
+        c1 = c.y;
+        c2 = c.z;
+    } else {
+        lv = ld<kNtLevel>(d.level + p);
+        const float* color = d.color + 3 * (size_t)p;
+        c0 = ld<kNtColor>(color + 0);
+        c1 = ld<kNtColor>(color + 1);
+        c2 = ld<kNtColor>(color + 2);
+    }
     const float dx = ((float)x + 0.5f) - d.gx;
     const float dy = ((float)y + 0.5f) - d.gy;
     const float w = weight_eq4(d.c, dx * dx + dy * dy, lv);
@@ -373,8 +392,8 @@ __device__ __forceinline__ uint32_t pixel_per_slot(const FrameDesc& d, uint32_t 
 // One work item (256 pixels).  The wave index is made explicit as a uniform
 // value so the tile arithmetic runs on the scalar unit.
 // ---------------------------------------------------------------------------
-template <int K, int OP, bool PER_SLOT = false>
-__device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t item)
+template <int K, int OP, bool PER_SLOT = false, bool FOV = false>
+__device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t item, const FovSrc* fs = nullptr)
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -389,8 +408,8 @@ __device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t it
     const uint32_t x = (tx << d.tile_x_log2) + (local & ((1u << d.tile_x_log2) - 1u));
     const uint32_t y = (ty << d.tile_y_log2) + (local >> d.tile_x_log2);
     if (y >= d.height || x >= d.width) return 0u;
-    if constexpr (PER_SLOT) return pixel_per_slot<K, OP>(d, x, y);
-    return pixel<K, OP>(d, x, y);
+    if constexpr (PER_SLOT) return pixel_per_slot<K, OP, FOV>(d, x, y, fs);
+    return pixel<K, OP, FOV>(d, x, y, fs);
 }
 
 __device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t v)
@@ -606,6 +625,133 @@ __global__ __launch_bounds__(kBlock) void reproject_kernel(ReprojDesc r)
     if (d.stats) add_stats(d.stats, n);
 }
 
+// ---------------------------------------------------------------------------
+// Foveation generator (Sec. 4.3).  mip_kernel: one thread per mip-2 texel
+// builds its (up to) 2x2 mip-1 texels from the full frame and then itself, each
+// texel the mean of the children that exist, summed in row-major order.
+// blur kernels: separable Gaussian, clamp to edge, accumulation in offset
+// order.  foveate_kernel: the degraded frame and level map on their own;
+// foveated_kernel: the same sampling fused into the reservoir pass.
+// ---------------------------------------------------------------------------
+struct MipArgs {
+    const float* full;
+    float* m1;
+    float* m2;
+    uint32_t w, h, w1, h1, w2, h2;
+};
+
+__device__ __forceinline__ float3 texel_mean(const float* src, uint32_t sw, uint32_t sh, uint32_t i, uint32_t j)
+{
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    uint32_t n = 0u;
+#pragma unroll
+    for (uint32_t dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (uint32_t dx = 0; dx < 2; ++dx) {
+            const uint32_t x = 2 * i + dx, y = 2 * j + dy;
+            if (x < sw && y < sh) {
+                const float* c = src + ((size_t)y * sw + x) * 3;
+                s0 = s0 + c[0];
+                s1 = s1 + c[1];
+                s2 = s2 + c[2];
+                n = n + 1u;
+            }
+        }
+    const float fn = (float)n;
+    return make_float3(s0 / fn, s1 / fn, s2 / fn);
+}
+
+__global__ __launch_bounds__(kBlock) void mip_kernel(MipArgs a)
+{
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= a.w2 * a.h2) return;
+    const uint32_t i2 = t % a.w2, j2 = t / a.w2;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    uint32_t n = 0u;
+#pragma unroll
+    for (uint32_t dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (uint32_t dx = 0; dx < 2; ++dx) {
+            const uint32_t i1 = 2 * i2 + dx, j1 = 2 * j2 + dy;
+            if (i1 < a.w1 && j1 < a.h1) {
+                const float3 m = texel_mean(a.full, a.w, a.h, i1, j1);
+                float* o = a.m1 + ((size_t)j1 * a.w1 + i1) * 3;
+                o[0] = m.x;
+                o[1] = m.y;
+                o[2] = m.z;
+                s0 = s0 + m.x;
+                s1 = s1 + m.y;
+                s2 = s2 + m.z;
+                n = n + 1u;
+            }
+        }
+    const float fn = (float)n;
+    float* o = a.m2 + ((size_t)j2 * a.w2 + i2) * 3;
+    o[0] = s0 / fn;
+    o[1] = s1 / fn;
+    o[2] = s2 / fn;
+}
+
+struct BlurArgs {
+    const float* src;
+    float* dst;
+    uint32_t w, h;
+    int radius;
+    float wt[2 * kMaxBlurRadius + 1];
+};
+
+template <bool VERTICAL>
+__global__ __launch_bounds__(kBlock) void blur_kernel(BlurArgs a)
+{
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= a.w * a.h) return;
+    const int x = (int)(p % a.w), y = (int)(p / a.w);
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int d = -a.radius; d <= a.radius; ++d) {
+        int xx = x, yy = y;
+        if (VERTICAL) yy = min(max(y + d, 0), (int)a.h - 1);
+        else xx = min(max(x + d, 0), (int)a.w - 1);
+        const float* c = a.src + ((size_t)yy * a.w + (uint32_t)xx) * 3;
+        const float g = a.wt[d + a.radius];
+        s0 = s0 + g * c[0];
+        s1 = s1 + g * c[1];
+        s2 = s2 + g * c[2];
+    }
+    float* o = a.dst + (size_t)p * 3;
+    o[0] = s0;
+    o[1] = s1;
+    o[2] = s2;
+}
+
+struct FoveateArgs {
+    FovSrc s;
+    float* color;
+    uint8_t* level;
+    uint32_t w, h;
+    float gx, gy;
+};
+
+__global__ __launch_bounds__(kBlock) void foveate_kernel(FoveateArgs a)
+{
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= a.w * a.h) return;
+    const uint32_t x = p % a.w, y = p / a.w;
+    const uint32_t lv = fov_level(a.s, a.gx, a.gy, x, y);
+    const float3 c = fov_colour(a.s, x, y, p, lv);
+    float* o = a.color + (size_t)p * 3;
+    o[0] = c.x;
+    o[1] = c.y;
+    o[2] = c.z;
+    a.level[p] = (uint8_t)lv;
+}
+
+template <int K, bool PER_SLOT, int OP>
+__global__ __launch_bounds__(kBlock) void foveated_kernel(FovDesc fd)
+{
+    const uint32_t n = process_item<K, OP, PER_SLOT, true>(fd.f, blockIdx.x, &fd.s);
+    if (fd.f.stats) add_stats(fd.f.stats, n);
+}
+
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, size_t n, uint32_t v)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -675,6 +821,69 @@ hipError_t launch_reproject(const ReprojDesc& r, hipStream_t stream)
             else hipLaunchKernelGGL((reproject_kernel<0, false>), grid, block, 0, stream, r);
             break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_mips(const float* full, float* m1, float* m2, uint32_t w, uint32_t h, hipStream_t stream)
+{
+    MipArgs a{full, m1, m2, w, h, (w + 1) / 2, (h + 1) / 2, 0u, 0u};
+    a.w2 = (a.w1 + 1) / 2;
+    a.h2 = (a.h1 + 1) / 2;
+    const uint32_t n = a.w2 * a.h2;
+    hipLaunchKernelGGL(mip_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_blur(const float* src, float* tmp, float* dst, uint32_t w, uint32_t h, int radius,
+                       const float* weights, hipStream_t stream)
+{
+    if (radius < 0 || radius > kMaxBlurRadius) return hipErrorInvalidValue;
+    BlurArgs a{};
+    a.w = w;
+    a.h = h;
+    a.radius = radius;
+    for (int i = 0; i <= 2 * radius; ++i) a.wt[i] = weights[i];
+    const uint32_t n = w * h;
+    const dim3 grid((n + kBlock - 1) / kBlock), block(kBlock);
+    a.src = src;
+    a.dst = tmp;
+    hipLaunchKernelGGL(blur_kernel<false>, grid, block, 0, stream, a);
+    a.src = tmp;
+    a.dst = dst;
+    hipLaunchKernelGGL(blur_kernel<true>, grid, block, 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_foveate(const FovSrc& s, float* color, uint8_t* level, uint32_t w, uint32_t h, float gx, float gy,
+                          hipStream_t stream)
+{
+    FoveateArgs a{s, color, level, w, h, gx, gy};
+    const uint32_t n = w * h;
+    hipLaunchKernelGGL(foveate_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_foveated(const FovDesc& fd, bool resolve, hipStream_t stream)
+{
+    if (fd.f.items == 0u) return hipSuccess;
+    const dim3 grid(fd.f.items), block(kBlock);
+    const bool ps = per_slot_mode(fd.f.bias);
+#define FWRS_FOV_LAUNCH(KK, PS)                                                                       \
+    do {                                                                                              \
+        if (resolve) hipLaunchKernelGGL((foveated_kernel<KK, PS, kFused>), grid, block, 0, stream, fd); \
+        else hipLaunchKernelGGL((foveated_kernel<KK, PS, kPush>), grid, block, 0, stream, fd);         \
+    } while (0)
+    if (ps) {
+        if (fd.f.k == 4) FWRS_FOV_LAUNCH(4, true);
+        else FWRS_FOV_LAUNCH(0, true);
+    } else {
+        switch (fd.f.k) {
+            case 4: FWRS_FOV_LAUNCH(4, false); break;
+            case 8: FWRS_FOV_LAUNCH(8, false); break;
+            default: FWRS_FOV_LAUNCH(0, false); break;
+        }
+    }
+#undef FWRS_FOV_LAUNCH
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfwrs.so")
 OK, E_ARG, E_NOMEM, E_HIP, E_STATE = 0, 1, 2, 3, 4
 BIAS_NONE, BIAS_BERNOULLI, BIAS_FULL, BIAS_MEMORYLESS, AES = 0, 1, 2, 3, 4
 FLAG_REPROJECT = 1
+FOV_MIP, FOV_GAUSS = 0, 1
 MAX_K = 16
 
 #: every symbol include/fwrs.h declares
@@ -28,7 +29,8 @@ EXPORTS = (
     "fwrs_push_frame_resolve", "fwrs_push_frame_resolve_incremental", "fwrs_push_frame_reproject",
     "fwrs_frame_index", "fwrs_get_state", "fwrs_download_state", "fwrs_get_stats",
     "fwrs_set_tile", "fwrs_sync", "fwrs_strerror", "fwrs_engine_create", "fwrs_engine_tick",
-    "fwrs_engine_set_tile", "fwrs_engine_destroy",
+    "fwrs_engine_set_tile", "fwrs_engine_destroy", "fwrs_foveator_create", "fwrs_foveate",
+    "fwrs_push_frame_foveated", "fwrs_foveator_destroy",
 )
 
 
@@ -127,6 +129,10 @@ def load(path: str | None = None):
         "fwrs_engine_tick": (i, [vp, C.POINTER(Frame), i]),
         "fwrs_engine_set_tile": (i, [vp, C.c_longlong, i, i]),
         "fwrs_engine_destroy": (i, [vp]),
+        "fwrs_foveator_create": (i, [i, i, f, f, u32, vp, C.POINTER(vp)]),
+        "fwrs_foveate": (i, [vp, vp, f, f, vp, vp]),
+        "fwrs_push_frame_foveated": (i, [vp, vp, vp, f, f, vp]),
+        "fwrs_foveator_destroy": (i, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -301,6 +307,16 @@ class Reservoir:
                                                  _ptr(out) if out is not None else None),
                "fwrs_push_frame_reproject")
 
+    def step_foveated(self, foveator: "Foveator", full, gaze_x: float, gaze_y: float, out=None) -> None:
+        """fwrs_push_frame_foveated: the foveator degrades the full frame and the reservoir pass
+        samples its candidates from the level images directly; resolves into `out` if given."""
+        foveator._check_full(full)
+        if out is not None:
+            self._check_out(out)
+        _check(self._L.fwrs_push_frame_foveated(self._h, foveator._h, _ptr(full), float(gaze_x), float(gaze_y),
+                                                _ptr(out) if out is not None else None),
+               "fwrs_push_frame_foveated")
+
     @property
     def frame_index(self) -> int:
         t = C.c_uint32()
@@ -389,3 +405,43 @@ class Engine:
             fr.out = _ptr(out)
             n += 1
         _check(self._L.fwrs_engine_tick(self._h, self._frames, n), "fwrs_engine_tick")
+
+
+class Foveator:
+    """The foveation generator: full frame -> degraded frame + level map (mip + bilinear or
+    Gaussian), standalone or fused into a context's frame (Reservoir.step_foveated)."""
+
+    def __init__(self, width: int, height: int, fovea_radius_px: float, ring_radius_px: float,
+                 mode: int = FOV_MIP, stream=None):
+        self._L = load()
+        self.width, self.height, self.mode = int(width), int(height), int(mode)
+        h = C.c_void_p()
+        _check(self._L.fwrs_foveator_create(self.width, self.height, float(fovea_radius_px), float(ring_radius_px),
+                                            self.mode, _stream_handle(stream), C.byref(h)), "fwrs_foveator_create")
+        self._h = h
+
+    def _check_full(self, full) -> None:
+        H, W = self.height, self.width
+        if tuple(full.shape) != (H, W, 3) or full.dtype.itemsize != 4 or not full.is_contiguous() or not full.is_cuda:
+            raise ValueError(f"full must be a contiguous float32 device tensor [{H}, {W}, 3]")
+
+    def foveate(self, full, gaze_x: float, gaze_y: float, color, level) -> None:
+        self._check_full(full)
+        H, W = self.height, self.width
+        if tuple(color.shape) != (H, W, 3) or not color.is_contiguous() or not color.is_cuda:
+            raise ValueError("color must be a contiguous float32 device tensor [H, W, 3]")
+        if tuple(level.shape) != (H, W) or level.dtype.itemsize != 1 or not level.is_contiguous():
+            raise ValueError("level must be a contiguous uint8 device tensor [H, W]")
+        _check(self._L.fwrs_foveate(self._h, _ptr(full), float(gaze_x), float(gaze_y), _ptr(color), _ptr(level)),
+               "fwrs_foveate")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(self._L.fwrs_foveator_destroy(self._h), "fwrs_foveator_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,141 @@
+"""Parity of the foveation generator (Sec. 4.3) and of the reservoir pass fed by it, through the C ABI.
+
+The generator's degraded frame and level map are compared with the oracle's bit for bit; the fused
+pass (levels sampled inside the reservoir kernel) must leave every state plane bit-identical to the
+oracle run on the oracle's foveated frames, and its output identical to the unfused GPU path."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2510_03964_amd import fwrs, synth
+
+pytestmark = pytest.mark.gpu
+COLOR_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fwrs.load()
+    return torch.device("cuda:0")
+
+
+def _full(spec, t, dev):
+    """A full-resolution frame: the moving workload's render at frame t."""
+    return synth.MovingSource(spec, device=dev, n_frames=t + 1).render(t)[0]
+
+
+@pytest.mark.parametrize("mode", [fwrs.FOV_MIP, fwrs.FOV_GAUSS])
+@pytest.mark.parametrize("w,h", [(96, 64), (37, 23), (1, 1), (255, 3), (3, 130), (640, 360)])
+def test_foveate_matches_oracle(dev, mode, w, h):
+    spec = synth.StreamSpec(w, h, 4, 3, max(1.0, 0.08 * w), max(2.0, 0.2 * w), 1.0, 2, 2.0)
+    gaze = synth.gaze_trace(spec, 3)
+    fov = fwrs.Foveator(w, h, spec.fovea_radius_px, spec.ring_radius_px, mode, stream=torch.cuda.current_stream())
+    col = torch.empty((h, w, 3), device=dev)
+    lev = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    for t in range(3):
+        full = _full(spec, t, dev)
+        gx, gy = float(gaze[t, 0]), float(gaze[t, 1])
+        fov.foveate(full, gx, gy, col, lev)
+        oc, ol = oracle.foveate(full.cpu().numpy(), gx, gy, spec.fovea_radius_px, spec.ring_radius_px, mode)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(lev.cpu().numpy(), ol)
+        np.testing.assert_array_equal(col.cpu().numpy().view(np.uint32), oc.view(np.uint32))
+    fov.close()
+
+
+def _fused_vs_oracle(dev, spec, n, bias, mode, resolve=True):
+    p = fwrs.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED,
+                            stream_id=spec.stream_id, bias_mode=bias)
+    q = oracle.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED,
+                              stream_id=spec.stream_id, bias_mode=bias)
+    stream = torch.cuda.current_stream()
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=stream)
+    plain = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=stream)
+    orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
+    fov = fwrs.Foveator(spec.width, spec.height, spec.fovea_radius_px, spec.ring_radius_px, mode, stream=stream)
+    gaze = synth.gaze_trace(spec, n)
+    out = torch.full((spec.height, spec.width, 3), -1.0, device=dev)
+    out_plain = torch.empty_like(out)
+    col = torch.empty_like(out)
+    lev = torch.empty((spec.height, spec.width), dtype=torch.uint8, device=dev)
+    src = synth.MovingSource(spec, device=dev, n_frames=n)
+    for t in range(n):
+        full = src.render(t)[0]
+        gx, gy = float(gaze[t, 0]), float(gaze[t, 1])
+        res.step_foveated(fov, full, gx, gy, out if resolve else None)
+        fov.foveate(full, gx, gy, col, lev)
+        plain.step(col, lev, gx, gy, out_plain)
+        oc, ol = oracle.foveate(full.cpu().numpy(), gx, gy, spec.fovea_radius_px, spec.ring_radius_px, mode)
+        orc.push(oc, ol, gx, gy)
+    res.sync()
+    st, so = res.download(), orc.state()
+    for name in ("cnt", "idx"):
+        np.testing.assert_array_equal(getattr(st, name), getattr(so, name), err_msg=name)
+    for name in ("wsum", "wt", "col", "wslot"):
+        np.testing.assert_array_equal(getattr(st, name).view(np.uint32), getattr(so, name).view(np.uint32),
+                                      err_msg=name)
+    if resolve:
+        assert np.abs(out.cpu().numpy().astype(np.float64) - orc.resolve()).max() <= COLOR_TOL
+        assert torch.equal(out, out_plain)
+    assert res.stats() == plain.stats()
+    fov.close()
+    return res
+
+
+@pytest.mark.parametrize("mode", [fwrs.FOV_MIP, fwrs.FOV_GAUSS])
+@pytest.mark.parametrize("bias", [fwrs.BIAS_BERNOULLI, fwrs.BIAS_FULL, fwrs.AES])
+def test_fused_pass_matches_oracle_and_unfused(dev, mode, bias):
+    spec = synth.StreamSpec(160, 96, 4, 8, 12.0, 30.0, 1.0, 3, 3.0, stream_id=5)
+    _fused_vs_oracle(dev, spec, 8, bias, mode)
+
+
+@pytest.mark.parametrize("w,h,k", [(37, 23, 3), (128, 72, 8), (255, 3, 1), (64, 64, 16)])
+def test_fused_pass_sizes_and_slot_counts(dev, w, h, k):
+    spec = synth.StreamSpec(w, h, k, 4, max(1.0, 0.1 * w), max(2.0, 0.25 * w), 1.0, 2, 2.0, stream_id=k)
+    _fused_vs_oracle(dev, spec, 4, fwrs.BIAS_BERNOULLI, fwrs.FOV_MIP)
+
+
+def test_fused_update_only(dev):
+    spec = synth.StreamSpec(96, 64, 4, 5, 8.0, 20.0, 1.0, 2, 2.0)
+    res = _fused_vs_oracle(dev, spec, 5, fwrs.BIAS_BERNOULLI, fwrs.FOV_MIP, resolve=False)
+    assert res.frame_index == 5
+
+
+def test_foveator_argument_checks(dev):
+    stream = torch.cuda.current_stream()
+    with pytest.raises(fwrs.FwrsError):
+        fwrs.Foveator(64, 32, 10.0, 5.0, fwrs.FOV_MIP, stream=stream)        # ring inside the fovea
+    with pytest.raises(fwrs.FwrsError):
+        fwrs.Foveator(64, 32, 5.0, 10.0, 7, stream=stream)
+    fov = fwrs.Foveator(64, 32, 5.0, 10.0, fwrs.FOV_MIP, stream=stream)
+    other = fwrs.Reservoir(32, 32, 4, stream=stream)
+    full = torch.zeros((32, 64, 3), device=dev)
+    with pytest.raises(fwrs.FwrsError) as e:                 # context and foveator sizes differ
+        other.step_foveated(fov, full, 1.0, 1.0, None)
+    assert e.value.status == fwrs.E_ARG
+    with pytest.raises(ValueError):                          # frame not the foveator's size
+        fov.foveate(torch.zeros((32, 32, 3), device=dev), 1.0, 1.0, full, torch.empty((32, 64), dtype=torch.uint8,
+                                                                                        device=dev))
+    p = fwrs.default_params(64, flags=fwrs.FLAG_REPROJECT)
+    rep = fwrs.Reservoir(64, 32, 4, p, stream=stream)
+    with pytest.raises(fwrs.FwrsError) as e:
+        rep.step_foveated(fov, full, 1.0, 1.0, None)
+    assert e.value.status == fwrs.E_STATE
+    col = torch.empty_like(full)
+    lev = torch.empty((32, 64), dtype=torch.uint8, device=dev)
+    with pytest.raises(fwrs.FwrsError):
+        fov.foveate(full, float("inf"), 1.0, col, lev)
+    fov.close()
+
+
+@pytest.mark.parametrize("mode", [fwrs.FOV_MIP, fwrs.FOV_GAUSS])
+def test_4k_foveate_and_fused_frame(dev, mode):
+    """3840x2160: one full frame through the generator against the oracle, then two fused frames
+    of the reservoir pass with every state plane compared."""
+    spec = synth.spec_4k()
+    _fused_vs_oracle(dev, spec, 2, fwrs.BIAS_BERNOULLI, mode)
