@@ -512,19 +512,28 @@ __device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_
     const float4 empty = make_float4(0.f, 0.f, 0.f, 0.f);
     const bool aes = d.bias == kAes;
     const float empty_slot = aes ? -INFINITY : 0.f;      // A-ES key / Eq. 7 sum of an empty slot
+    // loads are unconditional (q = 0 is a valid pixel when the history is dropped) and the
+    // empty values are selected afterwards, so every load is a plain global load
     if (K) {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            rv[j] = keep ? src[j] : empty;
-            iv[j] = keep ? sidx[j] : 0xFFFFFFFFu;
-            if (PER_SLOT) W[j] = keep ? r.src_wsum[(size_t)q * (size_t)kk + j] : empty_slot;
+            const float4 v = src[j];
+            const uint32_t i = sidx[j];
+            rv[j] = keep ? v : empty;
+            iv[j] = keep ? i : 0xFFFFFFFFu;
+            if (PER_SLOT) {
+                const float ws = r.src_wsum[(size_t)q * (size_t)kk + j];
+                W[j] = keep ? ws : empty_slot;
+            }
         }
     }
     float W1 = 0.f;
     uint32_t m = 0u;
-    if (keep) {
-        if (!PER_SLOT) W1 = r.src_wsum[q];
-        m = r.src_cnt[q];
+    {
+        const float ws = PER_SLOT ? 0.f : r.src_wsum[q];
+        const uint32_t mc = r.src_cnt[q];
+        W1 = keep ? ws : 0.f;
+        m = keep ? mc : 0u;
     }
 
     // 3. this frame's candidate
@@ -558,9 +567,14 @@ __device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_
             vi = iv[K ? j : 0];
             if (PER_SLOT) Wj = W[K ? j : 0];
         } else {
-            v = keep ? src[j] : empty;
-            vi = keep ? sidx[j] : 0xFFFFFFFFu;
-            if (PER_SLOT) Wj = keep ? r.src_wsum[(size_t)q * (size_t)kk + j] : empty_slot;
+            const float4 sv = src[j];
+            const uint32_t si = sidx[j];
+            v = keep ? sv : empty;
+            vi = keep ? si : 0xFFFFFFFFu;
+            if (PER_SLOT) {
+                const float ws = r.src_wsum[(size_t)q * (size_t)kk + j];
+                Wj = keep ? ws : empty_slot;
+            }
         }
         if ((j & 3) == 0) words = philox4x32_10(p, d.t, (uint32_t)(j >> 2), 0u, d.seed, d.stream_id);
         const uint32_t word = (j & 3) == 0 ? words.x : (j & 3) == 1 ? words.y : (j & 3) == 2 ? words.z : words.w;
