@@ -31,6 +31,10 @@ sys.path.insert(0, ROOT)
 METRIC = "4K k=4 update+resolve ms & Gpix/s, %HBM peak; multi-stream p99 vs plain"
 HBM_PEAK_GBPS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "fused_k4_4k_counters.json")
+VALU_COUNTERS = os.path.join(ROOT, "profiles", "fused_valu_4k_counters.json")
+#: VALU issue peak of the MI355X in lane-operations per second: the published fp32 vector rate, 157.3 TFLOP/s,
+#: counts a fused multiply-add as two flops, i.e. 78.6 T lane-operations/s (256 CUs x 128 lanes x 2.4 GHz)
+VALU_PEAK_TOPS = 78.6
 
 
 def log(msg: str) -> None:
@@ -85,6 +89,18 @@ def traffic_from_counters(n_pixels: int) -> float | None:
     if c.get("source_hash") != kernel_source_hash() or c.get("pixels") != n_pixels:
         return None
     return 1024.0 * (c["fetch_kib_per_dispatch"] * c["fetch_scale"] + c["write_kib_per_dispatch"] * c["write_scale"])
+
+
+def valu_per_pixel(kernel: str) -> float | None:
+    """VALU instructions per pixel of `kernel` (one thread per pixel) from the committed counter summary, if it was
+    taken on the current kernel sources; None otherwise."""
+    if not os.path.exists(VALU_COUNTERS):
+        return None
+    with open(VALU_COUNTERS) as f:
+        c = json.load(f)
+    if c.get("source_hash") != kernel_source_hash() or kernel not in c.get("kernels", {}):
+        return None
+    return float(c["kernels"][kernel]["valu_insts_per_wave"])
 
 
 def timed_run(res, frames, out, stream, step):
@@ -544,13 +560,21 @@ def main() -> int:
         f_B = bytes_per_update_eq7(spec.k, f_rbar)
         f_kern = float(f_per.mean())
         f_ach = spec.pixels * f_B / (f_kern / 1e3) / 1e9
+        vpp = valu_per_pixel("void fwrs::frame_kernel<4, 3, true>(fwrs::FrameDesc)")
+        alu = None
+        if vpp is not None:
+            a_t = spec.pixels * vpp / (f_kern / 1e3) / 1e12
+            alu = {"bound": "alu", "achieved": a_t, "peak": VALU_PEAK_TOPS, "unit": "T VALU lane-ops/s",
+                   "frac": a_t / VALU_PEAK_TOPS, "valu_per_pixel": vpp,
+                   "kernel": "fwrs::frame_kernel<4, 3, true> (Eq. 7)"}
         eq7 = {"entry": "fwrs_push_frame_resolve (FWRS_BIAS_FULL)", "frames": K, "ms_per_step": f_ms / K,
                "value": spec.pixels * K / (f_ms / 1e3) / 1e9, "unit": "Gpixel-updates/s",
                "ms_per_frame_p50": float(np.percentile(f_per, 50)),
                "ms_per_frame_p99": float(np.percentile(f_per, 99)),
                "hbm": {"achieved": f_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": f_ach / HBM_PEAK_GBPS,
                        "kernel_ms_avg": f_kern, "bytes_per_pixel_update": f_B,
-                       "slot_takes_per_pixel_update": f_rbar}}
+                       "slot_takes_per_pixel_update": f_rbar},
+               "roofline": alu}
         log(f"eq7: {f_ms / K:.4f} ms/frame")
 
     ablation = None if args.no_ablations else ablations(dev, stream, spec, frames, tile)
