@@ -118,5 +118,13 @@ def test_invalid_arguments_are_rejected_before_any_gpu_work():
     assert L.fwrs_destroy(None) == fwrs.OK
     assert L.fwrs_engine_destroy(None) == fwrs.OK
     assert L.fwrs_engine_create(None, 0, 0, C.byref(h)) == fwrs.E_ARG
+    # foveation generator: argument checks come before any device work
+    for args in [(0, 32, 5.0, 10.0, 0), (64, 32, 10.0, 5.0, 0), (64, 32, 5.0, 10.0, 7), (64, 32, float("nan"), 10.0, 0),
+                 (64, 32, -1.0, 10.0, 0)]:
+        assert L.fwrs_foveator_create(*args, None, C.byref(h)) == fwrs.E_ARG, args
+    assert L.fwrs_foveator_create(64, 32, 5.0, 10.0, 0, None, None) == fwrs.E_ARG
+    assert L.fwrs_foveate(None, None, 0.0, 0.0, None, None) == fwrs.E_ARG
+    assert L.fwrs_push_frame_foveated(None, None, None, 0.0, 0.0, None) == fwrs.E_ARG
+    assert L.fwrs_foveator_destroy(None) == fwrs.OK
     assert fwrs.strerror(fwrs.E_ARG) == "invalid argument"
     assert fwrs.strerror(99) == "unknown status"
