@@ -389,24 +389,30 @@ int fwrs_oracle_foveate(const float* full, int width, int height, float gx, floa
 /* ------------------------------------------------------------------------ */
 /* Colour difference for Eq. 7.                                               */
 /* ------------------------------------------------------------------------ */
-/* Cube root for t > 0: a seed from the exponent bits (the bit pattern of     */
-/* t^(1/3) is about bits(t)/3 + (2/3)*127*2^23), then Newton steps            */
-/* y <- y - (y^3 - t) / (3 y^2).                                              */
+/* Cube root for t > 0 without division: the reciprocal cube root r from an  */
+/* exponent-bit seed (the bit pattern of t^(-1/3) is about                    */
+/* (4/3)*127*2^23 - bits(t)/3), two Newton steps r <- r (4 - t r^3) / 3, then */
+/* y = t r^2 and one Newton step on y itself, y <- y - (y^3 - t) r^2 / 3      */
+/* (r^2 standing in for 1 / y^2).  1/3 is its binary32 rounding.             */
 float fwrs_oracle_cbrt(float t)
 {
     uint32_t bits;
     memcpy(&bits, &t, 4);
-    bits = bits / 3u + 0x2A555555u;
-    float y;
-    memcpy(&y, &bits, 4);
-    for (int it = 0; it < 4; ++it) {
-        float y2 = y * y;
-        float y3 = y2 * y;
-        float num = y3 - t;
-        float den = 3.0f * y2;
-        y = y - num / den;
+    bits = 0x54A2FA8Cu - bits / 3u;
+    float r;
+    memcpy(&r, &bits, 4);
+    const float third = 0x1.555556p-2f;
+    for (int it = 0; it < 2; ++it) {
+        float r2 = r * r;
+        float r3 = r2 * r;
+        float d = 4.0f - t * r3;
+        r = (r * d) * third;
     }
-    return y;
+    float r2 = r * r;
+    float y = t * r2;
+    float y3 = (y * y) * y;
+    float c = ((y3 - t) * r2) * third;
+    return y - c;
 }
 
 /* CIE Lab f(): cube root above (6/29)^3, the linear segment below. */

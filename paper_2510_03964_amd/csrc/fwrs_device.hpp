@@ -278,20 +278,26 @@ __device__ __forceinline__ float3 fov_colour(const FovSrc& s, uint32_t x, uint32
 // Lab (D65 white), then the CIE94 difference with graphic-arts weights and the
 // reservoir sample as the reference; |dL| = min(1, dE94 / 100).
 // ---------------------------------------------------------------------------
-// Cube root, t > 0: exponent-bit seed (bits(t^(1/3)) ~ bits(t)/3 + 2/3 * 127 * 2^23)
-// refined by four Newton steps y <- y - (y^3 - t) / (3 y^2).
+// Cube root, t > 0, without division: reciprocal cube root r from an exponent-bit
+// seed (bits(t^(-1/3)) ~ 4/3 * 127 * 2^23 - bits(t)/3), two Newton steps
+// r <- r (4 - t r^3) / 3, then y = t r^2 and one Newton step on y with r^2 for
+// 1 / y^2: y <- y - (y^3 - t) r^2 / 3.  1/3 is its binary32 rounding.
 __device__ __forceinline__ float cube_root(float t)
 {
-    float y = __uint_as_float(__float_as_uint(t) / 3u + 0x2A555555u);
+    float r = __uint_as_float(0x54A2FA8Cu - __float_as_uint(t) / 3u);
+    const float third = 0x1.555556p-2f;
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-        const float y2 = y * y;
-        const float y3 = y2 * y;
-        const float num = y3 - t;
-        const float den = 3.0f * y2;
-        y = y - num / den;
+    for (int it = 0; it < 2; ++it) {
+        const float r2 = r * r;
+        const float r3 = r2 * r;
+        const float d = 4.0f - t * r3;
+        r = (r * d) * third;
     }
-    return y;
+    const float r2 = r * r;
+    const float y = t * r2;
+    const float y3 = (y * y) * y;
+    const float c = ((y3 - t) * r2) * third;
+    return y - c;
 }
 
 __device__ __forceinline__ float lab_curve(float t)

@@ -42,6 +42,13 @@ def test_cbrt_against_libm(oracle_mod):
     ulp = np.ldexp(1.0, np.floor(np.log2(want)).astype(np.int64) - 23)
     assert (np.abs(got - want) / ulp).max() <= 1.0
     assert oracle_mod.cbrt(np.array([1.0, 0.125, 8.0], np.float32)).tolist() == [1.0, 0.5, 2.0]
+    # HDR inputs and far beyond: every 997th binary32 in [2, 2^40)
+    c = np.array([2.0, 2.0 ** 40], np.float32).view(np.uint32)
+    t = np.arange(c[0], c[1], 997, dtype=np.uint32).view(np.float32)
+    got = oracle_mod.cbrt(t).astype(np.float64)
+    want = np.cbrt(t.astype(np.float64))
+    ulp = np.ldexp(1.0, np.floor(np.log2(want)).astype(np.int64) - 23)
+    assert (np.abs(got - want) / ulp).max() <= 1.0
 
 
 def test_lab_special_cases(oracle_mod):

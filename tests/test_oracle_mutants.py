@@ -50,7 +50,8 @@ MUTANTS = {
     "lab_lightness_offset": ("lab[0] = 116.0f * fy - 16.0f;", "lab[0] = 116.0f * fy - 15.0f;"),
     "lab_knee_ignored": ("if (t > eps) return fwrs_oracle_cbrt(t);", "if (t > -1.0f) return fwrs_oracle_cbrt(t);"),
     "cie94_chroma_of_wrong_colour": ("float SC = 1.0f + 0.045f * C1;", "float SC = 1.0f + 0.045f * C2;"),
-    "cbrt_too_few_newton_steps": ("for (int it = 0; it < 4; ++it) {", "for (int it = 0; it < 1; ++it) {"),
+    "cbrt_too_few_newton_steps": ("for (int it = 0; it < 2; ++it) {", "for (int it = 0; it < 1; ++it) {"),
+    "cbrt_final_step_dropped": ("    return y - c;\n}", "    return y + 0.0f * c;\n}"),
     "xyz_matrix_entry": ("0.3575761f * g", "0.3757561f * g"),
     "reproject_motion_sign": ("const float sx = ((float)x + 0.5f) - motion[2 * p + 0];",
                               "const float sx = ((float)x + 0.5f) + motion[2 * p + 0];"),
