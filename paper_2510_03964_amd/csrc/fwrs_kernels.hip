@@ -654,25 +654,39 @@ struct MipArgs {
     uint32_t w, h, w1, h1, w2, h2;
 };
 
+// 1 / n for the child counts a texel can have (1, 2 or 4): a power of two, so
+// s * (1 / n) is exactly the correctly rounded s / n.
+__device__ __forceinline__ float inv_count(uint32_t n)
+{
+    return n == 4u ? 0.25f : (n == 2u ? 0.5f : 1.0f);
+}
+
+// Mean of the children (2i + dx, 2j + dy) of a texel; every load is issued
+// before the sums (children outside the source read the texel's first child
+// and are not added).
 __device__ __forceinline__ float3 texel_mean(const float* src, uint32_t sw, uint32_t sh, uint32_t i, uint32_t j)
 {
+    float3 v[4];
+    bool in[4];
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t x = 2 * i + (q & 1u), y = 2 * j + (q >> 1);
+        in[q] = x < sw && y < sh;
+        const float* c = src + ((size_t)(in[q] ? y : 2 * j) * sw + (in[q] ? x : 2 * i)) * 3;
+        v[q] = make_float3(c[0], c[1], c[2]);
+    }
     float s0 = 0.f, s1 = 0.f, s2 = 0.f;
     uint32_t n = 0u;
 #pragma unroll
-    for (uint32_t dy = 0; dy < 2; ++dy)
-#pragma unroll
-        for (uint32_t dx = 0; dx < 2; ++dx) {
-            const uint32_t x = 2 * i + dx, y = 2 * j + dy;
-            if (x < sw && y < sh) {
-                const float* c = src + ((size_t)y * sw + x) * 3;
-                s0 = s0 + c[0];
-                s1 = s1 + c[1];
-                s2 = s2 + c[2];
-                n = n + 1u;
-            }
+    for (uint32_t q = 0; q < 4; ++q)
+        if (in[q]) {
+            s0 = s0 + v[q].x;
+            s1 = s1 + v[q].y;
+            s2 = s2 + v[q].z;
+            n = n + 1u;
         }
-    const float fn = (float)n;
-    return make_float3(s0 / fn, s1 / fn, s2 / fn);
+    const float r = inv_count(n);
+    return make_float3(s0 * r, s1 * r, s2 * r);
 }
 
 __global__ __launch_bounds__(kBlock) void mip_kernel(MipArgs a)
@@ -680,30 +694,34 @@ __global__ __launch_bounds__(kBlock) void mip_kernel(MipArgs a)
     const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= a.w2 * a.h2) return;
     const uint32_t i2 = t % a.w2, j2 = t / a.w2;
+    float3 m[4];
+    bool in[4];
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t i1 = 2 * i2 + (q & 1u), j1 = 2 * j2 + (q >> 1);
+        in[q] = i1 < a.w1 && j1 < a.h1;
+        m[q] = texel_mean(a.full, a.w, a.h, in[q] ? i1 : 2 * i2, in[q] ? j1 : 2 * j2);
+    }
     float s0 = 0.f, s1 = 0.f, s2 = 0.f;
     uint32_t n = 0u;
 #pragma unroll
-    for (uint32_t dy = 0; dy < 2; ++dy)
-#pragma unroll
-        for (uint32_t dx = 0; dx < 2; ++dx) {
-            const uint32_t i1 = 2 * i2 + dx, j1 = 2 * j2 + dy;
-            if (i1 < a.w1 && j1 < a.h1) {
-                const float3 m = texel_mean(a.full, a.w, a.h, i1, j1);
-                float* o = a.m1 + ((size_t)j1 * a.w1 + i1) * 3;
-                o[0] = m.x;
-                o[1] = m.y;
-                o[2] = m.z;
-                s0 = s0 + m.x;
-                s1 = s1 + m.y;
-                s2 = s2 + m.z;
-                n = n + 1u;
-            }
+    for (uint32_t q = 0; q < 4; ++q)
+        if (in[q]) {
+            const uint32_t i1 = 2 * i2 + (q & 1u), j1 = 2 * j2 + (q >> 1);
+            float* o = a.m1 + ((size_t)j1 * a.w1 + i1) * 3;
+            o[0] = m[q].x;
+            o[1] = m[q].y;
+            o[2] = m[q].z;
+            s0 = s0 + m[q].x;
+            s1 = s1 + m[q].y;
+            s2 = s2 + m[q].z;
+            n = n + 1u;
         }
-    const float fn = (float)n;
+    const float r = inv_count(n);
     float* o = a.m2 + ((size_t)j2 * a.w2 + i2) * 3;
-    o[0] = s0 / fn;
-    o[1] = s1 / fn;
-    o[2] = s2 / fn;
+    o[0] = s0 * r;
+    o[1] = s1 * r;
+    o[2] = s2 * r;
 }
 
 struct BlurArgs {
@@ -714,19 +732,22 @@ struct BlurArgs {
     float wt[2 * kMaxBlurRadius + 1];
 };
 
-template <bool VERTICAL>
+// RADIUS > 0: compile-time radius (every tap's load issued up front); 0: a.radius.
+template <bool VERTICAL, int RADIUS>
 __global__ __launch_bounds__(kBlock) void blur_kernel(BlurArgs a)
 {
     const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= a.w * a.h) return;
     const int x = (int)(p % a.w), y = (int)(p / a.w);
+    const int rad = RADIUS ? RADIUS : a.radius;
     float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-    for (int d = -a.radius; d <= a.radius; ++d) {
+#pragma unroll
+    for (int d = -rad; d <= rad; ++d) {
         int xx = x, yy = y;
         if (VERTICAL) yy = min(max(y + d, 0), (int)a.h - 1);
         else xx = min(max(x + d, 0), (int)a.w - 1);
         const float* c = a.src + ((size_t)yy * a.w + (uint32_t)xx) * 3;
-        const float g = a.wt[d + a.radius];
+        const float g = a.wt[d + rad];
         s0 = s0 + g * c[0];
         s1 = s1 + g * c[1];
         s2 = s2 + g * c[2];
@@ -859,12 +880,19 @@ hipError_t launch_blur(const float* src, float* tmp, float* dst, uint32_t w, uin
     for (int i = 0; i <= 2 * radius; ++i) a.wt[i] = weights[i];
     const uint32_t n = w * h;
     const dim3 grid((n + kBlock - 1) / kBlock), block(kBlock);
+#define FWRS_BLUR_PASS(V)                                                                            \
+    do {                                                                                             \
+        if (radius == 3) hipLaunchKernelGGL((blur_kernel<V, 3>), grid, block, 0, stream, a);          \
+        else if (radius == 6) hipLaunchKernelGGL((blur_kernel<V, 6>), grid, block, 0, stream, a);     \
+        else hipLaunchKernelGGL((blur_kernel<V, 0>), grid, block, 0, stream, a);                      \
+    } while (0)
     a.src = src;
     a.dst = tmp;
-    hipLaunchKernelGGL(blur_kernel<false>, grid, block, 0, stream, a);
+    FWRS_BLUR_PASS(false);
     a.src = tmp;
     a.dst = dst;
-    hipLaunchKernelGGL(blur_kernel<true>, grid, block, 0, stream, a);
+    FWRS_BLUR_PASS(true);
+#undef FWRS_BLUR_PASS
     return hipGetLastError();
 }
 
