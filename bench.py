@@ -416,9 +416,16 @@ def cpu_baseline(frames_host, spec, n_frames: int) -> dict:
         o.resolve()
     dt = time.perf_counter() - t0
     px = spec.pixels * n_frames
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": px / dt / 1e9, "unit": "Gpixel-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n_frames} frames of the same 3840x2160 k=4 trace, full frames, update + resolve, "
-                      f"single-threaded C oracle ({dt:.1f} s)", "ms_per_frame": 1000.0 * dt / n_frames}
+                      f"single-threaded C oracle ({dt:.1f} s)", "ms_per_frame": 1000.0 * dt / n_frames,
+            "cpu_model": model, "host_threads_available": os.cpu_count()}
 
 
 def copy_bandwidth(torch, dev, nbytes: int = 1 << 30, reps: int = 20) -> float:
@@ -444,7 +451,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=600, help="timed frames (from an empty reservoir)")
     ap.add_argument("--warmup", type=int, default=10, help="untimed frames on a separate context")
-    ap.add_argument("--cpu-frames", type=int, default=8, help="frames of the oracle CPU baseline (0: skip)")
+    ap.add_argument("--cpu-frames", type=int, default=24, help="frames of the oracle CPU baseline (0: skip)")
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y override")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth reference")
     ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-resolve run")
