@@ -644,7 +644,7 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
-                     "kernel": "fwrs::frame_kernel<4, 3> (fused update + full resolve)",
+                     "kernel": "fwrs::frame_kernel<4, 3, false> (fused update + full resolve)",
                      "kernel_ms_avg": kern_ms, "bytes_per_pixel_update": B, "slot_takes_per_pixel_update": rbar},
         "cpu_baseline": cpu,
         "ms_per_frame_p50": float(np.percentile(per, 50)),
