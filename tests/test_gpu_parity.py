@@ -464,3 +464,13 @@ def test_eq7_engine_mixes_bias_modes(dev, use_graph):
         _compare_state(ctxs[i].download(), orcs[i].state(), f"stream {i} bias {modes[i]}")
         _compare_out(outs[i].cpu().numpy(), orcs[i].resolve(), f"stream {i}")
     eng.close()
+
+
+@pytest.mark.parametrize("bias", [fwrs.BIAS_NONE, fwrs.BIAS_BERNOULLI, fwrs.BIAS_FULL, fwrs.BIAS_MEMORYLESS, fwrs.AES])
+def test_long_run_every_mode(dev, bias):
+    """600 frames of a 128x96 stream with frequent saccades: the weight sums and keys after long
+    histories stay bit-identical (no drift between the binary32 sequences)."""
+    spec = synth.StreamSpec(128, 96, 4, 600, 10.0, 25.0, 2.0, 15, 6.0, stream_id=9)
+    res, orc, _ = _run_pair(dev, spec, 600, bias=bias, every=150)
+    takes, changed, updates = res.stats()
+    assert updates == 600 * spec.pixels and takes > 0
