@@ -385,6 +385,20 @@ int fwrs_push_frame_foveated(fwrs_ctx* ctx, fwrs_foveator* fov, const float* ful
 /* Waits for the foveator's stream, then frees it.  NULL is accepted. */
 int fwrs_foveator_destroy(fwrs_foveator* fov);
 
+/* ---- the constants the kernels use (host only, no device work) ----------- */
+/* The per-context constants derived from `params` for an image `width` pixels
+ * wide, exactly as a context passes them to the kernels (Sec. 4.1, Eq. 3-4):
+ * out[0..8] = a_k, 1 - a_k, 1 / r_2,k, 1 / r_m, log2(e) / r_e,k, degrees per
+ * pixel (fov_deg / width as 1 / (width / fov_deg)), r_f in degrees, the
+ * unnormalised density at r_f, and exp(-lambda_decay).  FWRS_E_ARG for
+ * width <= 0, out NULL or invalid params. */
+int fwrs_method_constants(int width, const fwrs_params* params, float* out);
+
+/* The foveation generator's normalised Gaussian weights for `sigma` pixels:
+ * writes 2R + 1 weights (offsets -R..R, R = ceil(3 sigma)) to `out` and returns
+ * R; -1 if out is NULL, sigma is not finite and > 0, or R would exceed 32. */
+int fwrs_gauss_weights(float sigma, float* out);
+
 #ifdef __cplusplus
 }
 #endif

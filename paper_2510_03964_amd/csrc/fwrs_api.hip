@@ -929,4 +929,19 @@ int fwrs_foveator_destroy(fwrs_foveator* f)
     return rc;
 }
 
+int fwrs_method_constants(int width, const fwrs_params* params, float* out)
+{
+    if (width <= 0 || !out || !params_ok(params)) return FWRS_E_ARG;
+    const fwrs::Consts c = derive(*params, width);
+    const float v[9] = {c.A, c.B, c.IR2, c.IRM, c.C, c.iPPD, c.rf, c.Drf, c.decay};
+    for (int i = 0; i < 9; ++i) out[i] = v[i];
+    return FWRS_OK;
+}
+
+int fwrs_gauss_weights(float sigma, float* out)
+{
+    if (!out || !std::isfinite(sigma) || sigma <= 0.0f || 3.0f * sigma > (float)fwrs::kMaxBlurRadius) return -1;
+    return gauss_weights(sigma, out);
+}
+
 }  // extern "C"

@@ -30,7 +30,7 @@ EXPORTS = (
     "fwrs_frame_index", "fwrs_get_state", "fwrs_download_state", "fwrs_get_stats",
     "fwrs_set_tile", "fwrs_sync", "fwrs_strerror", "fwrs_engine_create", "fwrs_engine_tick",
     "fwrs_engine_set_tile", "fwrs_engine_destroy", "fwrs_foveator_create", "fwrs_foveate",
-    "fwrs_push_frame_foveated", "fwrs_foveator_destroy",
+    "fwrs_push_frame_foveated", "fwrs_foveator_destroy", "fwrs_method_constants", "fwrs_gauss_weights",
 )
 
 
@@ -133,6 +133,8 @@ def load(path: str | None = None):
         "fwrs_foveate": (i, [vp, vp, f, f, vp, vp]),
         "fwrs_push_frame_foveated": (i, [vp, vp, vp, f, f, vp]),
         "fwrs_foveator_destroy": (i, [vp]),
+        "fwrs_method_constants": (i, [i, C.POINTER(Params), C.POINTER(f)]),
+        "fwrs_gauss_weights": (i, [f, C.POINTER(f)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -168,6 +170,23 @@ def state_bytes(width: int, height: int, k: int, params: Params | None = None) -
     if params is None:
         return int(load().fwrs_state_bytes(int(width), int(height), int(k)))
     return int(load().fwrs_state_bytes_params(int(width), int(height), int(k), C.byref(params)))
+
+
+def method_constants(width: int, params: Params | None = None) -> np.ndarray:
+    """The constants a context passes to the kernels (fwrs_method_constants), float32[9]."""
+    p = params if params is not None else default_params(width)
+    out = (C.c_float * 9)()
+    _check(load().fwrs_method_constants(int(width), C.byref(p), out), "fwrs_method_constants")
+    return np.array(out[:], dtype=np.float32)
+
+
+def gauss_weights(sigma: float) -> np.ndarray:
+    """The foveation generator's normalised Gaussian weights (fwrs_gauss_weights), float32[2R + 1]."""
+    out = (C.c_float * 65)()
+    R = int(load().fwrs_gauss_weights(float(sigma), out))
+    if R < 0:
+        raise ValueError(f"no Gaussian weights for sigma {sigma}")
+    return np.array(out[:2 * R + 1], dtype=np.float32)
 
 
 def state_host_bytes(width: int, height: int, k: int) -> int:

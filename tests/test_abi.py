@@ -128,3 +128,27 @@ def test_invalid_arguments_are_rejected_before_any_gpu_work():
     assert L.fwrs_foveator_destroy(None) == fwrs.OK
     assert fwrs.strerror(fwrs.E_ARG) == "invalid argument"
     assert fwrs.strerror(99) == "unknown status"
+
+
+@pytest.mark.parametrize("width,rf,lam", [(256, 32.0, 0.0231), (3840, 216.0, 0.0231), (2064, 103.0, 0.5), (37, 2.0, 0.0)])
+def test_kernel_constants_are_the_oracles(width, rf, lam):
+    """The constants the library derives on the host for its kernels equal the oracle's, bit for bit."""
+    import numpy as np
+    import oracle
+
+    p = fwrs.default_params(width, fovea_radius_px=rf, lambda_decay=lam)
+    got = fwrs.method_constants(width, p)
+    o = oracle.Oracle(width, 4, 1, oracle.default_params(width, fovea_radius_px=rf, lambda_decay=lam))
+    c = o.constants()
+    want = np.array([c["A"], c["B"], c["IR2"], c["IRM"], c["C"], c["iPPD"], c["rf"], c["Drf"], o.decay], np.float32)
+    np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("sigma", [1.0, 2.0, 0.7, 5.0])
+def test_gaussian_weights_are_the_oracles(sigma):
+    import numpy as np
+    import oracle
+
+    np.testing.assert_array_equal(fwrs.gauss_weights(sigma).view(np.uint32), oracle.gauss_weights(sigma).view(np.uint32))
+    assert fwrs.load().fwrs_gauss_weights(float("nan"), (C.c_float * 65)()) == -1
+    assert fwrs.load().fwrs_gauss_weights(20.0, (C.c_float * 65)()) == -1
