@@ -66,3 +66,29 @@ def test_small_budget_queues_sessions_on_the_gpu(dev):
     st = serve.Scheduler(ex, budget_bytes=2 * one, max_active=8).run(sessions)
     assert st.max_active <= 2 and st.max_queue >= 1
     assert st.admitted + st.rejected == len(sessions)
+
+
+def test_full_size_sessions_alone_equal_in_the_mix(dev):
+    """Sessions of the serving workload's sizes (1080p and 4K, k in {4, 8}) through batched ticks:
+    each one's output equals the same session run alone with plain launches."""
+    sizes = ((1920, 1080), (3840, 2160))
+    sessions = serve.poisson_sessions(n=4, rate_per_s=40.0, seed=21, lifetime_s=(0.04, 0.08), sizes=sizes,
+                                      ks=(4, 8), fps=(90.0, 120.0))
+    rings = _rings(dev, sizes, n=4)
+    stream = torch.cuda.current_stream()
+    ex = serve.BatchedExecutor(rings, max_frames=8, stream=stream)
+    sched = serve.Scheduler(ex, budget_bytes=64 * 10**9, max_active=8)
+    st = sched.run(sessions)
+    assert st.frames > 0 and st.admitted == len(sessions)
+    for s in sessions:
+        n = sched.frames_done.get(s.sid, 0)
+        assert n > 0
+        p = fwrs.default_params(s.width, seed=synth.PHILOX_SEED, stream_id=s.sid)
+        alone = fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream)
+        out = torch.empty((s.height, s.width, 3), device=dev)
+        ring = rings[(s.width, s.height)]
+        for i in range(n):
+            alone.step(*ring[(i + 7 * s.sid) % len(ring)], out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ex.outputs[s.sid]), f"session {s.sid} differs after {n} frames"
+        alone.close()
