@@ -300,6 +300,22 @@ __device__ __forceinline__ float cube_root(float t)
     return y - c;
 }
 
+// x / c for a constant divisor c given rc = RN(1 / c): the product x rc corrected
+// by one fused multiply-add of its residual (Markstein's method).  For each of the
+// divisors below (0.95047, 1.08883, 100) this equals the correctly rounded x / c for
+// every binary32 x with 2^-100 <= |x| <= 2^126 (checked exhaustively); other x
+// take the division, so the result is always the correctly rounded quotient.
+__device__ __forceinline__ float div_const(float x, float c, float rc)
+{
+    const float ax = fabsf(x);
+    if (ax >= 0x1p-100f && ax <= 0x1p126f) {
+        const float q = x * rc;
+        const float r = fmaf(-q, c, x);
+        return fmaf(r, rc, q);
+    }
+    return x / c;
+}
+
 __device__ __forceinline__ float lab_curve(float t)
 {
     // t^(1/3) above (6/29)^3, the linear segment t / (3 (6/29)^2) + 4/29 below
@@ -312,9 +328,9 @@ __device__ __forceinline__ float3 rgb_to_lab(float r, float g, float b)
     const float X = (0.4124564f * r + 0.3575761f * g) + 0.1804375f * b;
     const float Y = (0.2126729f * r + 0.7151522f * g) + 0.0721750f * b;
     const float Z = (0.0193339f * r + 0.1191920f * g) + 0.9503041f * b;
-    const float fx = lab_curve(X / 0.95047f);
+    const float fx = lab_curve(div_const(X, 0.95047f, 0x1.0d5728p+0f));   // X / X_n
     const float fy = lab_curve(Y);
-    const float fz = lab_curve(Z / 1.08883f);
+    const float fz = lab_curve(div_const(Z, 1.08883f, 0x1.d63ac2p-1f));   // Z / Z_n
     return make_float3(116.0f * fy - 16.0f, 500.0f * (fx - fy), 200.0f * (fy - fz));
 }
 

@@ -348,7 +348,7 @@ __device__ __forceinline__ uint32_t pixel_per_slot(const FrameDesc& d, uint32_t 
             s = take ? kn : W1;
         } else {
             // Eq. 7 against this slot's sample, then the slot's Alg. 2 decision
-            const float dl = fminf(1.0f, cie94(rgb_to_lab(v.y, v.z, v.w), lab_new) / 100.0f);
+            const float dl = fminf(1.0f, div_const(cie94(rgb_to_lab(v.y, v.z, v.w), lab_new), 100.0f, 0x1.47ae14p-7f));
             const float W1b = bias_eq7(W1, w, dl);
             s = W1b + w;
             take = unit_variate(word) * s > W1b;
@@ -586,7 +586,7 @@ __device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_
             st<kNtWsumSt>(d.wsum + (size_t)p * (size_t)kk + j, take ? kn : Wj);
         } else {
             if (PER_SLOT) {
-                const float dl = fminf(1.0f, cie94(rgb_to_lab(v.y, v.z, v.w), lab_new) / 100.0f);
+                const float dl = fminf(1.0f, div_const(cie94(rgb_to_lab(v.y, v.z, v.w), lab_new), 100.0f, 0x1.47ae14p-7f));
                 W1j = bias_eq7(Wj, w, dl);
                 sj = W1j + w;
                 st<kNtWsumSt>(d.wsum + (size_t)p * (size_t)kk + j, sj);
