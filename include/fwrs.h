@@ -355,7 +355,7 @@ int fwrs_engine_destroy(fwrs_engine* eng);
  *                   normalised, clamp to edge) at the pixel.
  * Every operation is binary32 in a fixed order, so results are reproducible
  * bit for bit.  The foveator owns the level images (mip: N/4 + N/16 texels;
- * Gaussian: 3N), reused by every call: calls on one foveator must be ordered
+ * Gaussian: N), reused by every call: calls on one foveator must be ordered
  * on one stream. */
 #define FWRS_FOV_MIP 0u
 #define FWRS_FOV_GAUSS 1u

@@ -778,7 +778,6 @@ struct fwrs_foveator {
     float* buf = nullptr;                  // one allocation for the level images
     float* l1 = nullptr;
     float* l2 = nullptr;
-    float* tmp = nullptr;                  // Gaussian only: the horizontal pass
     uint32_t w1 = 0, h1 = 0, w2 = 0, h2 = 0;
     int radius[2] = {0, 0};
     float wt[2][2 * fwrs::kMaxBlurRadius + 1] = {};
@@ -802,7 +801,8 @@ int gauss_weights(float sigma, float* w)
     return R;
 }
 
-fwrs::FovSrc build_levels(fwrs_foveator* f, const float* full, hipStream_t stream, hipError_t& err)
+fwrs::FovSrc build_levels(fwrs_foveator* f, const float* full, float gaze_x, float gaze_y, hipStream_t stream,
+                          hipError_t& err)
 {
     fwrs::FovSrc s{};
     s.full = full;
@@ -818,11 +818,8 @@ fwrs::FovSrc build_levels(fwrs_foveator* f, const float* full, hipStream_t strea
     if (f->mode == FWRS_FOV_MIP) {
         err = fwrs::launch_mips(full, f->l1, f->l2, (uint32_t)f->width, (uint32_t)f->height, stream);
     } else {
-        err = fwrs::launch_blur(full, f->tmp, f->l1, (uint32_t)f->width, (uint32_t)f->height, f->radius[0],
-                                f->wt[0], stream);
-        if (err == hipSuccess)
-            err = fwrs::launch_blur(full, f->tmp, f->l2, (uint32_t)f->width, (uint32_t)f->height, f->radius[1],
-                                    f->wt[1], stream);
+        err = fwrs::launch_gauss_levels(full, f->l1, (uint32_t)f->width, (uint32_t)f->height, gaze_x, gaze_y, s.r0sq,
+                                        s.r1sq, f->wt[0], f->wt[1], stream);
     }
     return s;
 }
@@ -856,23 +853,27 @@ int fwrs_foveator_create(int width, int height, float fovea_radius_px, float rin
     const size_t n = (size_t)width * (size_t)height * 3;
     // level images at 256-byte boundaries
     auto up = [](size_t v) { return (v + 63) / 64 * 64; };
-    size_t s1, s2, st = 0;
+    size_t s1, s2;
     if (mode == FWRS_FOV_MIP) {
         s1 = up((size_t)f->w1 * f->h1 * 3);
         s2 = up((size_t)f->w2 * f->h2 * 3);
     } else {
-        s1 = s2 = st = up(n);
+        s1 = up(n);                        // one plane: each pixel at its own level
+        s2 = 0;
         f->radius[0] = gauss_weights(1.0f, f->wt[0]);
         f->radius[1] = gauss_weights(2.0f, f->wt[1]);
+        if (f->radius[0] != fwrs::kGaussR1 || f->radius[1] != fwrs::kGaussR2) {
+            delete f;
+            return FWRS_E_ARG;
+        }
     }
-    if (hipMalloc(&f->buf, 4 * (s1 + s2 + st)) != hipSuccess) {
+    if (hipMalloc(&f->buf, 4 * (s1 + s2)) != hipSuccess) {
         (void)hipGetLastError();
         delete f;
         return FWRS_E_NOMEM;
     }
     f->l1 = f->buf;
-    f->l2 = f->buf + s1;
-    f->tmp = st ? f->buf + s1 + s2 : nullptr;
+    f->l2 = s2 ? f->buf + s1 : nullptr;
     *out = f;
     return FWRS_OK;
 }
@@ -883,7 +884,7 @@ int fwrs_foveate(fwrs_foveator* f, const float* full, float gaze_x, float gaze_y
     DeviceGuard g(f->device);
     if (!g.ok) return FWRS_E_HIP;
     hipError_t err = hipSuccess;
-    const fwrs::FovSrc s = build_levels(f, full, f->stream, err);
+    const fwrs::FovSrc s = build_levels(f, full, gaze_x, gaze_y, f->stream, err);
     if (err != hipSuccess) return FWRS_E_HIP;
     if (fwrs::launch_foveate(s, color, level_map, (uint32_t)f->width, (uint32_t)f->height, gaze_x, gaze_y,
                              f->stream) != hipSuccess)
@@ -900,7 +901,7 @@ int fwrs_push_frame_foveated(fwrs_ctx* x, fwrs_foveator* f, const float* full, f
     if (!g.ok) return FWRS_E_HIP;
     hipError_t err = hipSuccess;
     fwrs::FovDesc fd{};
-    fd.s = build_levels(f, full, x->stream, err);
+    fd.s = build_levels(f, full, gaze_x, gaze_y, x->stream, err);
     if (err != hipSuccess) return FWRS_E_HIP;
     fd.f = make_desc(x, nullptr, nullptr, gaze_x, gaze_y, out, x->tile_x, x->tile_y);
     if (fwrs::launch_foveated(fd, out != nullptr, x->stream) != hipSuccess) return FWRS_E_HIP;

@@ -61,15 +61,16 @@ struct alignas(8) ReprojDesc {
     float tol;                  // relative depth tolerance
 };
 
-// Foveation generator sources (Sec. 4.3): the full frame and the two reduced
-// levels -- mip 1 and mip 2 (bilinear sampling) or the frame blurred with
-// sigma 1 and 2 px (sampled at the pixel) -- and the rings that pick a level.
+// Foveation generator sources (Sec. 4.3): the full frame and the reduced
+// levels -- mip 1 and mip 2 (bilinear sampling), or one plane holding at every
+// pixel of level l >= 1 the frame blurred with sigma 2^(l-1) px (sampled at the
+// pixel; level-0 pixels are not written) -- and the rings that pick a level.
 constexpr uint32_t kFovMip = 0u;
 constexpr uint32_t kFovGauss = 1u;
 struct FovSrc {
     const float* full;          // [H][W][3]
-    const float* l1;            // mip 1 [h1][w1][3], or the sigma-1 blur [H][W][3]
-    const float* l2;            // mip 2 [h2][w2][3], or the sigma-2 blur [H][W][3]
+    const float* l1;            // mip 1 [h1][w1][3], or the Gaussian plane [H][W][3]
+    const float* l2;            // mip 2 [h2][w2][3] (Gaussian: unused)
     uint32_t w1, h1, w2, h2;
     float r0sq, r1sq;           // squared ring radii (level 0 within r0, 1 within r1)
     uint32_t mode;              // kFovMip / kFovGauss
@@ -228,12 +229,17 @@ __device__ __forceinline__ float log2_unit(uint32_t bits)
 // ---------------------------------------------------------------------------
 // Foveation: the level ring of a pixel and its degraded colour.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t fov_level(const FovSrc& s, float gx, float gy, uint32_t x, uint32_t y)
+__device__ __forceinline__ uint32_t ring_level(float r0sq, float r1sq, float gx, float gy, uint32_t x, uint32_t y)
 {
     const float dx = ((float)x + 0.5f) - gx;
     const float dy = ((float)y + 0.5f) - gy;
     const float d2 = dx * dx + dy * dy;
-    return d2 <= s.r0sq ? 0u : (d2 <= s.r1sq ? 1u : 2u);
+    return d2 <= r0sq ? 0u : (d2 <= r1sq ? 1u : 2u);
+}
+
+__device__ __forceinline__ uint32_t fov_level(const FovSrc& s, float gx, float gy, uint32_t x, uint32_t y)
+{
+    return ring_level(s.r0sq, s.r1sq, gx, gy, x, y);
 }
 
 // Bilinear sample of a w x h level (1/scale of full resolution) at the centre
@@ -265,7 +271,7 @@ __device__ __forceinline__ float3 bilinear(const float* lv, uint32_t w, uint32_t
 
 __device__ __forceinline__ float3 fov_colour(const FovSrc& s, uint32_t x, uint32_t y, uint32_t p, uint32_t level)
 {
-    const float* src = level == 0u ? s.full : (level == 1u ? s.l1 : s.l2);
+    const float* src = level == 0u ? s.full : s.l1;
     if (level == 0u || s.mode == kFovGauss) {
         const float* c = src + 3 * (size_t)p;
         return make_float3(c[0], c[1], c[2]);

@@ -11,6 +11,8 @@ namespace fwrs {
 
 constexpr int kMaxK = 16;
 constexpr int kMaxBlurRadius = 32;
+constexpr int kGaussR1 = 3;             // ceil(3 sigma) of the Gaussian levels, sigma = 1 and 2
+constexpr int kGaussR2 = 6;
 
 // op: 1 = update only, 2 = resolve only, 3 = update + resolve,
 // 5 = update + resolve of the changed pixels only.
@@ -31,12 +33,13 @@ hipError_t launch_tick(const TickArgs& a, hipStream_t stream);
 // Reprojected frame: gather from the previous bank, dense write to this one.
 hipError_t launch_reproject(const ReprojDesc& r, hipStream_t stream);
 
-// Foveation generator: mip 1 and 2 of a frame; a separable Gaussian blur
-// (src -> tmp -> dst, weights[2 radius + 1]); the degraded frame + level map;
-// the reservoir pass fed by the generator (no intermediate frame).
+// Foveation generator: mip 1 and 2 of a frame; the Gaussian plane of a frame
+// for a gaze (each pixel blurred at its own level's radius; weights
+// g1[2 kGaussR1 + 1], g2[2 kGaussR2 + 1]); the degraded frame + level map; the
+// reservoir pass fed by the generator (no intermediate frame).
 hipError_t launch_mips(const float* full, float* m1, float* m2, uint32_t w, uint32_t h, hipStream_t stream);
-hipError_t launch_blur(const float* src, float* tmp, float* dst, uint32_t w, uint32_t h, int radius,
-                       const float* weights, hipStream_t stream);
+hipError_t launch_gauss_levels(const float* full, float* dst, uint32_t w, uint32_t h, float gx, float gy, float r0sq,
+                               float r1sq, const float* g1, const float* g2, hipStream_t stream);
 hipError_t launch_foveate(const FovSrc& s, float* color, uint8_t* level, uint32_t w, uint32_t h, float gx, float gy,
                           hipStream_t stream);
 hipError_t launch_foveated(const FovDesc& fd, bool resolve, hipStream_t stream);

@@ -643,8 +643,8 @@ __global__ __launch_bounds__(kBlock) void reproject_kernel(ReprojDesc r)
 // Foveation generator (Sec. 4.3).  mip_kernel: one thread per mip-2 texel
 // builds its (up to) 2x2 mip-1 texels from the full frame and then itself, each
 // texel the mean of the children that exist, summed in row-major order.
-// blur kernels: separable Gaussian, clamp to edge, accumulation in offset
-// order.  foveate_kernel: the degraded frame and level map on their own;
+// gauss_levels_kernel: the separable Gaussian levels, clamp to edge,
+// accumulation in offset order.  foveate_kernel: the degraded frame and level map on their own;
 // foveated_kernel: the same sampling fused into the reservoir pass.
 // ---------------------------------------------------------------------------
 struct MipArgs {
@@ -724,38 +724,162 @@ __global__ __launch_bounds__(kBlock) void mip_kernel(MipArgs a)
     o[2] = s2 * r;
 }
 
-struct BlurArgs {
+// Gaussian levels from one read of the frame, into one plane: every pixel of
+// level l >= 1 gets the frame blurred with sigma 2^(l-1) (radius kGaussR1 or
+// kGaussR2) at that pixel; level-0 pixels are not written.  A block owns kBlock
+// columns (one per thread) and a strip of ROWS output rows.  It walks the
+// strip's rows and a halo of kGaussR2 rows above and below (row indices clamped
+// to the image): each row segment, columns x0 - kGaussR2 .. x0 + kBlock - 1 +
+// kGaussR2 (clamped), is staged in LDS as three channel planes; every thread
+// takes the horizontal sums of the radii the block needs at its column and
+// keeps the last rows' sums in registers; an output row's vertical sum is taken
+// once its last tap row is in.  The loads of the next rows are in flight while
+// the current row is summed.  Sums start at zero and add the taps in offset order,
+// the order of two separate passes (horizontal, then vertical).  Which levels
+// a block needs comes from its rectangle's distances to the gaze, widened by
+// 2^-10 relative so that rounding can only make it need more.
+struct GaussArgs {
     const float* src;
     float* dst;
     uint32_t w, h;
-    int radius;
-    float wt[2 * kMaxBlurRadius + 1];
+    float gx, gy, r0sq, r1sq;
+    float g1[2 * kGaussR1 + 1];
+    float g2[2 * kGaussR2 + 1];
 };
 
-// RADIUS > 0: compile-time radius (every tap's load issued up front); 0: a.radius.
-template <bool VERTICAL, int RADIUS>
-__global__ __launch_bounds__(kBlock) void blur_kernel(BlurArgs a)
+template <int ROWS>
+__global__ __launch_bounds__(kBlock) void gauss_levels_kernel(GaussArgs a)
 {
-    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= a.w * a.h) return;
-    const int x = (int)(p % a.w), y = (int)(p / a.w);
-    const int rad = RADIUS ? RADIUS : a.radius;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-#pragma unroll
-    for (int d = -rad; d <= rad; ++d) {
-        int xx = x, yy = y;
-        if (VERTICAL) yy = min(max(y + d, 0), (int)a.h - 1);
-        else xx = min(max(x + d, 0), (int)a.w - 1);
-        const float* c = a.src + ((size_t)yy * a.w + (uint32_t)xx) * 3;
-        const float g = a.wt[d + rad];
-        s0 = s0 + g * c[0];
-        s1 = s1 + g * c[1];
-        s2 = s2 + g * c[2];
+    constexpr int R1 = kGaussR1, R2 = kGaussR2;
+    constexpr int PF = 2;                              // rows in flight
+    constexpr int SEG = kBlock + 2 * R2;               // pixels of a staged row segment
+    constexpr int NF = 3 * SEG;                        // floats of it
+    constexpr int PER = (NF + kBlock - 1) / kBlock;    // floats staged per thread
+    constexpr int NV = ROWS + 2 * R2;                  // rows walked (halo included)
+    static_assert(R1 <= R2, "the sigma-1 taps are a subset of the sigma-2 taps");
+    static_assert(NV % PF == 0 && PF % 2 == 0, "whole, even prefetch groups");
+    __shared__ float seg[2][3 * SEG];
+
+    const int tid = (int)threadIdx.x;
+    const int W = (int)a.w, H = (int)a.h;
+    const int x0 = (int)blockIdx.x * kBlock, y0 = (int)blockIdx.y * ROWS;
+    const int x = x0 + tid;
+
+    // Levels present in the block's pixels (block-uniform, conservative).
+    bool need1, need2;
+    {
+        const float xa = (float)x0 + 0.5f, xb = (float)min(x0 + kBlock, W) - 0.5f;
+        const float ya = (float)y0 + 0.5f, yb = (float)min(y0 + ROWS, H) - 0.5f;
+        const float nx = fminf(fmaxf(a.gx, xa), xb) - a.gx, ny = fminf(fmaxf(a.gy, ya), yb) - a.gy;
+        const float fx = fmaxf(fabsf(xa - a.gx), fabsf(xb - a.gx)), fy = fmaxf(fabsf(ya - a.gy), fabsf(yb - a.gy));
+        const float dmin = nx * nx + ny * ny, dmax = fx * fx + fy * fy;
+        need1 = dmin * (1.0f - 0x1p-10f) <= a.r1sq && dmax * (1.0f + 0x1p-10f) > a.r0sq;
+        need2 = dmax * (1.0f + 0x1p-10f) > a.r1sq;
     }
-    float* o = a.dst + (size_t)p * 3;
-    o[0] = s0;
-    o[1] = s1;
-    o[2] = s2;
+    if (!need1 && !need2) return;                      // every pixel at level 0
+
+    // This thread stages floats f = tid + q kBlock of a segment: channel f % 3
+    // of segment pixel f / 3 (image column x0 - R2 + f / 3, clamped).
+    int goff[PER], loff[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int f = tid + q * kBlock;
+        const int e = f / 3, ch = f - 3 * e;
+        const int xx = min(max(x0 - R2 + e, 0), W - 1);
+        goff[q] = xx * 3 + ch;
+        loff[q] = f < NF ? ch * SEG + e : -1;
+    }
+    // Walked row v is loaded into stage[v % PF] PF rows ahead: rows v + 1 ..
+    // v + PF are in flight while row v is summed (the loop is unrolled by PF,
+    // so every index is a constant and the ring stays in registers).
+    float stage[PF][PER];
+    auto fetch = [&](int v, float* dst) {
+        const int yy = min(max(y0 - R2 + v, 0), H - 1);
+        const float* row = a.src + (size_t)yy * (size_t)W * 3;
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (loff[q] >= 0) dst[q] = row[goff[q]];
+    };
+
+    float3 h2[2 * R2 + 1];     // sigma-2 horizontal sums of walked rows v - 2 R2 .. v (oldest first)
+    float3 h1[2 * R1 + 1];     // sigma-1 horizontal sums of walked rows v - 2 R1 .. v
+#pragma unroll
+    for (int u = 0; u < PF; ++u) fetch(u, stage[u]);
+    for (int vb = 0; vb < NV; vb += PF) {
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const int v = vb + u;
+        float* s = seg[u & 1];                         // PF is even: u & 1 == v & 1
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (loff[q] >= 0) s[loff[q]] = stage[u][q];
+        __syncthreads();
+        if (v + PF < NV) fetch(v + PF, stage[u]);
+
+        const float* c = s + tid;                      // c[ch SEG + i]: channel ch, column x - R2 + i
+        if (need2) {
+#pragma unroll
+            for (int i = 0; i < 2 * R2; ++i) h2[i] = h2[i + 1];
+            float t[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.f;
+#pragma unroll
+                for (int i = 0; i <= 2 * R2; ++i) acc = acc + a.g2[i] * c[ch * SEG + i];
+                t[ch] = acc;
+            }
+            h2[2 * R2] = make_float3(t[0], t[1], t[2]);
+        }
+        if (need1) {
+#pragma unroll
+            for (int i = 0; i < 2 * R1; ++i) h1[i] = h1[i + 1];
+            float t[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.f;
+#pragma unroll
+                for (int i = 0; i <= 2 * R1; ++i) acc = acc + a.g1[i] * c[ch * SEG + R2 - R1 + i];
+                t[ch] = acc;
+            }
+            h1[2 * R1] = make_float3(t[0], t[1], t[2]);
+        }
+
+        // Walked row j is image row y0 - R2 + j (clamped); its radius-r sums
+        // are complete once walked row j + r is in, i.e. at v = j + r.
+        const int y1 = y0 + v - R1 - R2;
+        if (need1 && v >= R1 + R2 && v < R1 + R2 + ROWS && y1 < H && x < W &&
+            ring_level(a.r0sq, a.r1sq, a.gx, a.gy, (uint32_t)x, (uint32_t)y1) == 1u) {
+            float3 o = make_float3(0.f, 0.f, 0.f);
+#pragma unroll
+            for (int i = 0; i <= 2 * R1; ++i) {
+                const float g = a.g1[i];
+                o.x = o.x + g * h1[i].x;
+                o.y = o.y + g * h1[i].y;
+                o.z = o.z + g * h1[i].z;
+            }
+            float* d = a.dst + ((size_t)y1 * (size_t)W + (size_t)x) * 3;
+            d[0] = o.x;
+            d[1] = o.y;
+            d[2] = o.z;
+        }
+        const int y2 = y0 + v - 2 * R2;
+        if (need2 && v >= 2 * R2 && y2 < H && x < W &&
+            ring_level(a.r0sq, a.r1sq, a.gx, a.gy, (uint32_t)x, (uint32_t)y2) == 2u) {
+            float3 o = make_float3(0.f, 0.f, 0.f);
+#pragma unroll
+            for (int i = 0; i <= 2 * R2; ++i) {
+                const float g = a.g2[i];
+                o.x = o.x + g * h2[i].x;
+                o.y = o.y + g * h2[i].y;
+                o.z = o.z + g * h2[i].z;
+            }
+            float* d = a.dst + ((size_t)y2 * (size_t)W + (size_t)x) * 3;
+            d[0] = o.x;
+            d[1] = o.y;
+            d[2] = o.z;
+        }
+      }
+    }
 }
 
 struct FoveateArgs {
@@ -869,30 +993,27 @@ hipError_t launch_mips(const float* full, float* m1, float* m2, uint32_t w, uint
     return hipGetLastError();
 }
 
-hipError_t launch_blur(const float* src, float* tmp, float* dst, uint32_t w, uint32_t h, int radius,
-                       const float* weights, hipStream_t stream)
+hipError_t launch_gauss_levels(const float* full, float* dst, uint32_t w, uint32_t h, float gx, float gy, float r0sq,
+                               float r1sq, const float* g1, const float* g2, hipStream_t stream)
 {
-    if (radius < 0 || radius > kMaxBlurRadius) return hipErrorInvalidValue;
-    BlurArgs a{};
+    GaussArgs a{};
+    a.src = full;
+    a.dst = dst;
     a.w = w;
     a.h = h;
-    a.radius = radius;
-    for (int i = 0; i <= 2 * radius; ++i) a.wt[i] = weights[i];
-    const uint32_t n = w * h;
-    const dim3 grid((n + kBlock - 1) / kBlock), block(kBlock);
-#define FWRS_BLUR_PASS(V)                                                                            \
-    do {                                                                                             \
-        if (radius == 3) hipLaunchKernelGGL((blur_kernel<V, 3>), grid, block, 0, stream, a);          \
-        else if (radius == 6) hipLaunchKernelGGL((blur_kernel<V, 6>), grid, block, 0, stream, a);     \
-        else hipLaunchKernelGGL((blur_kernel<V, 0>), grid, block, 0, stream, a);                      \
-    } while (0)
-    a.src = src;
-    a.dst = tmp;
-    FWRS_BLUR_PASS(false);
-    a.src = tmp;
-    a.dst = dst;
-    FWRS_BLUR_PASS(true);
-#undef FWRS_BLUR_PASS
+    a.gx = gx;
+    a.gy = gy;
+    a.r0sq = r0sq;
+    a.r1sq = r1sq;
+    for (int i = 0; i <= 2 * kGaussR1; ++i) a.g1[i] = g1[i];
+    for (int i = 0; i <= 2 * kGaussR2; ++i) a.g2[i] = g2[i];
+    const uint32_t cols = (w + kBlock - 1) / kBlock;
+    // 32-row strips (halo rows re-read: 12 of 44) while they still give a few
+    // blocks per compute unit, else 16-row strips.
+    if ((uint64_t)cols * ((h + 31) / 32) >= 512u)
+        hipLaunchKernelGGL(gauss_levels_kernel<32>, dim3(cols, (h + 31) / 32), dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL(gauss_levels_kernel<16>, dim3(cols, (h + 15) / 16), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

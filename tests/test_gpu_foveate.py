@@ -48,6 +48,29 @@ def test_foveate_matches_oracle(dev, mode, w, h):
     fov.close()
 
 
+@pytest.mark.parametrize("mode", [fwrs.FOV_MIP, fwrs.FOV_GAUSS])
+@pytest.mark.parametrize("w,h,gx,gy,r0,r1", [
+    (300, 70, 150.5, 35.5, 0.0, 0.0),        # rings of radius 0: level 2 everywhere but the gaze pixel
+    (513, 40, 260.0, 20.0, 1e6, 1e6),        # fovea covers the frame: nothing degraded
+    (513, 40, -1e30, 20.0, 5.0, 50.0),       # gaze far outside (squared distances overflow to inf)
+    (600, 90, 299.5, 44.5, 40.0, 40.0),      # empty middle ring
+    (600, 90, 0.0, 0.0, 0.0, 1e5),           # middle ring covers the frame
+    (700, 300, 350.0, 150.0, 60.0, 200.0),   # all three levels, several blocks of each
+])
+def test_foveate_ring_edge_cases(dev, mode, w, h, gx, gy, r0, r1):
+    """Level maps whose blocks hold one, two or three levels, or none but level 0."""
+    full = torch.rand((h, w, 3), generator=torch.Generator().manual_seed(w + h), dtype=torch.float32).to(dev)
+    fov = fwrs.Foveator(w, h, r0, r1, mode, stream=torch.cuda.current_stream())
+    col = torch.empty((h, w, 3), device=dev)
+    lev = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    fov.foveate(full, gx, gy, col, lev)
+    oc, ol = oracle.foveate(full.cpu().numpy(), gx, gy, r0, r1, mode)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(lev.cpu().numpy(), ol)
+    np.testing.assert_array_equal(col.cpu().numpy().view(np.uint32), oc.view(np.uint32))
+    fov.close()
+
+
 def _fused_vs_oracle(dev, spec, n, bias, mode, resolve=True):
     p = fwrs.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED,
                             stream_id=spec.stream_id, bias_mode=bias)
