@@ -13,6 +13,7 @@ constexpr int kMaxK = 16;
 constexpr int kMaxBlurRadius = 32;
 constexpr int kGaussR1 = 3;             // ceil(3 sigma) of the Gaussian levels, sigma = 1 and 2
 constexpr int kGaussR2 = 6;
+constexpr int kGaussCols = 64;          // columns (threads) per block of the Gaussian level kernel
 
 // op: 1 = update only, 2 = resolve only, 3 = update + resolve,
 // 5 = update + resolve of the changed pixels only.

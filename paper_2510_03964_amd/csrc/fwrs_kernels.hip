@@ -726,10 +726,10 @@ __global__ __launch_bounds__(kBlock) void mip_kernel(MipArgs a)
 
 // Gaussian levels from one read of the frame, into one plane: every pixel of
 // level l >= 1 gets the frame blurred with sigma 2^(l-1) (radius kGaussR1 or
-// kGaussR2) at that pixel; level-0 pixels are not written.  A block owns kBlock
+// kGaussR2) at that pixel; level-0 pixels are not written.  A block owns COLS
 // columns (one per thread) and a strip of ROWS output rows.  It walks the
 // strip's rows and a halo of kGaussR2 rows above and below (row indices clamped
-// to the image): each row segment, columns x0 - kGaussR2 .. x0 + kBlock - 1 +
+// to the image): each row segment, columns x0 - kGaussR2 .. x0 + COLS - 1 +
 // kGaussR2 (clamped), is staged in LDS as three channel planes; every thread
 // takes the horizontal sums of the radii the block needs at its column and
 // keeps the last rows' sums in registers; an output row's vertical sum is taken
@@ -747,14 +747,14 @@ struct GaussArgs {
     float g2[2 * kGaussR2 + 1];
 };
 
-template <int ROWS>
-__global__ __launch_bounds__(kBlock) void gauss_levels_kernel(GaussArgs a)
+template <int ROWS, int COLS>
+__global__ __launch_bounds__(COLS) void gauss_levels_kernel(GaussArgs a)
 {
     constexpr int R1 = kGaussR1, R2 = kGaussR2;
     constexpr int PF = 2;                              // rows in flight
-    constexpr int SEG = kBlock + 2 * R2;               // pixels of a staged row segment
+    constexpr int SEG = COLS + 2 * R2;                 // pixels of a staged row segment
     constexpr int NF = 3 * SEG;                        // floats of it
-    constexpr int PER = (NF + kBlock - 1) / kBlock;    // floats staged per thread
+    constexpr int PER = (NF + COLS - 1) / COLS;        // floats staged per thread
     constexpr int NV = ROWS + 2 * R2;                  // rows walked (halo included)
     static_assert(R1 <= R2, "the sigma-1 taps are a subset of the sigma-2 taps");
     static_assert(NV % PF == 0 && PF % 2 == 0, "whole, even prefetch groups");
@@ -762,13 +762,13 @@ __global__ __launch_bounds__(kBlock) void gauss_levels_kernel(GaussArgs a)
 
     const int tid = (int)threadIdx.x;
     const int W = (int)a.w, H = (int)a.h;
-    const int x0 = (int)blockIdx.x * kBlock, y0 = (int)blockIdx.y * ROWS;
+    const int x0 = (int)blockIdx.x * COLS, y0 = (int)blockIdx.y * ROWS;
     const int x = x0 + tid;
 
     // Levels present in the block's pixels (block-uniform, conservative).
     bool need1, need2;
     {
-        const float xa = (float)x0 + 0.5f, xb = (float)min(x0 + kBlock, W) - 0.5f;
+        const float xa = (float)x0 + 0.5f, xb = (float)min(x0 + COLS, W) - 0.5f;
         const float ya = (float)y0 + 0.5f, yb = (float)min(y0 + ROWS, H) - 0.5f;
         const float nx = fminf(fmaxf(a.gx, xa), xb) - a.gx, ny = fminf(fmaxf(a.gy, ya), yb) - a.gy;
         const float fx = fmaxf(fabsf(xa - a.gx), fabsf(xb - a.gx)), fy = fmaxf(fabsf(ya - a.gy), fabsf(yb - a.gy));
@@ -778,12 +778,12 @@ __global__ __launch_bounds__(kBlock) void gauss_levels_kernel(GaussArgs a)
     }
     if (!need1 && !need2) return;                      // every pixel at level 0
 
-    // This thread stages floats f = tid + q kBlock of a segment: channel f % 3
+    // This thread stages floats f = tid + q COLS of a segment: channel f % 3
     // of segment pixel f / 3 (image column x0 - R2 + f / 3, clamped).
     int goff[PER], loff[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int f = tid + q * kBlock;
+        const int f = tid + q * COLS;
         const int e = f / 3, ch = f - 3 * e;
         const int xx = min(max(x0 - R2 + e, 0), W - 1);
         goff[q] = xx * 3 + ch;
@@ -1007,13 +1007,22 @@ hipError_t launch_gauss_levels(const float* full, float* dst, uint32_t w, uint32
     a.r1sq = r1sq;
     for (int i = 0; i <= 2 * kGaussR1; ++i) a.g1[i] = g1[i];
     for (int i = 0; i <= 2 * kGaussR2; ++i) a.g2[i] = g2[i];
-    const uint32_t cols = (w + kBlock - 1) / kBlock;
-    // 32-row strips (halo rows re-read: 12 of 44) while they still give a few
-    // blocks per compute unit, else 16-row strips.
-    if ((uint64_t)cols * ((h + 31) / 32) >= 512u)
-        hipLaunchKernelGGL(gauss_levels_kernel<32>, dim3(cols, (h + 31) / 32), dim3(kBlock), 0, stream, a);
+    // One-wave blocks; the tallest strip (32, 16, 8 or 4 rows; the halo costs
+    // 12 walked rows per strip) whose grid still gives the compute units about
+    // 16 waves each, else 4 rows: with fewer waves the per-row barrier and load
+    // latency are not hidden.
+    constexpr int C = kGaussCols;
+    const uint64_t cols = (w + C - 1) / C;
+    auto waves = [&](uint32_t rows) { return cols * ((h + rows - 1) / rows); };
+    const dim3 block(C);
+    if (waves(32) >= 4000u)
+        hipLaunchKernelGGL((gauss_levels_kernel<32, C>), dim3(cols, (h + 31) / 32), block, 0, stream, a);
+    else if (waves(16) >= 4000u)
+        hipLaunchKernelGGL((gauss_levels_kernel<16, C>), dim3(cols, (h + 15) / 16), block, 0, stream, a);
+    else if (waves(8) >= 4000u)
+        hipLaunchKernelGGL((gauss_levels_kernel<8, C>), dim3(cols, (h + 7) / 8), block, 0, stream, a);
     else
-        hipLaunchKernelGGL(gauss_levels_kernel<16>, dim3(cols, (h + 15) / 16), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL((gauss_levels_kernel<4, C>), dim3(cols, (h + 3) / 4), block, 0, stream, a);
     return hipGetLastError();
 }
 

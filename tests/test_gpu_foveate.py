@@ -71,6 +71,26 @@ def test_foveate_ring_edge_cases(dev, mode, w, h, gx, gy, r0, r1):
     fov.close()
 
 
+@pytest.mark.parametrize("w,h", [(1280, 720), (1920, 1080), (2560, 1600), (3840, 2160)])
+def test_gaussian_strip_heights(w, h, dev):
+    """The Gaussian level kernel picks its strip height (4, 8, 16 or 32 rows) from the frame size; one frame
+    of each against the oracle, with the gaze near a corner so that strips hold every level."""
+    spec = synth.StreamSpec(w, h, 4, 1, 0.06 * w, 0.15 * w, 1.0, 2, 2.0, stream_id=3)
+    full = _full(spec, 0, dev)
+    gx, gy = 0.2 * w + 0.25, 0.3 * h + 0.75
+    fov = fwrs.Foveator(w, h, spec.fovea_radius_px, spec.ring_radius_px, fwrs.FOV_GAUSS,
+                        stream=torch.cuda.current_stream())
+    col = torch.empty((h, w, 3), device=dev)
+    lev = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    fov.foveate(full, gx, gy, col, lev)
+    oc, ol = oracle.foveate(full.cpu().numpy(), gx, gy, spec.fovea_radius_px, spec.ring_radius_px, fwrs.FOV_GAUSS)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(lev.cpu().numpy(), ol)
+    assert set(np.unique(ol)) == {0, 1, 2}
+    np.testing.assert_array_equal(col.cpu().numpy().view(np.uint32), oc.view(np.uint32))
+    fov.close()
+
+
 def _fused_vs_oracle(dev, spec, n, bias, mode, resolve=True):
     p = fwrs.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED,
                             stream_id=spec.stream_id, bias_mode=bias)
