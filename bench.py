@@ -524,6 +524,9 @@ def main() -> int:
     kern_ms = float(per.mean())
     achieved = spec.pixels * B / (kern_ms / 1e3) / 1e9
     traffic = traffic_from_counters(spec.pixels)
+    # VALU beside the bytes: instructions per pixel from the committed counter summary (null if stale)
+    h_vpp = valu_per_pixel("void fwrs::frame_kernel<4, 3, false>(fwrs::FrameDesc)")
+    h_valu = None if h_vpp is None else spec.pixels * h_vpp / (kern_ms / 1e3) / 1e12
     ms_per_step = total_ms / K
     value = spec.pixels * K / (total_ms / 1e3) / 1e9
 
@@ -647,7 +650,9 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
                      "kernel": "fwrs::frame_kernel<4, 3, false> (fused update + full resolve)",
-                     "kernel_ms_avg": kern_ms, "bytes_per_pixel_update": B, "slot_takes_per_pixel_update": rbar},
+                     "kernel_ms_avg": kern_ms, "bytes_per_pixel_update": B, "slot_takes_per_pixel_update": rbar,
+                     "valu_per_pixel": h_vpp,
+                     "valu_tops": h_valu, "valu_frac": None if h_valu is None else h_valu / VALU_PEAK_TOPS},
         "cpu_baseline": cpu,
         "ms_per_frame_p50": float(np.percentile(per, 50)),
         "ms_per_frame_p99": float(np.percentile(per, 99)),
