@@ -741,7 +741,7 @@ __global__ __launch_bounds__(kBlock) void mip_kernel(MipArgs a)
 struct GaussArgs {
     const float* src;
     float* dst;
-    uint32_t w, h;
+    uint32_t w, h, cols;                               // cols: blocks per strip
     float gx, gy, r0sq, r1sq;
     float g1[2 * kGaussR1 + 1];
     float g2[2 * kGaussR2 + 1];
@@ -762,7 +762,8 @@ __global__ __launch_bounds__(COLS) void gauss_levels_kernel(GaussArgs a)
 
     const int tid = (int)threadIdx.x;
     const int W = (int)a.w, H = (int)a.h;
-    const int x0 = (int)blockIdx.x * COLS, y0 = (int)blockIdx.y * ROWS;
+    const uint32_t bx = blockIdx.x % a.cols, by = blockIdx.x / a.cols;   // one-dimensional grid, row-major
+    const int x0 = (int)bx * COLS, y0 = (int)by * ROWS;
     const int x = x0 + tid;
 
     // Levels present in the block's pixels (block-uniform, conservative).
@@ -1012,17 +1013,17 @@ hipError_t launch_gauss_levels(const float* full, float* dst, uint32_t w, uint32
     // 16 waves each, else 4 rows: with fewer waves the per-row barrier and load
     // latency are not hidden.
     constexpr int C = kGaussCols;
-    const uint64_t cols = (w + C - 1) / C;
-    auto waves = [&](uint32_t rows) { return cols * ((h + rows - 1) / rows); };
+    a.cols = (w + C - 1) / C;
+    auto blocks = [&](uint32_t rows) { return (uint64_t)a.cols * ((h + rows - 1) / rows); };
     const dim3 block(C);
-    if (waves(32) >= 4000u)
-        hipLaunchKernelGGL((gauss_levels_kernel<32, C>), dim3(cols, (h + 31) / 32), block, 0, stream, a);
-    else if (waves(16) >= 4000u)
-        hipLaunchKernelGGL((gauss_levels_kernel<16, C>), dim3(cols, (h + 15) / 16), block, 0, stream, a);
-    else if (waves(8) >= 4000u)
-        hipLaunchKernelGGL((gauss_levels_kernel<8, C>), dim3(cols, (h + 7) / 8), block, 0, stream, a);
+    if (blocks(32) >= 4000u)
+        hipLaunchKernelGGL((gauss_levels_kernel<32, C>), dim3((uint32_t)blocks(32)), block, 0, stream, a);
+    else if (blocks(16) >= 4000u)
+        hipLaunchKernelGGL((gauss_levels_kernel<16, C>), dim3((uint32_t)blocks(16)), block, 0, stream, a);
+    else if (blocks(8) >= 4000u)
+        hipLaunchKernelGGL((gauss_levels_kernel<8, C>), dim3((uint32_t)blocks(8)), block, 0, stream, a);
     else
-        hipLaunchKernelGGL((gauss_levels_kernel<4, C>), dim3(cols, (h + 3) / 4), block, 0, stream, a);
+        hipLaunchKernelGGL((gauss_levels_kernel<4, C>), dim3((uint32_t)blocks(4)), block, 0, stream, a);
     return hipGetLastError();
 }
 

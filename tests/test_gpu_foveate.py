@@ -56,6 +56,7 @@ def test_foveate_matches_oracle(dev, mode, w, h):
     (600, 90, 299.5, 44.5, 40.0, 40.0),      # empty middle ring
     (600, 90, 0.0, 0.0, 0.0, 1e5),           # middle ring covers the frame
     (700, 300, 350.0, 150.0, 60.0, 200.0),   # all three levels, several blocks of each
+    (1, 300000, 0.5, 150000.0, 50.0, 5000.0),  # one column, more strips than a grid dimension of 65535 holds
 ])
 def test_foveate_ring_edge_cases(dev, mode, w, h, gx, gy, r0, r1):
     """Level maps whose blocks hold one, two or three levels, or none but level 0."""
