@@ -640,9 +640,9 @@ __global__ __launch_bounds__(kBlock) void reproject_kernel(ReprojDesc r)
 }
 
 // ---------------------------------------------------------------------------
-// Foveation generator (Sec. 4.3).  mip_kernel: one thread per mip-2 texel
-// builds its (up to) 2x2 mip-1 texels from the full frame and then itself, each
-// texel the mean of the children that exist, summed in row-major order.
+// Foveation generator (Sec. 4.3).  mip_kernel: one lane per mip-1 texel, the
+// mip-2 texels from their mip-1 children by wave shuffles; each texel the mean
+// of the children that exist, summed in row-major order.
 // gauss_levels_kernel: the separable Gaussian levels, clamp to edge,
 // accumulation in offset order.  foveate_kernel: the degraded frame and level map on their own;
 // foveated_kernel: the same sampling fused into the reservoir pass.
@@ -691,37 +691,51 @@ __device__ __forceinline__ float3 texel_mean(const float* src, uint32_t sw, uint
 
 __global__ __launch_bounds__(kBlock) void mip_kernel(MipArgs a)
 {
-    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= a.w2 * a.h2) return;
-    const uint32_t i2 = t % a.w2, j2 = t / a.w2;
-    float3 m[4];
-    bool in[4];
-#pragma unroll
-    for (uint32_t q = 0; q < 4; ++q) {
-        const uint32_t i1 = 2 * i2 + (q & 1u), j1 = 2 * j2 + (q >> 1);
-        in[q] = i1 < a.w1 && j1 < a.h1;
-        m[q] = texel_mean(a.full, a.w, a.h, in[q] ? i1 : 2 * i2, in[q] ? j1 : 2 * j2);
+    // One lane per mip-1 texel: a wave covers 32 mip-1 columns of the two
+    // mip-1 rows under one mip-2 row (lanes 0-31 the upper row, 32-63 the
+    // lower); lane pairs (2m, 2m + 1) of each half are the children of one
+    // mip-2 texel, gathered by wave shuffles in row-major order.
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6, lane = threadIdx.x & 63u;
+    const uint32_t strips = (a.w1 + 31u) / 32u;
+    if (wave >= strips * a.h2) return;                 // whole waves only
+    const uint32_t i1 = (wave % strips) * 32u + (lane & 31u), j2 = wave / strips;
+    const uint32_t j1 = 2u * j2 + (lane >> 5);
+    const bool own = i1 < a.w1 && j1 < a.h1;
+    const float3 m = texel_mean(a.full, a.w, a.h, own ? i1 : 0u, own ? j1 : 0u);
+    if (own) {
+        float* o = a.m1 + ((size_t)j1 * a.w1 + i1) * 3;
+        o[0] = m.x;
+        o[1] = m.y;
+        o[2] = m.z;
     }
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-    uint32_t n = 0u;
+    // children of mip-2 texel (i1 / 2, j2) for the even lanes of the upper row
+    const int src[3] = {(int)(lane ^ 1u), (int)(lane + 32u) & 63, (int)((lane ^ 1u) + 32u) & 63};
+    float v[4][3] = {{m.x, m.y, m.z}};
+    bool in[4] = {own};
 #pragma unroll
-    for (uint32_t q = 0; q < 4; ++q)
-        if (in[q]) {
-            const uint32_t i1 = 2 * i2 + (q & 1u), j1 = 2 * j2 + (q >> 1);
-            float* o = a.m1 + ((size_t)j1 * a.w1 + i1) * 3;
-            o[0] = m[q].x;
-            o[1] = m[q].y;
-            o[2] = m[q].z;
-            s0 = s0 + m[q].x;
-            s1 = s1 + m[q].y;
-            s2 = s2 + m[q].z;
-            n = n + 1u;
-        }
-    const float r = inv_count(n);
-    float* o = a.m2 + ((size_t)j2 * a.w2 + i2) * 3;
-    o[0] = s0 * r;
-    o[1] = s1 * r;
-    o[2] = s2 * r;
+    for (int q = 0; q < 3; ++q) {
+        v[q + 1][0] = __shfl(m.x, src[q]);
+        v[q + 1][1] = __shfl(m.y, src[q]);
+        v[q + 1][2] = __shfl(m.z, src[q]);
+        in[q + 1] = __shfl((int)own, src[q]) != 0;
+    }
+    if ((lane & 33u) == 0u && own) {                   // even lane of the upper row, texel exists
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        uint32_t n = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (in[q]) {
+                s0 = s0 + v[q][0];
+                s1 = s1 + v[q][1];
+                s2 = s2 + v[q][2];
+                n = n + 1u;
+            }
+        const float r = inv_count(n);
+        float* o = a.m2 + ((size_t)j2 * a.w2 + i1 / 2u) * 3;
+        o[0] = s0 * r;
+        o[1] = s1 * r;
+        o[2] = s2 * r;
+    }
 }
 
 // Gaussian levels from one read of the frame, into one plane: every pixel of
@@ -989,8 +1003,8 @@ hipError_t launch_mips(const float* full, float* m1, float* m2, uint32_t w, uint
     MipArgs a{full, m1, m2, w, h, (w + 1) / 2, (h + 1) / 2, 0u, 0u};
     a.w2 = (a.w1 + 1) / 2;
     a.h2 = (a.h1 + 1) / 2;
-    const uint32_t n = a.w2 * a.h2;
-    hipLaunchKernelGGL(mip_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, a);
+    const uint64_t threads = (uint64_t)((a.w1 + 31u) / 32u) * a.h2 * 64u;   // whole waves
+    hipLaunchKernelGGL(mip_kernel, dim3((uint32_t)((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 
