@@ -201,7 +201,9 @@ int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void
  * context is accepted. */
 int fwrs_destroy(fwrs_ctx* ctx);
 
-/* Changes the stream later calls enqueue on (borrowed, NULL = null stream). */
+/* Changes the stream later calls enqueue on (borrowed, NULL = null stream).
+ * Waits for the previous stream first, so later calls and fwrs_destroy need
+ * only the new one.  FWRS_E_HIP if that wait fails (the stream is unchanged). */
 int fwrs_set_stream(fwrs_ctx* ctx, void* hip_stream);
 
 /* Enqueues a clear of the store to the empty state and sets the frame index
@@ -325,8 +327,13 @@ typedef struct fwrs_engine fwrs_engine;
  * the stream must then not be capturing. */
 int fwrs_engine_create(void* hip_stream, int max_frames, int use_graph, fwrs_engine** out);
 
-/* Enqueues one tick.  FWRS_E_ARG: n outside [0, max_frames], a NULL field, a
- * context repeated, contexts on another device. */
+/* Enqueues one tick on the engine's stream.  A context whose own stream is
+ * another one is ordered by events: the tick waits for the work already
+ * enqueued on that stream, and later work there (fwrs_destroy's wait
+ * included) waits for the tick.  FWRS_E_ARG: n outside [0, max_frames], a NULL
+ * field, a context repeated, contexts on another device.  FWRS_E_HIP: a
+ * launch or event call failed (if only the final ordering failed, the tick
+ * ran and the contexts advanced). */
 int fwrs_engine_tick(fwrs_engine* eng, const fwrs_frame* frames, int n);
 
 /* Selects the tile shape the engine uses for contexts whose width * height is
@@ -355,8 +362,8 @@ int fwrs_engine_destroy(fwrs_engine* eng);
  *                   normalised, clamp to edge) at the pixel.
  * Every operation is binary32 in a fixed order, so results are reproducible
  * bit for bit.  The foveator owns the level images (mip: N/4 + N/16 texels;
- * Gaussian: N), reused by every call: calls on one foveator must be ordered
- * on one stream. */
+ * Gaussian: N), reused by every call: fwrs_foveate runs on the foveator's
+ * stream, and fwrs_push_frame_foveated orders itself against that stream. */
 #define FWRS_FOV_MIP 0u
 #define FWRS_FOV_GAUSS 1u
 
@@ -376,7 +383,10 @@ int fwrs_foveate(fwrs_foveator* fov, const float* full, float gaze_x, float gaze
 /* fwrs_foveate followed by fwrs_push_frame_resolve (or fwrs_push_frame if
  * `out` is NULL) without the intermediate frame: the level images are built,
  * then one reservoir pass samples its candidates from them directly.  Runs on
- * the context's stream; results are bit-identical to the two calls.
+ * the context's stream; if the foveator's stream is another one, the call
+ * first waits (by an event) for the work enqueued there, and later work there
+ * (fwrs_foveator_destroy's wait included) waits for this call.  Results are
+ * bit-identical to the two calls.
  * FWRS_E_ARG: NULL ctx, fov or full, non-finite gaze, sizes differ.
  * FWRS_E_STATE: as fwrs_push_frame (a reprojecting context is refused). */
 int fwrs_push_frame_foveated(fwrs_ctx* ctx, fwrs_foveator* fov, const float* full, float gaze_x, float gaze_y,

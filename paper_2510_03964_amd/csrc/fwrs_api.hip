@@ -107,6 +107,23 @@ struct DeviceGuard {
     }
 };
 
+// Makes `waiter` wait for the work enqueued so far on `signaller` (nothing when
+// they are one stream).  `ev` is created on first use; its owner destroys it.
+hipError_t order_after(hipStream_t waiter, hipStream_t signaller, hipEvent_t& ev)
+{
+    if (waiter == signaller) return hipSuccess;
+    if (!ev) {
+        const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            ev = nullptr;
+            return e;
+        }
+    }
+    hipError_t e = hipEventRecord(ev, signaller);
+    if (e == hipSuccess) e = hipStreamWaitEvent(waiter, ev, 0);
+    return e;
+}
+
 }  // namespace
 
 struct fwrs_ctx {
@@ -140,6 +157,7 @@ struct fwrs_ctx {
     uint32_t resolved_at = 0;
     bool resolved = false;
     int tile_x = kDefaultTileX, tile_y = kDefaultTileY;
+    hipEvent_t order_ev = nullptr;   // marks this context's stream for work on other streams
 };
 
 namespace {
@@ -343,6 +361,7 @@ int fwrs_destroy(fwrs_ctx* x)
         DeviceGuard g(x->device);
         if (hipStreamSynchronize(x->stream) != hipSuccess) rc = FWRS_E_HIP;
         if (x->owns_arena && hipFree(x->arena) != hipSuccess) rc = FWRS_E_HIP;
+        if (x->order_ev) (void)hipEventDestroy(x->order_ev);
     }
     delete x;
     return rc;
@@ -351,6 +370,11 @@ int fwrs_destroy(fwrs_ctx* x)
 int fwrs_set_stream(fwrs_ctx* x, void* hip_stream)
 {
     if (!x) return FWRS_E_ARG;
+    if ((hipStream_t)hip_stream != x->stream) {
+        // later calls and fwrs_destroy see only the new stream
+        DeviceGuard g(x->device);
+        if (!g.ok || hipStreamSynchronize(x->stream) != hipSuccess) return FWRS_E_HIP;
+    }
     x->stream = (hipStream_t)hip_stream;
     return FWRS_OK;
 }
@@ -593,6 +617,7 @@ struct fwrs_engine {
     std::vector<TileClass> classes;
     std::vector<fwrs::TickArgs> args;          // one per launch of the current tick
     std::vector<TickGraph> graphs;             // graphs[m - 1]: a tick of m launches
+    hipEvent_t done_ev = nullptr;              // end of the latest tick, for contexts on other streams
 };
 
 namespace {
@@ -603,6 +628,7 @@ void engine_free(fwrs_engine* e)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
         if (g.graph) (void)hipGraphDestroy(g.graph);
     }
+    if (e->done_ev) (void)hipEventDestroy(e->done_ev);
     delete e;
 }
 
@@ -725,8 +751,17 @@ int fwrs_engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n)
             ++a.n;
         }
     }
+    // each context's earlier work on its own stream comes first
     hipError_t err = hipSuccess;
-    if (e->use_graph) {
+    bool foreign = false;
+    for (int i = 0; i < n && err == hipSuccess; ++i) {
+        fwrs_ctx* c = frames[i].ctx;
+        if (c->stream != e->stream) {
+            foreign = true;
+            err = order_after(e->stream, c->stream, c->order_ev);
+        }
+    }
+    if (err == hipSuccess && e->use_graph) {
         TickGraph* tg = nullptr;
         err = engine_graph(e, m, &tg);
         for (int c = 0; c < m && err == hipSuccess; ++c) {
@@ -749,6 +784,20 @@ int fwrs_engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n)
         c->resolved_out = frames[i].out;
         c->resolved_at = c->t;
         c->resolved = true;
+    }
+    // ... and its later work (and fwrs_destroy) waits for this tick
+    if (foreign) {
+        if (!e->done_ev && hipEventCreateWithFlags(&e->done_ev, hipEventDisableTiming) != hipSuccess) {
+            e->done_ev = nullptr;
+            err = hipErrorOutOfMemory;
+        }
+        if (err == hipSuccess) err = hipEventRecord(e->done_ev, e->stream);
+        for (int i = 0; i < n && err == hipSuccess; ++i)
+            if (frames[i].ctx->stream != e->stream) err = hipStreamWaitEvent(frames[i].ctx->stream, e->done_ev, 0);
+        if (err != hipSuccess) {
+            (void)hipGetLastError();
+            return FWRS_E_HIP;
+        }
     }
     return FWRS_OK;
 }
@@ -775,6 +824,7 @@ struct fwrs_foveator {
     uint32_t mode = FWRS_FOV_MIP;
     float r0 = 0.f, r1 = 0.f;
     hipStream_t stream = nullptr;
+    hipEvent_t order_ev = nullptr;         // marks `stream` for contexts on other streams
     float* buf = nullptr;                  // one allocation for the level images
     float* l1 = nullptr;
     float* l2 = nullptr;
@@ -899,6 +949,9 @@ int fwrs_push_frame_foveated(fwrs_ctx* x, fwrs_foveator* f, const float* full, f
     if (x->t == 0xFFFFFFFFu || x->reproject) return FWRS_E_STATE;
     DeviceGuard g(x->device);
     if (!g.ok) return FWRS_E_HIP;
+    // The level images are rebuilt on the context's stream: after the
+    // foveator's earlier work, and before its later work and its destroy.
+    if (order_after(x->stream, f->stream, f->order_ev) != hipSuccess) return FWRS_E_HIP;
     hipError_t err = hipSuccess;
     fwrs::FovDesc fd{};
     fd.s = build_levels(f, full, gaze_x, gaze_y, x->stream, err);
@@ -914,6 +967,7 @@ int fwrs_push_frame_foveated(fwrs_ctx* x, fwrs_foveator* f, const float* full, f
     } else {
         x->resolved = false;
     }
+    if (order_after(f->stream, x->stream, x->order_ev) != hipSuccess) return FWRS_E_HIP;
     return FWRS_OK;
 }
 
@@ -925,6 +979,7 @@ int fwrs_foveator_destroy(fwrs_foveator* f)
         DeviceGuard g(f->device);
         if (hipStreamSynchronize(f->stream) != hipSuccess) rc = FWRS_E_HIP;
         if (f->buf && hipFree(f->buf) != hipSuccess) rc = FWRS_E_HIP;
+        if (f->order_ev) (void)hipEventDestroy(f->order_ev);
     }
     delete f;
     return rc;
