@@ -205,6 +205,14 @@ def _ptr(t) -> int:
     return int(t.data_ptr())
 
 
+def _f32(t) -> bool:
+    return str(t.dtype) == "torch.float32"
+
+
+def _u8(t) -> bool:
+    return str(t.dtype) == "torch.uint8"
+
+
 @dataclass
 class HostState:
     """A packed host copy of a context's reservoir store (see fwrs_download_state)."""
@@ -268,15 +276,15 @@ class Reservoir:
 
     def _check_frame(self, color, level) -> None:
         H, W = self.height, self.width
-        if tuple(color.shape) != (H, W, 3) or color.dtype.itemsize != 4 or not color.is_contiguous():
+        if tuple(color.shape) != (H, W, 3) or not _f32(color) or not color.is_contiguous():
             raise ValueError(f"color must be contiguous float32 [{H}, {W}, 3]")
-        if tuple(level.shape) != (H, W) or level.dtype.itemsize != 1 or not level.is_contiguous():
+        if tuple(level.shape) != (H, W) or not _u8(level) or not level.is_contiguous():
             raise ValueError(f"level must be contiguous uint8 [{H}, {W}]")
         if not (color.is_cuda and level.is_cuda):
             raise ValueError("color and level must be device tensors")
 
     def _check_out(self, out) -> None:
-        if tuple(out.shape) != (self.height, self.width, 3) or out.dtype.itemsize != 4 or not out.is_contiguous():
+        if tuple(out.shape) != (self.height, self.width, 3) or not _f32(out) or not out.is_contiguous():
             raise ValueError("out must be contiguous float32 [H, W, 3]")
         if not out.is_cuda:
             raise ValueError("out must be a device tensor")
@@ -313,9 +321,9 @@ class Reservoir:
         given.  The context must have been created with FLAG_REPROJECT."""
         self._check_frame(color, level)
         H, W = self.height, self.width
-        if tuple(motion.shape) != (H, W, 2) or motion.dtype.itemsize != 4 or not motion.is_contiguous():
+        if tuple(motion.shape) != (H, W, 2) or not _f32(motion) or not motion.is_contiguous():
             raise ValueError(f"motion must be contiguous float32 [{H}, {W}, 2]")
-        if tuple(depth.shape) != (H, W) or depth.dtype.itemsize != 4 or not depth.is_contiguous():
+        if tuple(depth.shape) != (H, W) or not _f32(depth) or not depth.is_contiguous():
             raise ValueError(f"depth must be contiguous float32 [{H}, {W}]")
         if not (motion.is_cuda and depth.is_cuda):
             raise ValueError("motion and depth must be device tensors")
@@ -441,15 +449,15 @@ class Foveator:
 
     def _check_full(self, full) -> None:
         H, W = self.height, self.width
-        if tuple(full.shape) != (H, W, 3) or full.dtype.itemsize != 4 or not full.is_contiguous() or not full.is_cuda:
+        if tuple(full.shape) != (H, W, 3) or not _f32(full) or not full.is_contiguous() or not full.is_cuda:
             raise ValueError(f"full must be a contiguous float32 device tensor [{H}, {W}, 3]")
 
     def foveate(self, full, gaze_x: float, gaze_y: float, color, level) -> None:
         self._check_full(full)
         H, W = self.height, self.width
-        if tuple(color.shape) != (H, W, 3) or not color.is_contiguous() or not color.is_cuda:
+        if tuple(color.shape) != (H, W, 3) or not _f32(color) or not color.is_contiguous() or not color.is_cuda:
             raise ValueError("color must be a contiguous float32 device tensor [H, W, 3]")
-        if tuple(level.shape) != (H, W) or level.dtype.itemsize != 1 or not level.is_contiguous():
+        if tuple(level.shape) != (H, W) or not _u8(level) or not level.is_contiguous() or not level.is_cuda:
             raise ValueError("level must be a contiguous uint8 device tensor [H, W]")
         _check(self._L.fwrs_foveate(self._h, _ptr(full), float(gaze_x), float(gaze_y), _ptr(color), _ptr(level)),
                "fwrs_foveate")

@@ -124,6 +124,7 @@ class Scheduler:
       submit(list[(handle, frame_index)]) -> tick id   (asynchronous)
       poll() -> list[(tick id, completion time in the clock's seconds)]
       drain() -> same as poll, after waiting for all submitted work
+      max_batch (optional attribute) -> the most frames one submit may carry
     """
 
     def __init__(self, executor, budget_bytes: int, max_active: int = 64, max_inflight: int = 2,
@@ -193,6 +194,10 @@ class Scheduler:
                 for a in active.values():
                     if a.due_s(a.next_frame) <= now and a.due_s(a.next_frame) < a.end_s:
                         batch.append(a)
+                cap = getattr(ex, "max_batch", None)
+                if cap is not None and len(batch) > cap:    # the rest stay due for the next tick
+                    batch.sort(key=lambda a: a.due_s(a.next_frame))
+                    batch = batch[:cap]
             if batch:
                 stats["max_batch"] = max(stats["max_batch"], len(batch))
                 tick = ex.submit([(a.handle, a.next_frame) for a in batch])
@@ -316,6 +321,7 @@ class BatchedExecutor(_GpuExecutor):
     def __init__(self, frames_by_size: dict, max_frames: int = 64, use_graph: bool = True, **kw):
         super().__init__(frames_by_size, **kw)
         self.engine = self.fwrs.Engine(max_frames, stream=self.stream, use_graph=use_graph)
+        self.max_batch = int(max_frames)
         for (w, h), t in self.tiles.items():
             self.engine.set_tile(w * h, *t)
 

@@ -174,6 +174,16 @@ def test_foveator_argument_checks(dev):
     lev = torch.empty((32, 64), dtype=torch.uint8, device=dev)
     with pytest.raises(fwrs.FwrsError):
         fov.foveate(full, float("inf"), 1.0, col, lev)
+    with pytest.raises(ValueError):                          # element types are checked, not only their sizes
+        fov.foveate(full.to(torch.int32), 1.0, 1.0, col, lev)
+    with pytest.raises(ValueError):
+        fov.foveate(full, 1.0, 1.0, col, lev.to(torch.int8))
+    wide = fwrs.Reservoir(64, 32, 4, stream=stream)
+    with pytest.raises(ValueError):
+        wide.step(full, lev, 1.0, 1.0, torch.empty((32, 64, 3), dtype=torch.int32, device=dev))
+    with pytest.raises(ValueError):
+        wide.step(full, lev.to(torch.int8), 1.0, 1.0, col)
+    wide.close()
     fov.close()
 
 

@@ -161,3 +161,25 @@ def test_batches_grow_when_the_device_is_busy():
     heavy, _ = _run(_small_mix(), budget=1 << 40, s_per_pixel=1e-6)
     assert heavy.frames / heavy.ticks > light.frames / light.ticks
     assert heavy.max_batch > 1
+
+
+def test_ticks_never_exceed_the_executors_batch_limit():
+    """An executor that takes at most `max_batch` frames per submit: the rest of the due frames go into the
+    next tick, and every frame is still processed once, in order."""
+    sessions = _small_mix(n=12, scale=0.02)
+    clk = VirtualClock()
+    uncapped = FakeExecutor(clk, 1e-6)                       # a busy device: batches grow past the limit
+    serve.Scheduler(uncapped, 1 << 40, max_active=12, clock=clk, sleep=clk.sleep).run(sessions)
+    assert max(len(f) for _, f in uncapped.log) > 3
+    clk = VirtualClock()
+    ex = FakeExecutor(clk, 1e-6)
+    ex.max_batch = 3
+    st = serve.Scheduler(ex, 1 << 40, max_active=12, clock=clk, sleep=clk.sleep).run(sessions)
+    assert max(len(f) for _, f in ex.log) <= 3
+    assert st.max_batch <= 3
+    seen = {}
+    for _, frames in ex.log:
+        for sid, i in frames:
+            assert seen.get(sid, -1) == i - 1
+            seen[sid] = i
+    assert st.frames == sum(len(f) for _, f in ex.log) and st.admitted == len(sessions)
