@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "4K k=4 update+resolve ms & Gpix/s, %HBM peak; multi-stream p99 vs plain"
 HBM_PEAK_GBPS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "fused_k4_4k_counters.json")
+INC_COUNTERS = os.path.join(ROOT, "profiles", "incremental_k4_4k_counters.json")
 VALU_COUNTERS = os.path.join(ROOT, "profiles", "fused_valu_4k_counters.json")
 #: VALU issue peak of the MI355X in lane-operations per second: the published fp32 vector rate, 157.3 TFLOP/s,
 #: counts a fused multiply-add as two flops, i.e. 78.6 T lane-operations/s (256 CUs x 128 lanes x 2.4 GHz)
@@ -79,12 +80,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_counters(n_pixels: int) -> float | None:
+def traffic_from_counters(n_pixels: int, path: str = COUNTERS) -> float | None:
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
     current kernel sources and workload; None otherwise."""
-    if not os.path.exists(COUNTERS):
+    if not os.path.exists(path):
         return None
-    with open(COUNTERS) as f:
+    with open(path) as f:
         c = json.load(f)
     if c.get("source_hash") != kernel_source_hash() or c.get("pixels") != n_pixels:
         return None
@@ -550,7 +551,9 @@ def main() -> int:
                        "unit": "Gpixel-updates/s", "ms_per_frame_p50": float(np.percentile(inc_per, 50)),
                        "ms_per_frame_p99": float(np.percentile(inc_per, 99)),
                        "roofline": {"bound": "hbm", "achieved": i_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                                    "frac": i_ach / HBM_PEAK_GBPS, "kernel_ms_avg": i_kern,
+                                    "frac": i_ach / HBM_PEAK_GBPS,
+                                    "traffic": traffic_from_counters(spec.pixels, INC_COUNTERS),
+                                    "kernel_ms_avg": i_kern,
                                     "bytes_per_pixel_update": i_B, "slot_takes_per_pixel_update": i_rbar,
                                     "changed_pixel_fraction": i_changed_frac}}
         log(f"incremental: {inc_ms / n_inc:.4f} ms/frame")
