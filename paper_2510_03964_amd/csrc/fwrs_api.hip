@@ -618,6 +618,7 @@ struct fwrs_engine {
     std::vector<fwrs::TickArgs> args;          // one per launch of the current tick
     std::vector<TickGraph> graphs;             // graphs[m - 1]: a tick of m launches
     hipEvent_t done_ev = nullptr;              // end of the latest tick, for contexts on other streams
+    uint32_t ticks = 0;                        // ticks issued (odd ticks run in reverse order)
 };
 
 namespace {
@@ -737,11 +738,17 @@ int fwrs_engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n)
     DeviceGuard g(e->device);
     if (!g.ok) return FWRS_E_HIP;
     const int m = (n + fwrs::kTickFrames - 1) / fwrs::kTickFrames;
+    // Every other tick walks its work items last first (launches in reverse
+    // order, each launch's items in reverse), so a tick starts on the state the
+    // previous one touched last, while it is still in the Infinity Cache.
+    const bool reverse = (e->ticks & 1u) != 0u;
     for (int c = 0; c < m; ++c) {
         fwrs::TickArgs& a = e->args[c];
+        const int chunk = reverse ? m - 1 - c : c;
         a.n = 0;
         a.total = 0;
-        for (int i = c * fwrs::kTickFrames; i < n && i < (c + 1) * fwrs::kTickFrames; ++i) {
+        a.reverse = reverse ? 1u : 0u;
+        for (int i = chunk * fwrs::kTickFrames; i < n && i < (chunk + 1) * fwrs::kTickFrames; ++i) {
             const fwrs_frame& f = frames[i];
             int tx, ty;
             engine_tile(e, (long long)f.ctx->width * f.ctx->height, tx, ty);
@@ -777,6 +784,7 @@ int fwrs_engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n)
         (void)hipGetLastError();
         return FWRS_E_HIP;
     }
+    e->ticks += 1u;
     for (int i = 0; i < n; ++i) {
         fwrs_ctx* c = frames[i].ctx;
         c->t += 1u;

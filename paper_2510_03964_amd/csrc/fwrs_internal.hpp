@@ -20,9 +20,10 @@ constexpr int kGaussCols = 64;          // columns (threads) per block of the Ga
 hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream);
 
 // Arguments of one batched launch: n frames, `total` work items, frame f owns
-// items [begins[f], begins[f + 1]).  Passed by value (< 4 KiB).
+// items [begins[f], begins[f + 1]); reverse != 0 visits the items last first.
+// Passed by value (< 4 KiB).
 struct TickArgs {
-    uint32_t n, total;
+    uint32_t n, total, reverse;
     uint32_t begins[kTickFrames];
     FrameDesc descs[kTickFrames];
 };
