@@ -314,6 +314,39 @@ def test_engine_tick_matches_oracle_and_plain_launches(dev, use_graph):
     eng.close()
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_engine_ticks_over_several_launches(dev, use_graph):
+    """40 contexts per tick: a tick is split into two launches of at most 24 frames, and every other tick walks
+    the launches and their items in reverse.  Every context's output and state equal plain launches."""
+    ks = (1, 2, 3, 4, 8)
+    specs = [synth.StreamSpec(48 + 8 * (i % 3), 32, ks[i % len(ks)], 4, 4.0, 10.0, 1.0, 2, 2.0, stream_id=100 + i)
+             for i in range(40)]
+    stream = torch.cuda.current_stream()
+    srcs = [synth.FrameSource(s, device=dev) for s in specs]
+    eng = fwrs.Engine(len(specs), stream=stream, use_graph=use_graph)
+    batched, plain, outs_b, outs_p = [], [], [], []
+    for s in specs:
+        p, _ = _params(s)
+        batched.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
+        plain.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
+        outs_b.append(torch.empty((s.height, s.width, 3), device=dev))
+        outs_p.append(torch.empty((s.height, s.width, 3), device=dev))
+    for t in range(4):
+        frames = [src.frame(t) for src in srcs]
+        eng.tick([(batched[i], *frames[i], outs_b[i]) for i in range(len(specs))])
+        for i in range(len(specs)):
+            plain[i].step(*frames[i], outs_p[i])
+    torch.cuda.synchronize()
+    for i in range(len(specs)):
+        assert batched[i].frame_index == 4
+        assert torch.equal(outs_b[i], outs_p[i]), f"context {i}"
+        _compare_state(batched[i].download(), plain[i].download(), f"context {i}")
+        assert batched[i].stats() == plain[i].stats()
+        batched[i].close()
+        plain[i].close()
+    eng.close()
+
+
 def test_engine_stream_alone_equals_stream_in_mix(dev):
     specs = _mix_specs()
     stream = torch.cuda.current_stream()
