@@ -204,32 +204,29 @@ float fwrs_oracle_weight(const fwrs_oracle* o, int x, int y, uint8_t level, floa
 }
 
 /* ------------------------------------------------------------------------ */
-/* log2 of the uniform variate u = ((bits >> 8) + 1) * 2^-24, for A-ES keys.  */
-/* With m = (bits >> 8) + 1 = 2^e * f, f in [sqrt(1/2), sqrt(2)):             */
-/*   log2(u) = (e - 24) + log2(f),                                            */
-/*   log2(f) = (2 / ln 2) atanh(s) = sum_i 2 s^(2i+1) / ((2i+1) ln 2),        */
-/*   s = (f - 1) / (f + 1), |s| < 0.172, six terms.                           */
+/* log2 of the uniform variate u = ((bits >> 8) + 1) * 2^-24, for A-ES keys:   */
+/* the binary32 value nearest to the real number log2(u) = log2(m) - 24,       */
+/* m = (bits >> 8) + 1 in 1 .. 2^24.  log2(m) is an integer when m is a power  */
+/* of two and irrational otherwise, so it is never halfway between two        */
+/* binary32 values and the nearest one is unique.  It is found from the        */
+/* extended-precision log2l (64-bit significand): rounding that value to       */
+/* binary32 gives the nearest binary32 unless it lies within a few of its own  */
+/* ulps of a binary32 midpoint, which the function reports by returning NaN    */
+/* (a test evaluates all 2^24 variates and finds none).                        */
 /* ------------------------------------------------------------------------ */
 float fwrs_oracle_log2u(uint32_t bits)
 {
     const uint32_t m = (bits >> 8) + 1u;                 /* 1 .. 2^24 */
-    int e = 0;
-    while ((m >> (e + 1)) != 0u) ++e;                    /* floor(log2 m) */
-    float f = (float)m;
-    for (int i = 0; i < e; ++i) f = f * 0.5f;            /* exact: f in [1, 2) */
-    if (f >= 0x1.6a09e6p+0f) {                           /* sqrt(2) rounded */
-        f = f * 0.5f;
-        e = e + 1;
-    }
-    const float s = (f - 1.0f) / (f + 1.0f);
-    const float z = s * s;
-    float p = 0x1.0c9a84p-2f;                            /* 2 / (11 ln 2) */
-    p = p * z + 0x1.484b14p-2f;                          /* 2 / (9 ln 2) */
-    p = p * z + 0x1.a61762p-2f;                          /* 2 / (7 ln 2) */
-    p = p * z + 0x1.2776c6p-1f;                          /* 2 / (5 ln 2) */
-    p = p * z + 0x1.ec709ep-1f;                          /* 2 / (3 ln 2) */
-    p = p * z + 0x1.715476p+1f;                          /* 2 / ln 2 */
-    return (float)(e - 24) + s * p;
+    const long double v = log2l((long double)m) - 24.0L;
+    if (v == 0.0L) return 0.0f;
+    const float f = (float)v;
+    /* the binary32 neighbours of v and the midpoint between them (exact in long double) */
+    const float lo = (long double)f <= v ? f : nextafterf(f, -INFINITY);
+    const float hi = nextafterf(lo, INFINITY);
+    const long double mid = ((long double)lo + (long double)hi) * 0.5L;
+    const long double guard = fabsl(v) * 0x1p-58L;       /* a few ulps of the 64-bit significand */
+    if (fabsl(v - mid) <= guard) return NAN;
+    return f;
 }
 
 float fwrs_oracle_decay(const fwrs_oracle* o) { return o->decay; }
@@ -389,30 +386,70 @@ int fwrs_oracle_foveate(const float* full, int width, int height, float gx, floa
 /* ------------------------------------------------------------------------ */
 /* Colour difference for Eq. 7.                                               */
 /* ------------------------------------------------------------------------ */
-/* Cube root for t > 0 without division: the reciprocal cube root r from an  */
-/* exponent-bit seed (the bit pattern of t^(-1/3) is about                    */
-/* (4/3)*127*2^23 - bits(t)/3), two Newton steps r <- r (4 - t r^3) / 3, then */
-/* y = t r^2 and one Newton step on y itself, y <- y - (y^3 - t) r^2 / 3      */
-/* (r^2 standing in for 1 / y^2).  1/3 is its binary32 rounding.             */
+/* Cube root: the binary32 value nearest to the real number t^(1/3).  For a  */
+/* binary32 y = M 2^E (M a 24-bit integer) the midpoint to the next binary32   */
+/* above is (2M + 1) 2^(E-1), a 25-bit significand, whose cube has 75 bits and */
+/* is never a binary32; so the real cube root of t is never halfway and the   */
+/* nearest binary32 is unique: it is the y whose lower midpoint cubed is below */
+/* t and whose upper midpoint cubed is above t.  Those cubes are compared with */
+/* t exactly in 128-bit integer arithmetic, starting from libm's binary64     */
+/* cube root rounded to binary32 and stepping to a neighbour while a           */
+/* comparison fails.  cbrt(0) = 0, cbrt(inf) = inf, NaN stays NaN, and         */
+/* cbrt(-t) = -cbrt(t).                                                        */
+typedef unsigned __int128 u128;
+
+static int bit_length(u128 v)
+{
+    int n = 0;
+    while (v) { v >>= 1; ++n; }
+    return n;
+}
+
+/* Sign of a 2^ea - b 2^eb for a, b > 0. */
+static int compare_scaled(u128 a, int ea, u128 b, int eb)
+{
+    const int la = bit_length(a) + ea, lb = bit_length(b) + eb;
+    if (la != lb) return la < lb ? -1 : 1;
+    /* same binade: align the exponents (the shifted value keeps the other's bit length) */
+    if (ea > eb) a <<= (unsigned)(ea - eb);
+    else b <<= (unsigned)(eb - ea);
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* A finite binary32 x > 0 as an integer significand times a power of two. */
+static void split_float(float x, u128* sig, int* ex)
+{
+    int e;
+    const float f = frexpf(x, &e);                       /* x = f 2^e, f in [1/2, 1) */
+    *sig = (u128)(uint32_t)ldexpf(f, 24);                /* exact: 24 bits */
+    *ex = e - 24;
+}
+
+/* Sign of m^3 - t, m the midpoint between y > 0 and the next binary32 above it. */
+static int midpoint_cube_vs(float y, float t)
+{
+    u128 M, T;
+    int E, Et;
+    split_float(y, &M, &E);
+    split_float(t, &T, &Et);
+    const u128 m = 2 * M + 1;                            /* midpoint = m 2^(E-1) */
+    return compare_scaled(m * m * m, 3 * (E - 1), T, Et);
+}
+
 float fwrs_oracle_cbrt(float t)
 {
-    uint32_t bits;
-    memcpy(&bits, &t, 4);
-    bits = 0x54A2FA8Cu - bits / 3u;
-    float r;
-    memcpy(&r, &bits, 4);
-    const float third = 0x1.555556p-2f;
-    for (int it = 0; it < 2; ++it) {
-        float r2 = r * r;
-        float r3 = r2 * r;
-        float d = 4.0f - t * r3;
-        r = (r * d) * third;
+    if (t != t || t == 0.0f || t == INFINITY || t == -INFINITY) return t;
+    if (t < 0.0f) return -fwrs_oracle_cbrt(-t);
+    float y = (float)cbrt((double)t);
+    /* libm's binary64 cube root rounded to binary32 is within one ulp, so a step or two at most:
+     * up while the cube root lies above the upper midpoint, down while it lies below the lower
+     * midpoint (the upper midpoint of the binary32 below y).  NaN if that does not settle. */
+    for (int step = 0; step < 4; ++step) {
+        if (midpoint_cube_vs(y, t) < 0) y = nextafterf(y, INFINITY);
+        else if (midpoint_cube_vs(nextafterf(y, 0.0f), t) > 0) y = nextafterf(y, 0.0f);
+        else return y;
     }
-    float r2 = r * r;
-    float y = t * r2;
-    float y3 = (y * y) * y;
-    float c = ((y3 - t) * r2) * third;
-    return y - c;
+    return NAN;
 }
 
 /* CIE Lab f(): cube root above (6/29)^3, the linear segment below. */

@@ -1,6 +1,7 @@
 """Pins of the oracle's ablation modes (Sec. 3.1): A-ES keys and the memory-less bias, CPU only.
 
-What fixes the expected values: log2 of the 2^24 possible variates against binary64 log2; the
+What fixes the expected values: log2 of the 2^24 possible variates against binary64 log2 and a
+high-precision decimal log2; the
 decay factor against binary64 exp; for a single stream, the Efraimidis-Spirakis theorem (the
 largest key u^(1/w) belongs to item i with probability w_i / sum w) and the closed form of the
 memory-less bias, P(final = i) = w_i d^(N-i) / sum_j w_j d^(N-j) with d = exp(-lambda), both by
@@ -8,33 +9,51 @@ chi-square over 10^5 Philox seeds; lambda = 0 is plain Alg. 2 bit for bit."""
 from __future__ import annotations
 
 import math
+from decimal import Decimal, localcontext
 
 import numpy as np
 import pytest
 
 from paper_2510_03964_amd import synth
+from test_oracle_eq7 import _nearest_f32
 from test_oracle_pins import P_REJECT, _chi2_pvalue, _pixel_stream, varied_pixel  # noqa: F401
 
 
+def _log2_decimal(m):
+    """log2(m) - 24 to 60 significant digits."""
+    with localcontext() as ctx:
+        ctx.prec = 60
+        return Decimal(int(m)).ln() / Decimal(2).ln() - 24
+
+
 def test_log2_of_every_variate(oracle_mod):
+    """log2 of the variate is the binary32 nearest to log2(m) - 24: against binary64 log2 for all
+    2^24 variates (the two agree wherever binary64 is not within 2^-30 ulp of a binary32
+    midpoint), and against a 60-digit decimal log2 on random variates and on those nearest a
+    midpoint; exact at the powers of two; monotone."""
     m = np.arange(1, 2 ** 24 + 1, dtype=np.uint64)
     bits = ((m - 1) << np.uint64(8)).astype(np.uint32)
-    got = oracle_mod.log2u(bits).astype(np.float64)
-    want = np.log2(m.astype(np.float64)) - 24.0
-    err = np.abs(got - want)
-    # within 3 ulp of the result for every variate (near u = 1 the result is tiny and the
-    # bound is relative to it)
-    nz = want != 0.0
-    ulp = np.ldexp(1.0, np.floor(np.log2(np.abs(want[nz]))).astype(np.int64) - 23)
-    assert (err[nz] / ulp).max() <= 3.0
+    got = oracle_mod.log2u(bits)
+    want64 = np.log2(m.astype(np.float64)) - 24.0
+    nz = want64 != 0.0
+    ulp = np.ldexp(1.0, np.floor(np.log2(np.abs(want64[nz]))).astype(np.int64) - 23)
+    dist = np.abs((np.abs(want64[nz]) / ulp) % 1.0 - 0.5)       # distance to a midpoint, in ulps
+    clear = dist > 2.0 ** -30
+    assert np.array_equal(got[nz][clear], want64[nz][clear].astype(np.float32))
     assert got[~nz].tolist() == [0.0]
+    rng = np.random.Generator(np.random.PCG64(32))
+    pick = np.concatenate([rng.integers(1, 2 ** 24 + 1, 1000), m[nz][np.argsort(dist)[:300]].astype(np.int64)])
+    for mi in pick:
+        g = oracle_mod.log2u(np.array([(int(mi) - 1) << 8], np.uint32))[0]
+        want = _nearest_f32(_log2_decimal(mi), np.float32(np.log2(float(mi)) - 24.0))
+        assert g == want, f"log2 variate m={int(mi)}: {float(g)!r} vs nearest {float(want)!r}"
     # exact at the powers of two; monotone non-decreasing in the variate
     pw = np.array([2 ** e for e in range(25)], np.uint64)
     assert np.array_equal(oracle_mod.log2u(((pw - 1) << np.uint64(8)).astype(np.uint32)),
                           np.arange(25, dtype=np.float32) - 24)
-    assert np.all(np.diff(got) >= 0.0)
+    assert np.all(np.diff(got.astype(np.float64)) >= 0.0)
     # the low 8 bits of the word are not used
-    assert np.array_equal(oracle_mod.log2u(bits[:1000] | np.uint32(0xFF)), got[:1000].astype(np.float32))
+    assert np.array_equal(oracle_mod.log2u(bits[:1000] | np.uint32(0xFF)), got[:1000])
 
 
 @pytest.mark.parametrize("lam", [0.0231, 0.001, 0.5, 2.0])

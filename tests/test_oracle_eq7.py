@@ -1,8 +1,11 @@
-"""Pins of the oracle's Eq. 7 (full temporal bias) pieces, CPU only: the cube root against libm,
+"""Pins of the oracle's Eq. 7 (full temporal bias) pieces, CPU only: the cube root against a
+high-precision decimal cube root,
 Lab and CIE94 against a binary64 evaluation of the published definitions and their closed-form
 special cases, and the whole update against Eq. 6 where dL vanishes and against "always replace"
 where it saturates."""
 from __future__ import annotations
+
+from decimal import Decimal, localcontext
 
 import numpy as np
 import pytest
@@ -33,22 +36,51 @@ def de94_64(ref, x):
     return np.sqrt(dL ** 2 + (dC / (1 + 0.045 * c1)) ** 2 + dH2 / (1 + 0.015 * c1) ** 2)
 
 
-def test_cbrt_against_libm(oracle_mod):
-    a = np.array([216.0 / 24389.0], np.float32).view(np.uint32)[0]
-    b = np.array([2.0], np.float32).view(np.uint32)[0]
-    t = np.arange(a, b, 7, dtype=np.uint32).view(np.float32)
-    got = oracle_mod.cbrt(t).astype(np.float64)
-    want = np.cbrt(t.astype(np.float64))
-    ulp = np.ldexp(1.0, np.floor(np.log2(want)).astype(np.int64) - 23)
-    assert (np.abs(got - want) / ulp).max() <= 1.0
-    assert oracle_mod.cbrt(np.array([1.0, 0.125, 8.0], np.float32)).tolist() == [1.0, 0.5, 2.0]
-    # HDR inputs and far beyond: every 997th binary32 in [2, 2^40)
-    c = np.array([2.0, 2.0 ** 40], np.float32).view(np.uint32)
-    t = np.arange(c[0], c[1], 997, dtype=np.uint32).view(np.float32)
-    got = oracle_mod.cbrt(t).astype(np.float64)
-    want = np.cbrt(t.astype(np.float64))
-    ulp = np.ldexp(1.0, np.floor(np.log2(want)).astype(np.int64) - 23)
-    assert (np.abs(got - want) / ulp).max() <= 1.0
+def _nearest_f32(exact, guess):
+    """The binary32 nearest to the Decimal `exact`, among `guess` and its two neighbours."""
+    cands = [np.nextafter(guess, np.float32(-np.inf)), guess, np.nextafter(guess, np.float32(np.inf))]
+    return min(cands, key=lambda c: abs(Decimal(float(c)) - exact))
+
+
+def _cbrt_decimal(t):
+    """t^(1/3) to 60 significant digits (Decimal ln and exp are correctly rounded)."""
+    with localcontext() as ctx:
+        ctx.prec = 60
+        return (Decimal(float(t)).ln() / 3).exp()
+
+
+def test_cbrt_is_the_nearest_binary32(oracle_mod):
+    """The oracle's cube root is the binary32 nearest to the real cube root: checked against a
+    60-digit decimal cube root on random inputs over the Lab range and far beyond, and on the
+    inputs whose cube roots lie closest to a binary32 midpoint (found from binary64 cube roots);
+    exact on perfect cubes; monotone and within one ulp of libm on a dense grid."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    lo = np.array([216.0 / 24389.0], np.float32).view(np.uint32)[0]
+    hi = np.array([2.0 ** 40], np.float32).view(np.uint32)[0]
+    bits = rng.integers(lo, hi, 1500, dtype=np.uint32)
+    # hard cases: binary64 cube roots nearest to a binary32 midpoint, from 4M inputs
+    grid = rng.integers(lo, np.array([256.0], np.float32).view(np.uint32)[0], 4_000_000, dtype=np.uint32)
+    y = np.cbrt(grid.view(np.float32).astype(np.float64))
+    ulp = np.ldexp(1.0, np.floor(np.log2(y)).astype(np.int64) - 23)
+    frac = (y / ulp) % 1.0
+    hard = grid[np.argsort(np.abs(frac - 0.5))[:300]]
+    t = np.concatenate([bits, hard]).view(np.float32)
+    got = oracle_mod.cbrt(t)
+    for ti, gi in zip(t, got):
+        want = _nearest_f32(_cbrt_decimal(ti), np.float32(np.cbrt(np.float64(ti))))
+        assert gi == want, f"cbrt({float(ti)!r}) = {float(gi)!r}, nearest binary32 is {float(want)!r}"
+    # perfect cubes: (a 2^j)^3 for 8-bit a is a binary32 and its cube root is exact
+    a = np.arange(1, 256, dtype=np.float64)
+    for j in (-20, -3, 0, 5, 11):
+        r = a * 2.0 ** j
+        assert np.array_equal(oracle_mod.cbrt((r ** 3).astype(np.float32)), r.astype(np.float32))
+    # dense grid: monotone non-decreasing and within one ulp of binary64 libm
+    g = np.arange(lo, np.array([2.0], np.float32).view(np.uint32)[0], 7, dtype=np.uint32).view(np.float32)
+    c = oracle_mod.cbrt(g).astype(np.float64)
+    assert np.all(np.diff(c) >= 0.0)
+    want = np.cbrt(g.astype(np.float64))
+    assert (np.abs(c - want) / np.ldexp(1.0, np.floor(np.log2(want)).astype(np.int64) - 23)).max() <= 0.5 + 1e-9
+    assert oracle_mod.cbrt(np.array([0.0, np.inf, -8.0], np.float32)).tolist() == [0.0, np.inf, -2.0]
 
 
 def test_lab_special_cases(oracle_mod):

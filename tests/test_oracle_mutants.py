@@ -50,8 +50,10 @@ MUTANTS = {
     "lab_lightness_offset": ("lab[0] = 116.0f * fy - 16.0f;", "lab[0] = 116.0f * fy - 15.0f;"),
     "lab_knee_ignored": ("if (t > eps) return fwrs_oracle_cbrt(t);", "if (t > -1.0f) return fwrs_oracle_cbrt(t);"),
     "cie94_chroma_of_wrong_colour": ("float SC = 1.0f + 0.045f * C1;", "float SC = 1.0f + 0.045f * C2;"),
-    "cbrt_too_few_newton_steps": ("for (int it = 0; it < 2; ++it) {", "for (int it = 0; it < 1; ++it) {"),
-    "cbrt_final_step_dropped": ("    return y - c;\n}", "    return y + 0.0f * c;\n}"),
+    "cbrt_midpoint_is_lower_neighbour": ("const u128 m = 2 * M + 1;", "const u128 m = 2 * M - 1;"),
+    "cbrt_midpoint_exponent": ("return compare_scaled(m * m * m, 3 * (E - 1), T, Et);",
+                               "return compare_scaled(m * m * m, 3 * E - 1, T, Et);"),
+    "cbrt_single_precision_start": ("float y = (float)cbrt((double)t);", "float y = cbrtf(t) * (1.0f + 0x1p-22f);"),
     "xyz_matrix_entry": ("0.3575761f * g", "0.3757561f * g"),
     "reproject_motion_sign": ("const float sx = ((float)x + 0.5f) - motion[2 * p + 0];",
                               "const float sx = ((float)x + 0.5f) + motion[2 * p + 0];"),
@@ -68,8 +70,10 @@ MUTANTS = {
                              "float kn = fwrs_oracle_log2u(words[j % 4]) * w;"),
     "aes_empty_key_zero": ("return o->prm.bias_mode == FWRS_ORACLE_AES ? -INFINITY : 0.0f;",
                            "return o->prm.bias_mode == FWRS_ORACLE_AES ? 0.0f : 0.0f;"),
-    "log2_series_coefficient": ("p = p * z + 0x1.ec709ep-1f;", "p = p * z + 0x1.ec709ep-2f;"),
-    "log2_range_reduction_exponent": ("        e = e + 1;\n", "        e = e + 0;\n"),
+    "log2_variate_offset": ("const uint32_t m = (bits >> 8) + 1u;                 /* 1 .. 2^24 */",
+                            "const uint32_t m = (bits >> 8) + 0u;                 /* 1 .. 2^24 */"),
+    "log2_scale": ("log2l((long double)m) - 24.0L;", "log2l((long double)m) - 23.0L;"),
+    "log2_truncated": ("    const float f = (float)v;\n", "    const float f = (float)(double)(float)(v * (1.0L - 0x1p-30L));\n"),
     "memoryless_decay_twice": ("W1b = W1 * o->decay;", "W1b = (W1 * o->decay) * o->decay;"),
     "mip_divisor_fixed": ("= s / (float)n;", "= s / 4.0f;"),
     "bilinear_no_half_texel": ("* inv_scale - 0.5f;", "* inv_scale;"),
