@@ -90,6 +90,13 @@ extern "C" {
 /* The context follows a moving camera (Sec. 4.3): it keeps two banks of the
  * store and is updated only by fwrs_push_frame_reproject. */
 #define FWRS_FLAG_REPROJECT 1u
+/* The context keeps no resolve plane (12 bytes per pixel less).  By default a
+ * context whose bias mode keeps one w_sum per pixel (NONE, BERNOULLI,
+ * MEMORYLESS) also stores every pixel's resolve as of the last frame that
+ * replaced one of its slots; a fused update + resolve then copies the
+ * unchanged resolve of a pixel without a replacement instead of re-reading
+ * its k slot records.  Results are identical either way. */
+#define FWRS_FLAG_NO_RESOLVE_PLANE 2u
 
 /* Method parameters.
  *   seed, stream_id   Philox key words.
@@ -132,6 +139,11 @@ typedef struct fwrs_ctx fwrs_ctx;
  *   rec[(p*k + j)*4 + 1..3]  float32  its colour (r, g, b)
  *   idx[p*k + j]             uint32   frame index of slot j's sample
  *                                     (0xFFFFFFFF while empty)
+ *   res[p*3 + c]             float32  the pixel's resolve (channel c), where
+ *                                     the context keeps the resolve plane and
+ *                                     it is current; NULL otherwise (before
+ *                                     the frames that use it, after
+ *                                     fwrs_push_frame or an incremental frame)
  * A pixel's k slots are one contiguous 16k-byte record, so a replacement
  * touches only that pixel's record.  `pitch` (>= N, a multiple of 64) times
  * `wsum_slots` is the element count reserved for the wsum plane.  Alg. 2's candidate count m is
@@ -154,6 +166,7 @@ typedef struct fwrs_state_view {
     int wsum_slots;         /* 1, or k under FWRS_BIAS_FULL and FWRS_AES */
     uint32_t* cnt;
     float* depth;
+    float* res;
 } fwrs_state_view;
 
 /* Fills `p` with the defaults for an image `width` pixels wide: seed 0,
@@ -162,16 +175,19 @@ typedef struct fwrs_state_view {
 int fwrs_default_params(int width, fwrs_params* p);
 
 /* Device bytes of the reservoir store for a width x height image with k
- * slots under FWRS_BIAS_NONE or FWRS_BIAS_BERNOULLI: 4 * pitch * (1 + 5k)
- * plus a small statistics area, where pitch is width * height rounded up to
- * 64 (20 bytes per slot and 4 per pixel).  Use it for admission control and
- * to size a caller-provided arena.  Returns 0 for invalid sizes. */
+ * slots under the default parameters (FWRS_BIAS_BERNOULLI, with the resolve
+ * plane): 4 * pitch * (1 + 5k + 3) plus a small statistics area, where pitch
+ * is width * height rounded up to 64 (20 bytes per slot, 4 for w_sum and 12
+ * for the resolve plane per pixel).  Use it for admission control and to size
+ * a caller-provided arena.  Returns 0 for invalid sizes. */
 size_t fwrs_state_bytes(int width, int height, int k);
 
 /* As fwrs_state_bytes for given parameters: FWRS_BIAS_FULL and FWRS_AES keep
- * one value per slot (4 * pitch * 6k), FWRS_FLAG_REPROJECT two banks, each with a
- * count and a depth per pixel (2 * 4 * pitch * (s + 5k + 2), s = 1 or k),
- * plus the statistics area.  Returns 0 for invalid sizes or parameters. */
+ * one value per slot and no resolve plane (4 * pitch * 6k),
+ * FWRS_FLAG_NO_RESOLVE_PLANE drops the plane (4 * pitch * (1 + 5k)),
+ * FWRS_FLAG_REPROJECT keeps two banks, each with a count and a depth per pixel
+ * and no plane (2 * 4 * pitch * (s + 5k + 2), s = 1 or k), plus the
+ * statistics area.  Returns 0 for invalid sizes or parameters. */
 size_t fwrs_state_bytes_params(int width, int height, int k, const fwrs_params* params);
 
 /* Host bytes written by fwrs_download_state: width * height * (8 + 24k). */
@@ -287,6 +303,16 @@ int fwrs_download_state(fwrs_ctx* ctx, void* host, size_t host_bytes);
  * history was flushed.  Any pointer may be NULL. */
 int fwrs_get_stats(fwrs_ctx* ctx, uint64_t* slot_takes, uint64_t* pixels_changed, uint64_t* pixel_updates,
                    uint64_t* pixels_flushed);
+
+/* The frame index from which the context's fused passes (fwrs_push_frame_resolve,
+ * batched ticks, fwrs_push_frame_foveated with an output) use the resolve
+ * plane: the pass at frame index frame_index - 1 writes it for every pixel, and
+ * the later passes read a pixel's slot records only where a slot was replaced
+ * (default 8: while a store fills after a reset most pixels change every
+ * frame).  0 uses it from the first frame.  A launch policy: results are
+ * identical for every value.  FWRS_E_STATE if the context keeps no resolve
+ * plane (FWRS_FLAG_NO_RESOLVE_PLANE, FWRS_BIAS_FULL, FWRS_AES, reprojecting). */
+int fwrs_set_resolve_plane_from(fwrs_ctx* ctx, uint32_t frame_index);
 
 /* Selects the thread-block tile: tile_x pixels by tile_y rows (one thread per
  * pixel), tile_x * tile_y in {64, 128, 256}, both powers of two.  It only

@@ -1,8 +1,7 @@
 // C ABI of the weighted-reservoir-sampling library (include/fwrs.h):
-// contexts with a structure-of-arrays reservoir store in HBM, argument
-// validation, single-frame launches on a borrowed stream, state access, and
-// the batched tick engine (persistent kernel, optionally replayed as a HIP
-// graph).
+// contexts with their reservoir store in HBM (per-pixel slot records, frame
+// indices, w_sum and the resolve plane), argument validation, single-frame
+// launches on a borrowed stream, state access, and the batched tick engine.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -23,6 +22,17 @@ namespace {
 constexpr size_t kPitchAlign = 64;   // elements; planes start on 256-byte boundaries
 constexpr size_t kStatBytes = 3 * sizeof(unsigned long long) * fwrs::kStatSlots;
 constexpr int kDefaultTileX = 64, kDefaultTileY = 1;
+
+// Frames of a context before its fused passes use the resolve plane.  While a
+// store fills (the first frames after a reset), most pixels replace a slot every
+// frame, so copying unchanged resolves from the plane saves little and keeping
+// the plane costs a write per changed pixel; the frame before this one writes the
+// plane densely (kOpFill) and later frames use it (kOpCached).  A launch-policy
+// constant: it never changes results.
+#ifndef FWRS_RES_FROM
+#define FWRS_RES_FROM 8
+#endif
+constexpr uint32_t kResFrom = FWRS_RES_FROM;
 
 size_t pitch_for(int width, int height)
 {
@@ -46,17 +56,26 @@ bool params_ok(const fwrs_params* p)
     if (p->bias_mode > FWRS_AES) return false;
     if (!std::isfinite(p->lambda_decay) || p->lambda_decay < 0.0f) return false;
     if (!(p->a_k > 0.0f && p->a_k <= 1.0f)) return false;
-    if ((p->flags & ~(uint32_t)FWRS_FLAG_REPROJECT) != 0u) return false;
+    if ((p->flags & ~(uint32_t)(FWRS_FLAG_REPROJECT | FWRS_FLAG_NO_RESOLVE_PLANE)) != 0u) return false;
     return finite_pos(p->r_m) && finite_pos(p->r2k) && finite_pos(p->rek);
 }
 
+// Whether a context keeps the resolve plane: every mode with one w_sum per
+// pixel, unless the caller opted out; not the per-slot modes (Eq. 7 reads every
+// slot's colour each frame anyway) nor reprojecting contexts (dense passes).
+bool keeps_res(uint32_t bias_mode, uint32_t flags)
+{
+    return !fwrs::per_slot_mode(bias_mode) && (flags & (FWRS_FLAG_REPROJECT | FWRS_FLAG_NO_RESOLVE_PLANE)) == 0u;
+}
+
 // Elements (4 bytes) of one bank of the store: w_sum (one per pixel, or one per
-// slot under Eq. 7), the slot records, the slot frame indices, and for a
-// reprojecting context the pixel counts and depths.
+// slot under Eq. 7), the slot records, the slot frame indices, the resolve
+// plane (3 per pixel) where kept, and for a reprojecting context the pixel
+// counts and depths.
 size_t bank_elems(size_t pitch, size_t k, uint32_t bias_mode, uint32_t flags)
 {
     const size_t ws = fwrs::per_slot_mode(bias_mode) ? k : 1;
-    const size_t extra = (flags & FWRS_FLAG_REPROJECT) ? 2 : 0;
+    const size_t extra = (flags & FWRS_FLAG_REPROJECT) ? 2 : (keeps_res(bias_mode, flags) ? 3 : 0);
     return pitch * (ws + 5 * k + extra);
 }
 
@@ -147,6 +166,11 @@ struct fwrs_ctx {
     uint32_t* bank_idx[2] = {nullptr, nullptr};
     uint32_t* bank_cnt[2] = {nullptr, nullptr};
     float* bank_depth[2] = {nullptr, nullptr};
+    // the resolve plane (null if not kept) and whether it holds every pixel's
+    // current resolve
+    float* res = nullptr;
+    bool res_valid = false;
+    uint32_t res_from = kResFrom;    // first frame index whose fused pass may use the plane
     unsigned long long* stats = nullptr;
     uint32_t t = 0;
     uint64_t pixel_updates = 0;
@@ -173,6 +197,10 @@ int clear_store(fwrs_ctx* x)
         fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->rec), P * 4 * k, 0u, x->stream) != hipSuccess)
         return FWRS_E_HIP;
     if (fwrs::launch_fill_u32(x->idx, P * k, 0xFFFFFFFFu, x->stream) != hipSuccess) return FWRS_E_HIP;
+    // the resolve of an empty reservoir is 0
+    if (x->res && fwrs::launch_fill_u32(reinterpret_cast<uint32_t*>(x->res), P * 3, 0u, x->stream) != hipSuccess)
+        return FWRS_E_HIP;
+    x->res_valid = x->res != nullptr;
     if (x->reproject) {
         // counts 0; depths NaN: no previous frame, so the first reprojected frame flushes
         if (fwrs::launch_fill_u32(x->bank_cnt[x->cur], P, 0u, x->stream) != hipSuccess ||
@@ -211,6 +239,7 @@ FrameDesc make_desc(const fwrs_ctx* x, const float* color, const uint8_t* level,
     d.wsum = x->wsum;
     d.rec = x->rec;
     d.idx = x->idx;
+    d.res = x->res;
     d.stats = x->stats;
     d.width = (uint32_t)x->width;
     d.height = (uint32_t)x->height;
@@ -228,23 +257,43 @@ FrameDesc make_desc(const fwrs_ctx* x, const float* color, const uint8_t* level,
 
 bool gaze_ok(float gx, float gy) { return std::isfinite(gx) && std::isfinite(gy); }
 
-int run_frame(fwrs_ctx* x, const float* color, const uint8_t* level, float gx, float gy, float* out, int op)
+// The kernel op of a fused frame (update + resolve of every pixel) of context x
+// at its current frame index: from the resolve plane once it is valid and the
+// store is past its filling frames, filling the plane on the frame before.
+int fused_op(const fwrs_ctx* x)
 {
-    DeviceGuard g(x->device);
-    if (!g.ok) return FWRS_E_HIP;
-    FrameDesc d = make_desc(x, color, level, gx, gy, out, x->tile_x, x->tile_y);
-    if (fwrs::launch_frame(d, op, x->stream) != hipSuccess) return FWRS_E_HIP;
-    if (op & 1) {
+    if (!x->res) return fwrs::kOpFused;
+    if (x->res_valid && x->t >= x->res_from) return fwrs::kOpCached;
+    return x->t + 1u >= x->res_from ? fwrs::kOpFill : fwrs::kOpFused;
+}
+
+// After a successful launch of `op` on x: the frame count, the record of the
+// last resolve target and the validity of the resolve plane.
+void advance(fwrs_ctx* x, int op, const float* out)
+{
+    if (op != fwrs::kOpResolve) {
         x->t += 1u;
         x->pixel_updates += (uint64_t)x->width * (uint64_t)x->height;
+        // kOpPush, kOpFused and kOpIncremental change records without the plane
+        x->res_valid = op == fwrs::kOpCached || op == fwrs::kOpFill;
     }
-    if (op == 2 || op == 3 || op == 5) {   // every op that leaves `out` holding the resolve
+    if (op != fwrs::kOpPush && out) {   // every op that leaves `out` holding the resolve
         x->resolved_out = out;
         x->resolved_at = x->t;
         x->resolved = true;
     } else {
         x->resolved = false;
     }
+}
+
+int run_frame(fwrs_ctx* x, const float* color, const uint8_t* level, float gx, float gy, float* out, int op)
+{
+    DeviceGuard g(x->device);
+    if (!g.ok) return FWRS_E_HIP;
+    if (op == fwrs::kOpFused) op = fused_op(x);
+    FrameDesc d = make_desc(x, color, level, gx, gy, out, x->tile_x, x->tile_y);
+    if (fwrs::launch_frame(d, op, x->stream) != hipSuccess) return FWRS_E_HIP;
+    advance(x, op, out);
     return FWRS_OK;
 }
 
@@ -327,6 +376,7 @@ int fwrs_create_ex(int width, int height, int k, const fwrs_params* params, void
         x->bank_wsum[b] = B;
         x->bank_rec[b] = B + ws * P;
         x->bank_idx[b] = reinterpret_cast<uint32_t*>(B + (ws + 4 * kk) * P);
+        if (keeps_res(params->bias_mode, params->flags)) x->res = B + (ws + 5 * kk) * P;
         if (x->reproject) {
             x->bank_cnt[b] = reinterpret_cast<uint32_t*>(B + (ws + 5 * kk) * P);
             x->bank_depth[b] = B + (ws + 5 * kk + 1) * P;
@@ -391,13 +441,13 @@ int fwrs_push_frame(fwrs_ctx* x, const float* color, const uint8_t* level_map, f
 {
     if (!x || !color || !level_map || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
     if (x->t == 0xFFFFFFFFu || x->reproject) return FWRS_E_STATE;
-    return run_frame(x, color, level_map, gaze_x, gaze_y, nullptr, 1);
+    return run_frame(x, color, level_map, gaze_x, gaze_y, nullptr, fwrs::kOpPush);
 }
 
 int fwrs_resolve(fwrs_ctx* x, float* out)
 {
     if (!x || !out) return FWRS_E_ARG;
-    return run_frame(x, nullptr, nullptr, 0.0f, 0.0f, out, 2);
+    return run_frame(x, nullptr, nullptr, 0.0f, 0.0f, out, fwrs::kOpResolve);
 }
 
 int fwrs_push_frame_resolve(fwrs_ctx* x, const float* color, const uint8_t* level_map, float gaze_x, float gaze_y,
@@ -405,7 +455,7 @@ int fwrs_push_frame_resolve(fwrs_ctx* x, const float* color, const uint8_t* leve
 {
     if (!x || !color || !level_map || !out || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
     if (x->t == 0xFFFFFFFFu || x->reproject) return FWRS_E_STATE;
-    return run_frame(x, color, level_map, gaze_x, gaze_y, out, 3);
+    return run_frame(x, color, level_map, gaze_x, gaze_y, out, fwrs::kOpFused);
 }
 
 int fwrs_push_frame_resolve_incremental(fwrs_ctx* x, const float* color, const uint8_t* level_map, float gaze_x,
@@ -414,7 +464,7 @@ int fwrs_push_frame_resolve_incremental(fwrs_ctx* x, const float* color, const u
     if (!x || !color || !level_map || !out || !gaze_ok(gaze_x, gaze_y)) return FWRS_E_ARG;
     if (x->t == 0xFFFFFFFFu || x->reproject) return FWRS_E_STATE;
     if (!x->resolved || x->resolved_out != out || x->resolved_at != x->t) return FWRS_E_STATE;
-    return run_frame(x, color, level_map, gaze_x, gaze_y, out, 5);
+    return run_frame(x, color, level_map, gaze_x, gaze_y, out, fwrs::kOpIncremental);
 }
 
 int fwrs_push_frame_reproject(fwrs_ctx* x, const float* color, const uint8_t* level_map, const float* motion,
@@ -473,6 +523,7 @@ int fwrs_get_state(const fwrs_ctx* x, fwrs_state_view* v)
     v->wsum = x->wsum;
     v->rec = x->rec;
     v->idx = x->idx;
+    v->res = x->res_valid ? x->res : nullptr;
     return FWRS_OK;
 }
 
@@ -552,6 +603,14 @@ int fwrs_get_stats(fwrs_ctx* x, uint64_t* slot_takes, uint64_t* pixels_changed, 
     if (pixels_changed) *pixels_changed = changed;
     if (pixel_updates) *pixel_updates = x->pixel_updates;
     if (pixels_flushed) *pixels_flushed = flushed;
+    return FWRS_OK;
+}
+
+int fwrs_set_resolve_plane_from(fwrs_ctx* x, uint32_t frame_index)
+{
+    if (!x) return FWRS_E_ARG;
+    if (!x->res) return FWRS_E_STATE;
+    x->res_from = frame_index;
     return FWRS_OK;
 }
 
@@ -753,6 +812,7 @@ int fwrs_engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n)
             int tx, ty;
             engine_tile(e, (long long)f.ctx->width * f.ctx->height, tx, ty);
             a.descs[a.n] = make_desc(f.ctx, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, tx, ty);
+            a.descs[a.n].op = (uint32_t)fused_op(f.ctx);
             a.begins[a.n] = a.total;
             a.total += a.descs[a.n].items;
             ++a.n;
@@ -785,13 +845,12 @@ int fwrs_engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n)
         return FWRS_E_HIP;
     }
     e->ticks += 1u;
-    for (int i = 0; i < n; ++i) {
-        fwrs_ctx* c = frames[i].ctx;
-        c->t += 1u;
-        c->pixel_updates += (uint64_t)c->width * (uint64_t)c->height;
-        c->resolved_out = frames[i].out;
-        c->resolved_at = c->t;
-        c->resolved = true;
+    for (int c = 0; c < m; ++c) {
+        const int chunk = reverse ? m - 1 - c : c;
+        for (uint32_t i = 0; i < e->args[c].n; ++i) {
+            const fwrs_frame& f = frames[chunk * fwrs::kTickFrames + (int)i];
+            advance(f.ctx, (int)e->args[c].descs[i].op, f.out);
+        }
     }
     // ... and its later work (and fwrs_destroy) waits for this tick
     if (foreign) {
@@ -965,16 +1024,9 @@ int fwrs_push_frame_foveated(fwrs_ctx* x, fwrs_foveator* f, const float* full, f
     fd.s = build_levels(f, full, gaze_x, gaze_y, x->stream, err);
     if (err != hipSuccess) return FWRS_E_HIP;
     fd.f = make_desc(x, nullptr, nullptr, gaze_x, gaze_y, out, x->tile_x, x->tile_y);
-    if (fwrs::launch_foveated(fd, out != nullptr, x->stream) != hipSuccess) return FWRS_E_HIP;
-    x->t += 1u;
-    x->pixel_updates += (uint64_t)x->width * (uint64_t)x->height;
-    if (out) {
-        x->resolved_out = out;
-        x->resolved_at = x->t;
-        x->resolved = true;
-    } else {
-        x->resolved = false;
-    }
+    const int op = out ? fused_op(x) : fwrs::kOpPush;
+    if (fwrs::launch_foveated(fd, op, x->stream) != hipSuccess) return FWRS_E_HIP;
+    advance(x, op, out);
     if (order_after(f->stream, x->stream, x->order_ev) != hipSuccess) return FWRS_E_HIP;
     return FWRS_OK;
 }

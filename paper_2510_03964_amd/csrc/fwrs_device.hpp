@@ -36,11 +36,13 @@ struct alignas(8) FrameDesc {
     float* wsum;                // [N] w_sum per pixel; [N][k] per slot under Eq. 7
     float* rec;                 // [N][k][4] slot records {w, r, g, b}
     uint32_t* idx;              // [N][k] frame index of each slot's sample
+    float* res;                 // [N][3] each pixel's resolve as of its last change (resolve plane), or null
     unsigned long long* stats;  // [kStatSlots][3] counters (slots replaced, pixels changed, flushed), or null
     uint32_t width, height, t, k;
     float gx, gy;
     Consts c;
     uint32_t seed, stream_id, bias;
+    uint32_t op;                // what the batched kernel runs for this frame (an Op of the kernels)
     uint32_t tile_x_log2, tile_y_log2, tiles_x, items;  // launch geometry
 };
 
@@ -203,27 +205,37 @@ __device__ __forceinline__ float bias_shared(float W1, float w, uint32_t mode, f
     return mode == kBiasBernoulli ? W1 * survive : W1;
 }
 
-// log2 of the variate ((bits >> 8) + 1) 2^-24 for A-ES keys: m = (bits >> 8) + 1
-// = 2^e f with f in [sqrt(1/2), sqrt(2)); log2 f = (2 / ln 2) atanh(s),
-// s = (f - 1) / (f + 1), as the odd series to s^11 (|s| < 0.172).
-__device__ __forceinline__ float log2_unit(uint32_t bits)
+// log2 of the variate ((bits >> 8) + 1) 2^-24 for A-ES keys, correctly rounded to
+// binary32.  m = (bits >> 8) + 1 = 2^e f with f in [sqrt(1/2), sqrt(2)):
+// log2 u = (e - 24) + log2 f and log2 f = (2 / ln 2) atanh(s), s = (f - 1) / (f + 1),
+// |s| < 0.172, summed as the odd series to s^21 in binary64 (truncation below
+// 2^-60 relative); the binary64 value is then rounded once to binary32.  That
+// this is the nearest binary32 for every one of the 2^24 variates is checked
+// exhaustively on the host.
+__host__ __device__ __forceinline__ float log2_unit(uint32_t bits)
 {
     const uint32_t m = (bits >> 8) + 1u;
-    int e = 31 - __clz(m);
-    float f = ldexpf((float)m, -e);              // exact, [1, 2)
-    if (f >= 0x1.6a09e6p+0f) {
-        f = f * 0.5f;
+    int e = 31 - __builtin_clz(m);
+    double f = ldexp((double)m, -e);                 // exact, [1, 2)
+    if (f >= 1.4142135623730951) {
+        f = f * 0.5;
         e = e + 1;
     }
-    const float s = (f - 1.0f) / (f + 1.0f);
-    const float z = s * s;
-    float p = 0x1.0c9a84p-2f;                    // 2 / (11 ln 2)
-    p = p * z + 0x1.484b14p-2f;                  // 2 / (9 ln 2)
-    p = p * z + 0x1.a61762p-2f;                  // 2 / (7 ln 2)
-    p = p * z + 0x1.2776c6p-1f;                  // 2 / (5 ln 2)
-    p = p * z + 0x1.ec709ep-1f;                  // 2 / (3 ln 2)
-    p = p * z + 0x1.715476p+1f;                  // 2 / ln 2
-    return (float)(e - 24) + s * p;
+    const double s = (f - 1.0) / (f + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 21.0;
+    p = p * z + 1.0 / 19.0;
+    p = p * z + 1.0 / 17.0;
+    p = p * z + 1.0 / 15.0;
+    p = p * z + 1.0 / 13.0;
+    p = p * z + 1.0 / 11.0;
+    p = p * z + 1.0 / 9.0;
+    p = p * z + 1.0 / 7.0;
+    p = p * z + 1.0 / 5.0;
+    p = p * z + 1.0 / 3.0;
+    p = p * z + 1.0;
+    const double two_over_ln2 = 2.8853900817779268;   // 2 / ln 2
+    return (float)((double)(e - 24) + (two_over_ln2 * s) * p);
 }
 
 // ---------------------------------------------------------------------------
@@ -284,13 +296,31 @@ __device__ __forceinline__ float3 fov_colour(const FovSrc& s, uint32_t x, uint32
 // Lab (D65 white), then the CIE94 difference with graphic-arts weights and the
 // reservoir sample as the reference; |dL| = min(1, dE94 / 100).
 // ---------------------------------------------------------------------------
-// Cube root, t > 0, without division: reciprocal cube root r from an exponent-bit
+// Cube root of t > 0, correctly rounded to binary32.  An approximation y
+// without division comes first: the reciprocal cube root r from an exponent-bit
 // seed (bits(t^(-1/3)) ~ 4/3 * 127 * 2^23 - bits(t)/3), two Newton steps
 // r <- r (4 - t r^3) / 3, then y = t r^2 and one Newton step on y with r^2 for
-// 1 / y^2: y <- y - (y^3 - t) r^2 / 3.  1/3 is its binary32 rounding.
-__device__ __forceinline__ float cube_root(float t)
+// 1 / y^2: y <- y - (y^3 - t) r^2 / 3 (1/3 is its binary32 rounding).  y is
+// within one ulp of the cube root, so the nearest binary32 is y or a
+// neighbour: the real cube root lies above the midpoint m between y and the
+// binary32 above it iff m^3 < t, and below the midpoint under y iff t < m^3.
+// A midpoint has 25 significant bits, so m^2 is exact in binary64 and m^3 is
+// exactly hi + lo with hi = m^2 m rounded and lo = fma(m^2, m, -hi); hi is
+// within a few ulps of t, so t - hi is exact and t - m^3 has the sign of
+// (t - hi) - lo.  That the result is the nearest binary32 for every t in
+// [(6/29)^3, 2^8) and for samples beyond is checked exhaustively on the host.
+__host__ __device__ __forceinline__ bool cube_below(double m, double t)     // m^3 < t, exactly
 {
-    float r = __uint_as_float(0x54A2FA8Cu - __float_as_uint(t) / 3u);
+    const double m2 = m * m;
+    const double hi = m2 * m;
+    const double lo = fma(m2, m, -hi);
+    return (t - hi) > lo;
+}
+
+__host__ __device__ __forceinline__ float cube_root(float t)
+{
+    if (!(t < INFINITY)) return t;                   // +inf, NaN
+    float r = __builtin_bit_cast(float, 0x54A2FA8Cu - __builtin_bit_cast(uint32_t, t) / 3u);
     const float third = 0x1.555556p-2f;
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
@@ -300,10 +330,17 @@ __device__ __forceinline__ float cube_root(float t)
         r = (r * d) * third;
     }
     const float r2 = r * r;
-    const float y = t * r2;
-    const float y3 = (y * y) * y;
+    const float y0 = t * r2;
+    const float y3 = (y0 * y0) * y0;
     const float c = ((y3 - t) * r2) * third;
-    return y - c;
+    const float y = y0 - c;
+    const uint32_t yb = __builtin_bit_cast(uint32_t, y);
+    const float up = __builtin_bit_cast(float, yb + 1u);
+    const float dn = __builtin_bit_cast(float, yb - 1u);
+    const double td = (double)t;
+    if (cube_below(0.5 * ((double)y + (double)up), td)) return up;
+    if (!cube_below(0.5 * ((double)dn + (double)y), td)) return dn;
+    return y;
 }
 
 // x / c for a constant divisor c given rc = RN(1 / c): the product x rc corrected
@@ -311,7 +348,7 @@ __device__ __forceinline__ float cube_root(float t)
 // divisors below (0.95047, 1.08883, 100) this equals the correctly rounded x / c for
 // every binary32 x with 2^-100 <= |x| <= 2^126 (checked exhaustively); other x
 // take the division, so the result is always the correctly rounded quotient.
-__device__ __forceinline__ float div_const(float x, float c, float rc)
+__host__ __device__ __forceinline__ float div_const(float x, float c, float rc)
 {
     const float ax = fabsf(x);
     if (ax >= 0x1p-100f && ax <= 0x1p126f) {
@@ -322,14 +359,14 @@ __device__ __forceinline__ float div_const(float x, float c, float rc)
     return x / c;
 }
 
-__device__ __forceinline__ float lab_curve(float t)
+__host__ __device__ __forceinline__ float lab_curve(float t)
 {
     // t^(1/3) above (6/29)^3, the linear segment t / (3 (6/29)^2) + 4/29 below
     const float lin = t * (841.0f / 108.0f) + 4.0f / 29.0f;
     return t > 216.0f / 24389.0f ? cube_root(t) : lin;
 }
 
-__device__ __forceinline__ float3 rgb_to_lab(float r, float g, float b)
+__host__ __device__ __forceinline__ float3 rgb_to_lab(float r, float g, float b)
 {
     const float X = (0.4124564f * r + 0.3575761f * g) + 0.1804375f * b;
     const float Y = (0.2126729f * r + 0.7151522f * g) + 0.0721750f * b;
@@ -340,7 +377,7 @@ __device__ __forceinline__ float3 rgb_to_lab(float r, float g, float b)
     return make_float3(116.0f * fy - 16.0f, 500.0f * (fx - fy), 200.0f * (fy - fz));
 }
 
-__device__ __forceinline__ float cie94(const float3& ref, const float3& x)
+__host__ __device__ __forceinline__ float cie94(const float3& ref, const float3& x)
 {
     const float dL = ref.x - x.x;
     const float C1 = sqrtf(ref.y * ref.y + ref.z * ref.z);

@@ -15,8 +15,13 @@ constexpr int kGaussR1 = 3;             // ceil(3 sigma) of the Gaussian levels,
 constexpr int kGaussR2 = 6;
 constexpr int kGaussCols = 64;          // columns (threads) per block of the Gaussian level kernel
 
-// op: 1 = update only, 2 = resolve only, 3 = update + resolve,
-// 5 = update + resolve of the changed pixels only.
+// The kernels' ops (the launchers take them as int).
+constexpr int kOpPush = 1;          // update only
+constexpr int kOpResolve = 2;       // resolve only
+constexpr int kOpFused = 3;         // update + resolve of every pixel from its slots
+constexpr int kOpIncremental = 5;   // update + resolve of the changed pixels only
+constexpr int kOpCached = 7;        // update + resolve, unchanged pixels from the resolve plane
+constexpr int kOpFill = 9;          // kOpFused that also writes the resolve plane
 hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream);
 
 // Arguments of one batched launch: n frames, `total` work items, frame f owns
@@ -44,7 +49,7 @@ hipError_t launch_gauss_levels(const float* full, float* dst, uint32_t w, uint32
                                float r1sq, const float* g1, const float* g2, hipStream_t stream);
 hipError_t launch_foveate(const FovSrc& s, float* color, uint8_t* level, uint32_t w, uint32_t h, float gx, float gy,
                           hipStream_t stream);
-hipError_t launch_foveated(const FovDesc& fd, bool resolve, hipStream_t stream);
+hipError_t launch_foveated(const FovDesc& fd, int op, hipStream_t stream);
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t stream);
 

@@ -31,36 +31,63 @@
 // Which streams use non-temporal loads / stores (bits, see kNt* below); a
 // launch-shape tuning constant that never changes results.
 #ifndef FWRS_NT_MASK
-#define FWRS_NT_MASK 0xC7u
+#define FWRS_NT_MASK 0x3C7u
 #endif
 
 namespace fwrs {
 
 // kPush: update only; kResolve: resolve only; kFused: update + resolve of every
-// pixel; kIncremental: update + resolve of the pixels whose record changed
-// (the output already holds the previous frame's resolve everywhere else).
-enum Op : int { kPush = 1, kResolve = 2, kFused = 3, kIncremental = 5 };
+// pixel from its slots; kIncremental: update + resolve of the pixels whose record
+// changed (the output already holds the previous frame's resolve everywhere
+// else); kCached: update + resolve of every pixel, where a pixel without a
+// replacement copies its resolve from the store's resolve plane (which holds it
+// unchanged since the pixel last changed) and a changed pixel recomputes it and
+// refreshes the plane; kFill: kFused that also writes every pixel's resolve into
+// the plane, making it valid for the kCached frames that follow.
+enum Op : int {
+    kPush = kOpPush, kResolve = kOpResolve, kFused = kOpFused, kIncremental = kOpIncremental, kCached = kOpCached,
+    kFill = kOpFill,
+};
 
 enum : uint32_t {
     kNtLevel = 1u, kNtWsumLd = 2u, kNtWsumSt = 4u, kNtRecLd = 8u, kNtRecSt = 16u, kNtIdxSt = 32u,
-    kNtColor = 64u, kNtOut = 128u,
+    kNtColor = 64u, kNtOut = 128u, kNtResLd = 256u, kNtResSt = 512u,
 };
 constexpr uint32_t kNt = FWRS_NT_MASK;
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+// Every access of the pass goes through these helpers, which address global
+// memory explicitly: a descriptor read from a table in device memory (the
+// batched kernel) yields generic pointers, which would otherwise compile to
+// flat instructions.
+#define FWRS_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ const FWRS_GLOBAL T* gbl(const T* p)
+{
+    return (const FWRS_GLOBAL T*)p;
+}
+
+template <typename T>
+__device__ __forceinline__ FWRS_GLOBAL T* gbl(T* p)
+{
+    return (FWRS_GLOBAL T*)p;
+}
 
 template <uint32_t BIT, typename T>
 __device__ __forceinline__ T ld(const T* p)
 {
-    if constexpr ((kNt & BIT) != 0u) return __builtin_nontemporal_load(p);
-    return *p;
+    if constexpr ((kNt & BIT) != 0u) return __builtin_nontemporal_load(gbl(p));
+    return *gbl(p);
 }
 
 template <uint32_t BIT, typename T>
 __device__ __forceinline__ void st(T* p, T v)
 {
-    if constexpr ((kNt & BIT) != 0u) __builtin_nontemporal_store(v, p);
-    else *p = v;
+    if constexpr ((kNt & BIT) != 0u) __builtin_nontemporal_store(v, gbl(p));
+    else *gbl(p) = v;
 }
 
 template <uint32_t BIT>
@@ -73,7 +100,6 @@ __device__ __forceinline__ float4 ld4(const float4* p)
 template <uint32_t BIT>
 __device__ __forceinline__ float2 ld2(const float* p)
 {
-    typedef float v2f __attribute__((ext_vector_type(2)));
     const v2f v = ld<BIT>(reinterpret_cast<const v2f*>(p));
     return make_float2(v.x, v.y);
 }
@@ -138,6 +164,13 @@ __device__ __forceinline__ uint32_t decide_any(const FrameDesc& d, uint32_t p, f
     return mask;
 }
 
+// Whether the resolve plane is read before the decision (with the pixel's other
+// loads, so an unchanged pixel has it at hand) or only by unchanged pixels
+// after it; a scheduling choice that never changes results.
+#ifndef FWRS_RES_EARLY
+#define FWRS_RES_EARLY 1
+#endif
+
 // ---------------------------------------------------------------------------
 // One pixel.  K > 0 keeps the pixel's whole record in registers; K == 0
 // (any slot count up to kMaxK) streams the record one slot at a time.
@@ -148,11 +181,20 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
 {
     const uint32_t p = y * d.width + x;
     const int kk = K ? K : (int)d.k;
-    constexpr bool kUpdates = OP == kPush || OP == kFused || OP == kIncremental;
-    constexpr bool kResolves = OP == kResolve || OP == kFused || OP == kIncremental;
+    constexpr int R = K ? K : 1;
+    constexpr bool kUpdates = OP != kResolve;
+    constexpr bool kResolves = OP != kPush;
+    // every slot's record is read before the decision: the resolve needs them all
+    constexpr bool kEager = OP == kFused || OP == kFill || OP == kResolve;
+    // a recomputed resolve is also written to the resolve plane
+    constexpr bool kKeepsRes = OP == kCached || OP == kFill;
+    constexpr bool kResEarly = OP == kCached && FWRS_RES_EARLY;
     float4* rec = reinterpret_cast<float4*>(d.rec) + (size_t)p * (size_t)kk;
     uint32_t* idx = d.idx + (size_t)p * (size_t)kk;
     const float* color = d.color + 3 * (size_t)p;
+    float* res = d.res + 3 * (size_t)p;
+    // Frame 0 of a context meets the empty store (every slot zero): nothing to read.
+    const bool empty = d.t == 0u;
 
     // 1. every load that does not depend on this frame's decisions (the compiler's
     //    own schedule interleaves them with step 2; forcing all of them ahead of
@@ -164,17 +206,25 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
         else lv = ld<kNtLevel>(d.level + p);
         W1 = ld<kNtWsumLd>(d.wsum + p);
     }
-    float4 r[K ? K : 1];
-    if (K && (OP == kFused || OP == kResolve)) {
+    float4 r[R];
 #pragma unroll
-        for (int j = 0; j < (K ? K : 1); ++j) r[j] = ld4<kNtRecLd>(rec + j);
+    for (int j = 0; j < R; ++j) r[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (K && kEager && !empty) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) r[j] = ld4<kNtRecLd>(rec + j);
+    }
+    float q0 = 0.f, q1 = 0.f, q2 = 0.f;
+    if (kResEarly) {
+        q0 = ld<kNtResLd>(res + 0);
+        q1 = ld<kNtResLd>(res + 1);
+        q2 = ld<kNtResLd>(res + 2);
     }
 
     // 2. arithmetic that needs no loaded value: the Philox words and the weight's geometry
-    Words<K ? K : 1> words;
+    Words<R> words;
     float outside = 0.f, e = 0.f;
     if (kUpdates) {
-        if (K) words = philox_words<K ? K : 1>(d, p);
+        if (K) words = philox_words<R>(d, p);
         const float dx = ((float)x + 0.5f) - d.gx;
         const float dy = ((float)y + 0.5f) - d.gy;
         outside = weight_outside(d.c, dx * dx + dy * dy, e);
@@ -187,11 +237,12 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
         w = select_eq4(d.c, outside, e, lv);
         const float W1b = bias_shared(W1, w, d.bias, d.c.decay);
         const float s = W1b + w;
-        tk = K ? decide_words<K ? K : 1>(words, W1b, s) : decide_any(d, p, W1b, s);
+        tk = K ? decide_words<R>(words, W1b, s) : decide_any(d, p, W1b, s);
         st<kNtWsumSt>(d.wsum + p, s);
     }
 
-    // 3. the new colour where some slot takes it, then the replaced slots
+    // 4. the new colour where some slot takes it, the records of the slots that
+    //    keep their sample where only now needed, then the replaced slots
     float c0 = 0.f, c1 = 0.f, c2 = 0.f;
     if (tk) {
         if constexpr (FOV) {
@@ -206,14 +257,14 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
         }
     }
     const float4 fresh = make_float4(w, c0, c1, c2);
-    if (K && OP == kIncremental && tk) {
-        // only now is the record needed: the output changes with it
+    if (K && (OP == kIncremental || OP == kCached) && tk && !empty) {
 #pragma unroll
-        for (int j = 0; j < (K ? K : 1); ++j) r[j] = ld4<kNtRecLd>(rec + j);
+        for (int j = 0; j < R; ++j)
+            if (!((tk >> j) & 1u)) r[j] = ld4<kNtRecLd>(rec + j);
     }
     if (K) {
 #pragma unroll
-        for (int j = 0; j < (K ? K : 1); ++j) {
+        for (int j = 0; j < R; ++j) {
             if ((tk >> j) & 1u) {
                 r[j] = fresh;
                 st4<kNtRecSt>(rec + j, fresh);
@@ -222,39 +273,58 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
         }
     }
 
-    // 4. resolve: sum_j w_j col_j / sum_j w_j, slot order
-    if (kResolves && (OP != kIncremental || tk)) {
-        float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
-        if (K) {
-#pragma unroll
-            for (int j = 0; j < (K ? K : 1); ++j) {
-                S = S + r[j].x;
-                a0 = a0 + r[j].x * r[j].y;
-                a1 = a1 + r[j].x * r[j].z;
-                a2 = a2 + r[j].x * r[j].w;
-            }
-        } else {
-            for (int j = 0; j < kk; ++j) {
-                float4 v;
-                if ((tk >> j) & 1u) {
-                    v = fresh;
-                    st4<kNtRecSt>(rec + j, fresh);
-                    st<kNtIdxSt>(idx + j, d.t);
-                } else {
-                    v = ld4<kNtRecLd>(rec + j);
-                }
-                S = S + v.x;
-                a0 = a0 + v.x * v.y;
-                a1 = a1 + v.x * v.z;
-                a2 = a2 + v.x * v.w;
-            }
-        }
-        // S == 0 only before the first frame (every kept weight is > 0): output 0.
-        const float rs = S > 0.0f ? 1.0f / S : 0.0f;
+    // 5. resolve: sum_j w_j col_j / sum_j w_j in slot order -- recomputed, or for a
+    //    pixel without a replacement the unchanged value (kCached: from the
+    //    resolve plane; kIncremental: the output already holds it)
+    if (kResolves) {
+        const bool recompute = (OP != kIncremental && OP != kCached) || tk != 0u;
         float* o = d.out + 3 * (size_t)p;
-        st<kNtOut>(o + 0, a0 * rs);
-        st<kNtOut>(o + 1, a1 * rs);
-        st<kNtOut>(o + 2, a2 * rs);
+        if (recompute) {
+            float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
+            if (K) {
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    S = S + r[j].x;
+                    a0 = a0 + r[j].x * r[j].y;
+                    a1 = a1 + r[j].x * r[j].z;
+                    a2 = a2 + r[j].x * r[j].w;
+                }
+            } else {
+                for (int j = 0; j < kk; ++j) {
+                    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if ((tk >> j) & 1u) {
+                        v = fresh;
+                        st4<kNtRecSt>(rec + j, fresh);
+                        st<kNtIdxSt>(idx + j, d.t);
+                    } else if (!empty) {
+                        v = ld4<kNtRecLd>(rec + j);
+                    }
+                    S = S + v.x;
+                    a0 = a0 + v.x * v.y;
+                    a1 = a1 + v.x * v.z;
+                    a2 = a2 + v.x * v.w;
+                }
+            }
+            // S == 0 only before the first frame (every kept weight is > 0): output 0.
+            const float rs = S > 0.0f ? 1.0f / S : 0.0f;
+            q0 = a0 * rs;
+            q1 = a1 * rs;
+            q2 = a2 * rs;
+            if (kKeepsRes) {
+                st<kNtResSt>(res + 0, q0);
+                st<kNtResSt>(res + 1, q1);
+                st<kNtResSt>(res + 2, q2);
+            }
+        } else if (OP == kCached && !kResEarly) {
+            q0 = ld<kNtResLd>(res + 0);
+            q1 = ld<kNtResLd>(res + 1);
+            q2 = ld<kNtResLd>(res + 2);
+        }
+        if (recompute || OP == kCached) {
+            st<kNtOut>(o + 0, q0);
+            st<kNtOut>(o + 1, q1);
+            st<kNtOut>(o + 2, q2);
+        }
     } else if (!K) {
         for (int j = 0; j < kk; ++j)
             if ((tk >> j) & 1u) {
@@ -392,8 +462,10 @@ __device__ __forceinline__ uint32_t pixel_per_slot(const FrameDesc& d, uint32_t 
 // One work item (256 pixels).  The wave index is made explicit as a uniform
 // value so the tile arithmetic runs on the scalar unit.
 // ---------------------------------------------------------------------------
-template <int K, int OP, bool PER_SLOT = false, bool FOV = false>
-__device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t item, const FovSrc* fs = nullptr)
+// Pixel of this thread in work item `item`; false outside the image (or past
+// the frame's last item).  The wave index is made explicit as a uniform value
+// so the tile arithmetic runs on the scalar unit.
+__device__ __forceinline__ bool item_pixel(const FrameDesc& d, uint32_t item, uint32_t& x, uint32_t& y)
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -405,9 +477,17 @@ __device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t it
     const uint32_t local = ((wave & ((1u << waves_per_tile_log2) - 1u)) << 6) | lane;
     const uint32_t ty = tile / d.tiles_x;
     const uint32_t tx = tile - ty * d.tiles_x;
-    const uint32_t x = (tx << d.tile_x_log2) + (local & ((1u << d.tile_x_log2) - 1u));
-    const uint32_t y = (ty << d.tile_y_log2) + (local >> d.tile_x_log2);
-    if (y >= d.height || x >= d.width) return 0u;
+    x = (tx << d.tile_x_log2) + (local & ((1u << d.tile_x_log2) - 1u));
+    y = (ty << d.tile_y_log2) + (local >> d.tile_x_log2);
+    return item < d.items && y < d.height && x < d.width;
+}
+
+// One work item (256 pixels, one per thread).
+template <int K, int OP, bool PER_SLOT = false, bool FOV = false>
+__device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t item, const FovSrc* fs = nullptr)
+{
+    uint32_t x, y;
+    if (!item_pixel(d, item, x, y)) return 0u;
     if constexpr (PER_SLOT) return pixel_per_slot<K, OP, FOV>(d, x, y, fs);
     return pixel<K, OP, FOV>(d, x, y, fs);
 }
@@ -440,7 +520,7 @@ template <int K, int OP, bool PER_SLOT = false>
 __global__ __launch_bounds__(kBlock) void frame_kernel(FrameDesc d)
 {
     const uint32_t n = process_item<K, OP, PER_SLOT>(d, frame_item(blockIdx.x, d.items, d.t));
-    if ((OP == kPush || OP == kFused || OP == kIncremental) && d.stats) add_stats(d.stats, n);
+    if (OP != kResolve && d.stats) add_stats(d.stats, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -467,12 +547,18 @@ __global__ __launch_bounds__(kBlock) void tick_kernel(const TickArgs a)
         if (d.stats) add_stats(d.stats, n);
         return;
     }
+    // the frame's op (kFused, kCached or kFill) is uniform: a scalar branch
     switch (d.k) {
-        case 1: n = process_item<1, kFused>(d, local); break;
-        case 2: n = process_item<2, kFused>(d, local); break;
-        case 4: n = process_item<4, kFused>(d, local); break;
-        case 8: n = process_item<8, kFused>(d, local); break;
-        default: n = process_item<0, kFused>(d, local); break;
+        case 1: n = d.op == kCached ? process_item<1, kCached>(d, local)
+                  : d.op == kFill ? process_item<1, kFill>(d, local) : process_item<1, kFused>(d, local); break;
+        case 2: n = d.op == kCached ? process_item<2, kCached>(d, local)
+                  : d.op == kFill ? process_item<2, kFill>(d, local) : process_item<2, kFused>(d, local); break;
+        case 4: n = d.op == kCached ? process_item<4, kCached>(d, local)
+                  : d.op == kFill ? process_item<4, kFill>(d, local) : process_item<4, kFused>(d, local); break;
+        case 8: n = d.op == kCached ? process_item<8, kCached>(d, local)
+                  : d.op == kFill ? process_item<8, kFill>(d, local) : process_item<8, kFused>(d, local); break;
+        default: n = d.op == kCached ? process_item<0, kCached>(d, local)
+                   : d.op == kFill ? process_item<0, kFill>(d, local) : process_item<0, kFused>(d, local); break;
     }
     if (d.stats) add_stats(d.stats, n);
 }
@@ -950,7 +1036,8 @@ template <int OP>
 static hipError_t launch_frame_op(const FrameDesc& d, hipStream_t stream)
 {
     const dim3 grid(d.items), block(kBlock);
-    if constexpr (OP != kResolve) {
+    // the per-slot modes keep no resolve plane: they run kPush, kFused or kIncremental
+    if constexpr (OP == kPush || OP == kFused || OP == kIncremental) {
         if (per_slot_mode(d.bias)) {
             switch (d.k) {
                 case 4: hipLaunchKernelGGL((frame_kernel<4, OP, true>), grid, block, 0, stream, d); break;
@@ -977,6 +1064,8 @@ hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream)
         case kPush: return launch_frame_op<kPush>(d, stream);
         case kResolve: return launch_frame_op<kResolve>(d, stream);
         case kIncremental: return launch_frame_op<kIncremental>(d, stream);
+        case kCached: return launch_frame_op<kCached>(d, stream);
+        case kFill: return launch_frame_op<kFill>(d, stream);
         default: return launch_frame_op<kFused>(d, stream);
     }
 }
@@ -1061,26 +1150,36 @@ hipError_t launch_foveate(const FovSrc& s, float* color, uint8_t* level, uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_foveated(const FovDesc& fd, bool resolve, hipStream_t stream)
+hipError_t launch_foveated(const FovDesc& fd, int op, hipStream_t stream)
 {
     if (fd.f.items == 0u) return hipSuccess;
     const dim3 grid(fd.f.items), block(kBlock);
     const bool ps = per_slot_mode(fd.f.bias);
-#define FWRS_FOV_LAUNCH(KK, PS)                                                                       \
-    do {                                                                                              \
-        if (resolve) hipLaunchKernelGGL((foveated_kernel<KK, PS, kFused>), grid, block, 0, stream, fd); \
-        else hipLaunchKernelGGL((foveated_kernel<KK, PS, kPush>), grid, block, 0, stream, fd);         \
+#define FWRS_FOV_LAUNCH(KK, PS, OPV) hipLaunchKernelGGL((foveated_kernel<KK, PS, OPV>), grid, block, 0, stream, fd)
+#define FWRS_FOV_OPS(KK)                                      \
+    do {                                                      \
+        if (op == kCached) FWRS_FOV_LAUNCH(KK, false, kCached);   \
+        else if (op == kFill) FWRS_FOV_LAUNCH(KK, false, kFill);  \
+        else if (op == kPush) FWRS_FOV_LAUNCH(KK, false, kPush);  \
+        else FWRS_FOV_LAUNCH(KK, false, kFused);              \
     } while (0)
     if (ps) {
-        if (fd.f.k == 4) FWRS_FOV_LAUNCH(4, true);
-        else FWRS_FOV_LAUNCH(0, true);
+        const bool push = op == kPush;
+        if (fd.f.k == 4) {
+            if (push) FWRS_FOV_LAUNCH(4, true, kPush);
+            else FWRS_FOV_LAUNCH(4, true, kFused);
+        } else {
+            if (push) FWRS_FOV_LAUNCH(0, true, kPush);
+            else FWRS_FOV_LAUNCH(0, true, kFused);
+        }
     } else {
         switch (fd.f.k) {
-            case 4: FWRS_FOV_LAUNCH(4, false); break;
-            case 8: FWRS_FOV_LAUNCH(8, false); break;
-            default: FWRS_FOV_LAUNCH(0, false); break;
+            case 4: FWRS_FOV_OPS(4); break;
+            case 8: FWRS_FOV_OPS(8); break;
+            default: FWRS_FOV_OPS(0); break;
         }
     }
+#undef FWRS_FOV_OPS
 #undef FWRS_FOV_LAUNCH
     return hipGetLastError();
 }

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfwrs.so")
 OK, E_ARG, E_NOMEM, E_HIP, E_STATE = 0, 1, 2, 3, 4
 BIAS_NONE, BIAS_BERNOULLI, BIAS_FULL, BIAS_MEMORYLESS, AES = 0, 1, 2, 3, 4
 FLAG_REPROJECT = 1
+FLAG_NO_RESOLVE_PLANE = 2
 FOV_MIP, FOV_GAUSS = 0, 1
 MAX_K = 16
 
@@ -28,7 +29,7 @@ EXPORTS = (
     "fwrs_destroy", "fwrs_set_stream", "fwrs_reset", "fwrs_push_frame", "fwrs_resolve",
     "fwrs_push_frame_resolve", "fwrs_push_frame_resolve_incremental", "fwrs_push_frame_reproject",
     "fwrs_frame_index", "fwrs_get_state", "fwrs_download_state", "fwrs_get_stats",
-    "fwrs_set_tile", "fwrs_sync", "fwrs_strerror", "fwrs_engine_create", "fwrs_engine_tick",
+    "fwrs_set_tile", "fwrs_set_resolve_plane_from", "fwrs_sync", "fwrs_strerror", "fwrs_engine_create", "fwrs_engine_tick",
     "fwrs_engine_set_tile", "fwrs_engine_destroy", "fwrs_foveator_create", "fwrs_foveate",
     "fwrs_push_frame_foveated", "fwrs_foveator_destroy", "fwrs_method_constants", "fwrs_gauss_weights",
 )
@@ -73,6 +74,7 @@ class StateView(C.Structure):
         ("wsum_slots", C.c_int),
         ("cnt", C.c_void_p),
         ("depth", C.c_void_p),
+        ("res", C.c_void_p),
     ]
 
 
@@ -123,6 +125,7 @@ def load(path: str | None = None):
         "fwrs_get_stats": (i, [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                C.POINTER(C.c_uint64)]),
         "fwrs_set_tile": (i, [vp, i, i]),
+        "fwrs_set_resolve_plane_from": (i, [vp, u32]),
         "fwrs_sync": (i, [vp]),
         "fwrs_strerror": (C.c_char_p, [i]),
         "fwrs_engine_create": (i, [vp, i, i, C.POINTER(vp)]),
@@ -273,6 +276,11 @@ class Reservoir:
 
     def reset(self) -> None:
         _check(self._L.fwrs_reset(self._h), "fwrs_reset")
+
+    def set_resolve_plane_from(self, frame_index: int) -> None:
+        """fwrs_set_resolve_plane_from: the frame index from which fused passes copy unchanged
+        pixels' resolves from the resolve plane (a launch policy; results never change)."""
+        _check(self._L.fwrs_set_resolve_plane_from(self._h, int(frame_index)), "fwrs_set_resolve_plane_from")
 
     def _check_frame(self, color, level) -> None:
         H, W = self.height, self.width

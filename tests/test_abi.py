@@ -70,9 +70,10 @@ def test_default_params_and_sizes():
     assert p.flags == 0 and p.lambda_decay == pytest.approx(0.0231)
     assert (p.a_k, p.r2k, p.rek) == (pytest.approx(0.9851), pytest.approx(1.058), pytest.approx(22.14))
     N = 3840 * 2160
-    assert fwrs.state_bytes(3840, 2160, 4) == 4 * N * (1 + 20) + 24576      # N is a multiple of 64
+    # w_sum, k records and frame indices, the resolve plane (3 floats per pixel)
+    assert fwrs.state_bytes(3840, 2160, 4) == 4 * N * (1 + 20 + 3) + 24576      # N is a multiple of 64
     assert fwrs.state_host_bytes(3840, 2160, 4) == N * (8 + 96)
-    assert fwrs.state_bytes(13, 7, 3) == 4 * 128 * (1 + 15) + 24576        # pitch rounded up to 64
+    assert fwrs.state_bytes(13, 7, 3) == 4 * 128 * (1 + 15 + 3) + 24576        # pitch rounded up to 64
     # Eq. 7 keeps one w_sum per slot
     def prm(**kw):
         return fwrs.default_params(13, **kw)
@@ -87,7 +88,11 @@ def test_default_params_and_sizes():
     assert fwrs.state_bytes(13, 7, 3, prm(flags=fwrs.FLAG_REPROJECT)) == 2 * 4 * 128 * (1 + 15 + 2) + 24576
     assert fwrs.state_bytes(13, 7, 3, prm(flags=fwrs.FLAG_REPROJECT, bias_mode=fwrs.BIAS_FULL)) == \
         2 * 4 * 128 * (3 + 15 + 2) + 24576
-    assert fwrs.state_bytes(13, 7, 3, prm(flags=2)) == 0
+    # without the resolve plane
+    assert fwrs.state_bytes(13, 7, 3, prm(flags=fwrs.FLAG_NO_RESOLVE_PLANE)) == 4 * 128 * (1 + 15) + 24576
+    assert fwrs.state_bytes(13, 7, 3, prm(flags=fwrs.FLAG_NO_RESOLVE_PLANE, bias_mode=fwrs.BIAS_FULL)) == \
+        fwrs.state_bytes(13, 7, 3, prm(bias_mode=fwrs.BIAS_FULL))
+    assert fwrs.state_bytes(13, 7, 3, prm(flags=4)) == 0
     for bad in [(0, 5, 4), (5, 0, 4), (5, 5, 0), (5, 5, 17), (65536, 65536, 1)]:
         assert fwrs.state_bytes(*bad) == 0
 
@@ -108,10 +113,11 @@ def test_invalid_arguments_are_rejected_before_any_gpu_work():
     # a caller arena that is too small or misaligned
     assert L.fwrs_create_ex(64, 64, 4, C.byref(p), None, 256, 16, C.byref(h)) == fwrs.E_ARG
     assert L.fwrs_create_ex(64, 64, 4, C.byref(p), None, 4100, 1 << 30, C.byref(h)) == fwrs.E_ARG
-    # an arena sized for the shared-sum layout is too small under Eq. 7
+    # an arena sized for the shared-sum layout without the resolve plane is too small under Eq. 7
     q = fwrs.default_params(64)
     q.bias_mode = fwrs.BIAS_FULL
-    assert L.fwrs_create_ex(64, 64, 4, C.byref(q), None, 256, fwrs.state_bytes(64, 64, 4), C.byref(h)) == fwrs.E_ARG
+    small = fwrs.state_bytes(64, 64, 4, fwrs.default_params(64, flags=fwrs.FLAG_NO_RESOLVE_PLANE))
+    assert L.fwrs_create_ex(64, 64, 4, C.byref(q), None, 256, small, C.byref(h)) == fwrs.E_ARG
     assert L.fwrs_push_frame(None, None, None, 0.0, 0.0) == fwrs.E_ARG
     assert L.fwrs_push_frame_reproject(None, None, None, None, None, 0.0, 0.0, 0.1, None) == fwrs.E_ARG
     assert L.fwrs_resolve(None, None) == fwrs.E_ARG

@@ -49,14 +49,22 @@ def _compare_out(out, ref, where=""):
     return err
 
 
-def _run_pair(dev, spec, n_frames, mode="fused", tile=None, bias=fwrs.BIAS_BERNOULLI, every=1, src=None):
+def _keeps_plane(bias):
+    return bias in (fwrs.BIAS_NONE, fwrs.BIAS_BERNOULLI, fwrs.BIAS_MEMORYLESS)
+
+
+def _run_pair(dev, spec, n_frames, mode="fused", tile=None, bias=fwrs.BIAS_BERNOULLI, every=1, src=None,
+              res_from=None):
     """mode: "fused" (push + resolve in one call), "split" (push, then resolve) or
-    "incremental" (first frame fused, then only the changed pixels are rewritten)."""
+    "incremental" (first frame fused, then only the changed pixels are rewritten).
+    res_from: the frame from which fused passes use the resolve plane (None: the library's default)."""
     p, q = _params(spec, bias)
     src = src or synth.FrameSource(spec, device=dev, n_frames=n_frames)
     res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream())
     if tile is not None:
         res.set_tile(*tile)
+    if res_from is not None and _keeps_plane(bias):
+        res.set_resolve_plane_from(res_from)
     orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
     out = torch.full((spec.height, spec.width, 3), -1.0, dtype=torch.float32, device=dev)
     for t in range(n_frames):
@@ -77,10 +85,12 @@ def _run_pair(dev, spec, n_frames, mode="fused", tile=None, bias=fwrs.BIAS_BERNO
     return res, orc, out
 
 
-def test_small_workload_every_frame(dev):
-    """256x256, k = 4, 60 frames of the synthetic gaze trace, fused update + resolve."""
+@pytest.mark.parametrize("res_from", [None, 0, 1, 30])
+def test_small_workload_every_frame(dev, res_from):
+    """256x256, k = 4, 60 frames of the synthetic gaze trace, fused update + resolve; the resolve
+    plane used from the library's default frame, from the first, second and thirtieth frame."""
     spec = synth.spec_small()
-    res, orc, _ = _run_pair(dev, spec, spec.frames)
+    res, orc, _ = _run_pair(dev, spec, spec.frames, res_from=res_from)
     takes, changed, updates = res.stats()
     assert updates == spec.frames * spec.pixels
     assert 0 < changed <= takes
@@ -130,22 +140,112 @@ def test_incremental_resolve_checks_its_precondition(dev):
     (1, 1, 1, 5), (3, 2, 16, 4), (13, 7, 3, 6), (100, 37, 5, 4), (64, 64, 8, 5), (255, 3, 2, 5),
     (96, 40, 7, 4), (128, 33, 12, 3), (1367, 769, 4, 3),
 ])
-def test_sizes_and_slot_counts(dev, w, h, k, frames):
-    """Ragged widths (scalar path), every specialised and generic slot count, tiny images."""
+@pytest.mark.parametrize("res_from", [None, 1])
+def test_sizes_and_slot_counts(dev, w, h, k, frames, res_from):
+    """Ragged widths (scalar path), every specialised and generic slot count, tiny images; from
+    frame 1 on, unchanged pixels through the resolve plane."""
     spec = synth.StreamSpec(w, h, k, frames, max(1.0, 0.1 * w), max(2.5, 0.25 * w), 0.2 * w + 0.5, 2, 0.3 * w + 1,
                             stream_id=k)
-    _run_pair(dev, spec, frames)
+    _run_pair(dev, spec, frames, res_from=res_from)
 
 
 @pytest.mark.parametrize("tile", [(8, 8), (16, 16), (32, 8), (64, 4), (256, 1), (16, 4), (8, 16), (128, 2)])
 def test_tile_shape_never_changes_results(dev, tile):
     spec = synth.StreamSpec(200, 120, 4, 5, 20.0, 50.0, 3.0, 2, 9.0)
-    _run_pair(dev, spec, 5, tile=tile)
+    _run_pair(dev, spec, 5, tile=tile, res_from=2)
 
 
-def test_bias_none_mode(dev):
+@pytest.mark.parametrize("res_from", [None, 1])
+def test_bias_none_mode(dev, res_from):
     spec = synth.StreamSpec(160, 96, 4, 8, 16.0, 40.0, 3.0, 3, 8.0)
-    _run_pair(dev, spec, 8, bias=fwrs.BIAS_NONE)
+    _run_pair(dev, spec, 8, bias=fwrs.BIAS_NONE, res_from=res_from)
+
+
+def _plane(res, arena):
+    """The resolve plane as a host array [H, W, 3] (read from the caller arena at the offset the
+    state view reports), or None while the context reports it stale."""
+    v = res.state_view()
+    if not v.res:
+        return None
+    off = v.res - arena.data_ptr()
+    assert off == 4 * v.pitch * (1 + 5 * res.k)          # after w_sum, the records and the indices
+    n = res.height * res.width * 3
+    return arena[off:off + 4 * n].view(torch.float32).view(res.height, res.width, 3).cpu().numpy()
+
+
+@pytest.mark.parametrize("k", [4, 3])
+def test_resolve_plane_across_entry_points(dev, k):
+    """Every entry point that changes a context keeps its resolve plane current or marks it stale,
+    so a fused pass after any sequence of calls equals the oracle: fused frames from the plane,
+    an update without resolve (plane stale), an incremental frame (stale), a resolve-only call,
+    a reset, and the plane rebuilt by the frame before the next cached one."""
+    spec = synth.StreamSpec(160, 96, k, 16, 16.0, 40.0, 3.0, 4, 8.0)
+    p, q = _params(spec)
+    src = synth.FrameSource(spec, device=dev, n_frames=16)
+    arena = torch.empty(fwrs.state_bytes(spec.width, spec.height, spec.k, p), dtype=torch.uint8, device=dev)
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream(), arena=arena)
+    res.set_resolve_plane_from(1)
+    orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
+    out = torch.full((spec.height, spec.width, 3), -1.0, device=dev)
+    script = ["fused", "fused", "fused", "push", "fused", "fused", "incremental", "fused", "fused", "resolve",
+              "fused", "reset", "fused", "fused", "push", "resolve", "fused"]
+    t = 0
+    for op in script:
+        if op == "reset":
+            res.reset()
+            orc.close()
+            orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
+            t = 0
+            continue
+        if op == "resolve":
+            res.resolve(out)
+        else:
+            c, lev, gx, gy = src.frame(t)
+            if op == "fused":
+                res.step(c, lev, gx, gy, out)
+            elif op == "incremental":
+                res.step_incremental(c, lev, gx, gy, out)
+            else:
+                res.push(c, lev, gx, gy)
+            orc.push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+            t += 1
+        res.sync()
+        _compare_state(res.download(), orc.state(), f"after {op} at frame {t}")
+        if op != "push":
+            o = out.cpu().numpy()
+            _compare_out(o, orc.resolve(), f"after {op} at frame {t}")
+            plane = _plane(res, arena)
+            if op == "fused" and t >= 2:
+                assert plane is not None, f"plane stale after a fused frame at {t}"
+            if plane is not None:
+                assert np.array_equal(plane.view(np.uint32), o.view(np.uint32)), f"plane != resolve after {op}"
+        else:
+            assert _plane(res, arena) is None
+
+
+def test_no_resolve_plane_flag_gives_identical_results(dev):
+    spec = synth.StreamSpec(200, 120, 4, 12, 20.0, 50.0, 3.0, 4, 9.0)
+    outs = []
+    for flags in (0, fwrs.FLAG_NO_RESOLVE_PLANE):
+        p, _ = _params(spec)
+        p.flags = flags
+        src = synth.FrameSource(spec, device=dev, n_frames=12)
+        res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream())
+        if flags:
+            with pytest.raises(fwrs.FwrsError):
+                res.set_resolve_plane_from(0)
+        else:
+            res.set_resolve_plane_from(0)
+        out = torch.empty((spec.height, spec.width, 3), device=dev)
+        seq = []
+        for t in range(12):
+            res.step(*src.frame(t), out)
+            seq.append(out.clone())
+        res.sync()
+        outs.append((seq, res.download()))
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert torch.equal(a, b)
+    np.testing.assert_array_equal(outs[0][1].idx, outs[1][1].idx)
 
 
 def test_unaligned_buffers_take_the_scalar_path(dev):
@@ -284,9 +384,10 @@ def test_engine_tick_matches_oracle_and_plain_launches(dev, use_graph):
     eng.set_tile(0, 16, 16)
     eng.set_tile(30000, 64, 4)
     batched, plain, orcs, outs_b, outs_p = [], [], [], [], []
-    for s in specs:
+    for i, s in enumerate(specs):
         p, q = _params(s)
         batched.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
+        batched[-1].set_resolve_plane_from(i % 3)      # the frame's op differs between the tick's frames
         plain.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
         orcs.append(oracle.Oracle(s.width, s.height, s.k, q))
         outs_b.append(torch.empty((s.height, s.width, 3), device=dev))
@@ -325,9 +426,10 @@ def test_engine_ticks_over_several_launches(dev, use_graph):
     srcs = [synth.FrameSource(s, device=dev) for s in specs]
     eng = fwrs.Engine(len(specs), stream=stream, use_graph=use_graph)
     batched, plain, outs_b, outs_p = [], [], [], []
-    for s in specs:
+    for i, s in enumerate(specs):
         p, _ = _params(s)
         batched.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
+        batched[-1].set_resolve_plane_from(i % 4)
         plain.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
         outs_b.append(torch.empty((s.height, s.width, 3), device=dev))
         outs_p.append(torch.empty((s.height, s.width, 3), device=dev))
@@ -454,7 +556,8 @@ def test_eq7_static_scene_equals_eq6(dev):
 def test_eq7_caller_arena_is_sized_by_mode(dev):
     spec = synth.StreamSpec(128, 64, 4, 4, 12.0, 30.0, 2.0, 2, 6.0)
     p, q = _params(spec, fwrs.BIAS_FULL)
-    small = torch.empty(fwrs.state_bytes(spec.width, spec.height, spec.k), dtype=torch.uint8, device=dev)
+    shared = fwrs.default_params(spec.width, flags=fwrs.FLAG_NO_RESOLVE_PLANE)
+    small = torch.empty(fwrs.state_bytes(spec.width, spec.height, spec.k, shared), dtype=torch.uint8, device=dev)
     with pytest.raises(fwrs.FwrsError):
         fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream(), arena=small)
     arena = torch.full((fwrs.state_bytes(spec.width, spec.height, spec.k, p),), 0xAB,
