@@ -308,7 +308,7 @@ int fwrs_get_stats(fwrs_ctx* ctx, uint64_t* slot_takes, uint64_t* pixels_changed
  * batched ticks, fwrs_push_frame_foveated with an output) use the resolve
  * plane: the pass at frame index frame_index - 1 writes it for every pixel, and
  * the later passes read a pixel's slot records only where a slot was replaced
- * (default 8: while a store fills after a reset most pixels change every
+ * (default 32: while a store fills after a reset most pixels change every
  * frame).  0 uses it from the first frame.  A launch policy: results are
  * identical for every value.  FWRS_E_STATE if the context keeps no resolve
  * plane (FWRS_FLAG_NO_RESOLVE_PLANE, FWRS_BIAS_FULL, FWRS_AES, reprojecting). */
@@ -326,14 +326,15 @@ int fwrs_sync(fwrs_ctx* ctx);
 const char* fwrs_strerror(int status);
 
 /* ---- batched form --------------------------------------------------------
- * One tick advances several contexts -- any mix of sizes and slot counts, on
- * the same device -- by one frame each with a single kernel launch (one block
- * per 256-pixel work item of any of the tick's frames).
- * Each entry is the argument list of fwrs_push_frame_resolve; the results are
- * bit-identical to calling it once per entry.  A context may appear at most
- * once per tick.  Contexts' own streams are not used: the tick runs on the
- * engine's stream, and the caller orders it after any other work on those
- * contexts. */
+ * One tick advances several contexts -- any mix of sizes, slot counts and bias
+ * modes, on the same device -- by one frame each with a single kernel launch:
+ * one block per 256-pixel work item of all the tick's frames, whose
+ * descriptors the kernel reads from a table in device memory (copied there
+ * from pinned host memory on the tick's stream).  Sec. 3.2 and 4.1 make every
+ * pixel of every stream an independent reservoir, so the order in which a tick
+ * visits them never changes a result: each entry's results are bit-identical
+ * to calling fwrs_push_frame_resolve once per entry.  A context may appear at
+ * most once per tick. */
 typedef struct fwrs_frame {
     fwrs_ctx* ctx;
     const float* color;
@@ -343,23 +344,36 @@ typedef struct fwrs_frame {
     float* out;
 } fwrs_frame;
 
+/* Enqueues one tick of the n entries of `frames` (0 <= n <= 4096) on the HIP
+ * stream `hip_stream` (borrowed; NULL = null stream), each context tiled as
+ * its fwrs_set_tile says.  A context whose own stream is another one is
+ * ordered by events: the tick waits for the work already enqueued on that
+ * stream, and later work there (fwrs_destroy's wait included) waits for the
+ * tick.  The descriptor table lives in a ring of pinned host and device
+ * buffers that the library allocates for each device on first use and keeps
+ * until the process ends; a call waits (on the host) only if the ring's
+ * oldest tick is still running.  Thread-safe.
+ * FWRS_E_ARG: n outside [0, 4096], frames NULL with n > 0, a NULL field or
+ * non-finite gaze, a context repeated, contexts on different devices.
+ * FWRS_E_STATE: as fwrs_push_frame.  FWRS_E_HIP: the copy of the table or the
+ * launch failed (no context advanced), or only the final cross-stream
+ * ordering failed (the tick ran and every context advanced). */
+int fwrs_tick(const fwrs_frame* frames, int n, void* hip_stream);
+
+/* An engine: fwrs_tick with its own ring, a fixed stream, a tile table per
+ * resolution class and optionally HIP graphs. */
 typedef struct fwrs_engine fwrs_engine;
 
-/* Creates a tick engine for up to `max_frames` (<= 4096) entries per tick on a
- * borrowed HIP stream.  A tick is issued as ceil(n / 24) launches of the
- * batched kernel whose frame descriptors are kernel arguments.  With
- * use_graph != 0 those launches are the kernel nodes of a HIP graph that each
- * tick updates and replays (one graph per launch count, built on first use);
- * the stream must then not be capturing. */
+/* Creates an engine for up to `max_frames` (1 .. 4096) entries per tick on a
+ * borrowed HIP stream.  With use_graph != 0 each tick is the replay of a HIP
+ * graph -- the copy of the descriptor table, then the batched kernel -- built
+ * once per ring slot and updated only when a tick's frames change size; the
+ * stream must then not be capturing.
+ * FWRS_E_ARG, FWRS_E_NOMEM, FWRS_E_HIP. */
 int fwrs_engine_create(void* hip_stream, int max_frames, int use_graph, fwrs_engine** out);
 
-/* Enqueues one tick on the engine's stream.  A context whose own stream is
- * another one is ordered by events: the tick waits for the work already
- * enqueued on that stream, and later work there (fwrs_destroy's wait
- * included) waits for the tick.  FWRS_E_ARG: n outside [0, max_frames], a NULL
- * field, a context repeated, contexts on another device.  FWRS_E_HIP: a
- * launch or event call failed (if only the final ordering failed, the tick
- * ran and the contexts advanced). */
+/* fwrs_tick on the engine's stream and ring, tiles from its class table.
+ * FWRS_E_ARG also for n above the engine's max_frames. */
 int fwrs_engine_tick(fwrs_engine* eng, const fwrs_frame* frames, int n);
 
 /* Selects the tile shape the engine uses for contexts whose width * height is
@@ -367,7 +381,7 @@ int fwrs_engine_tick(fwrs_engine* eng, const fwrs_frame* frames, int n);
  * first wins); same constraints as fwrs_set_tile.  Results never change. */
 int fwrs_engine_set_tile(fwrs_engine* eng, long long min_pixels, int tile_x, int tile_y);
 
-/* Waits for the engine's stream, then frees the engine. */
+/* Waits for the engine's stream and ticks, then frees the engine. */
 int fwrs_engine_destroy(fwrs_engine* eng);
 
 /* ---- foveation generator (Sec. 4.3) -------------------------------------

@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -30,7 +32,7 @@ constexpr int kDefaultTileX = 64, kDefaultTileY = 1;
 // plane densely (kOpFill) and later frames use it (kOpCached).  A launch-policy
 // constant: it never changes results.
 #ifndef FWRS_RES_FROM
-#define FWRS_RES_FROM 8
+#define FWRS_RES_FROM 32
 #endif
 constexpr uint32_t kResFrom = FWRS_RES_FROM;
 
@@ -646,24 +648,42 @@ const char* fwrs_strerror(int status)
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Batched tick engine: the frames of a tick go to the batched kernel in
-// launches of up to fwrs::kTickFrames frames whose descriptors are kernel
-// arguments (nothing is uploaded before a launch).  In graph mode the
-// launches of a tick are the kernel nodes of a HIP graph (one graph per
-// launch count, built on first use); each tick rewrites the nodes' arguments
-// and grids and replays it.
+// Batched ticks.  A tick's frame descriptors form a table that one launch of
+// the batched kernel reads from device memory (one block per 256-pixel work
+// item of all the tick's frames).  An engine keeps a ring of kRing tick slots
+// -- a pinned host table, its device copy and an event marking the end of the
+// tick that last used the slot -- so the host writes the next tick's table
+// while earlier ticks run, and a slot is written again only after its event.
+// A tick is the copy of its table (host to device, on the tick's stream) and
+// the kernel; in graph mode each slot's copy and kernel are a HIP graph built
+// on first use and replayed as it is, updating only the copy's byte count and
+// the kernel's grid when the tick's frames change size.
 // ---------------------------------------------------------------------------
 namespace {
+
+constexpr int kRing = 4;                // even: a slot always serves ticks of the same direction
+constexpr int kTickMax = 4096;          // frames per tick (fwrs_tick; engines up to their max_frames)
+constexpr int kMaxDevices = 64;
 
 struct TileClass {
     long long min_pixels;
     int tx, ty;
 };
 
-struct TickGraph {
+struct TickSlot {
+    void* host = nullptr;               // pinned table
+    void* dev = nullptr;                // device table
+    hipEvent_t done = nullptr;          // end of the slot's latest tick
+    bool pending = false;               // `done` recorded, not yet waited for
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<hipGraphNode_t> nodes;
+    hipGraphNode_t copy = nullptr;
+    hipGraphNode_t kernel = nullptr;
+    size_t copy_bytes = 0;              // bytes the graph's copy node moves
+    uint32_t grid = 0;                  // the graph's kernel grid
+    const void* head_arg = nullptr;     // the kernel node's argument values
+    const void* descs_arg = nullptr;
+    void* kparams[2] = {nullptr, nullptr};
 };
 
 }  // namespace
@@ -673,27 +693,74 @@ struct fwrs_engine {
     int device = 0;
     int max_frames = 0;
     int use_graph = 0;
+    bool ctx_tiles = false;             // each context's own tile (fwrs_tick) instead of the class table
+    size_t table_bytes = 0;
     std::vector<TileClass> classes;
-    std::vector<fwrs::TickArgs> args;          // one per launch of the current tick
-    std::vector<TickGraph> graphs;             // graphs[m - 1]: a tick of m launches
-    hipEvent_t done_ev = nullptr;              // end of the latest tick, for contexts on other streams
-    uint32_t ticks = 0;                        // ticks issued (odd ticks run in reverse order)
+    std::vector<int> ops;               // op of each frame of the tick being issued
+    TickSlot slot[kRing];
+    hipEvent_t done_ev = nullptr;       // end of the latest tick, for contexts on other streams
+    uint32_t ticks = 0;                 // ticks issued (odd ticks run in reverse order)
 };
 
 namespace {
 
+void slot_free(TickSlot& sl)
+{
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    if (sl.graph) (void)hipGraphDestroy(sl.graph);
+    sl.exec = nullptr;
+    sl.graph = nullptr;
+    sl.copy = nullptr;
+    sl.kernel = nullptr;
+    sl.copy_bytes = 0;
+    sl.grid = 0;
+}
+
 void engine_free(fwrs_engine* e)
 {
-    for (TickGraph& g : e->graphs) {
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
-        if (g.graph) (void)hipGraphDestroy(g.graph);
+    for (TickSlot& sl : e->slot) {
+        slot_free(sl);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.host) (void)hipHostFree(sl.host);
     }
     if (e->done_ev) (void)hipEventDestroy(e->done_ev);
     delete e;
 }
 
-void engine_tile(const fwrs_engine* e, long long pixels, int& tx, int& ty)
+// Allocates the ring; FWRS_OK or an error status (the caller frees e).
+int engine_init(fwrs_engine* e, int max_frames)
 {
+    e->max_frames = max_frames;
+    e->table_bytes = fwrs::tick_table_bytes((size_t)max_frames);
+    try {
+        e->ops.resize((size_t)max_frames);
+    } catch (const std::bad_alloc&) {
+        return FWRS_E_NOMEM;
+    }
+    for (TickSlot& sl : e->slot) {
+        if (hipHostMalloc(&sl.host, e->table_bytes, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(&sl.dev, e->table_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return FWRS_E_NOMEM;
+        }
+        if (hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) return FWRS_E_HIP;
+        sl.head_arg = sl.dev;
+        sl.descs_arg = static_cast<const char*>(sl.dev) + fwrs::kTickDescOffset;
+        sl.kparams[0] = &sl.head_arg;
+        sl.kparams[1] = &sl.descs_arg;
+    }
+    return FWRS_OK;
+}
+
+void engine_tile(const fwrs_engine* e, const fwrs_ctx* x, int& tx, int& ty)
+{
+    if (e->ctx_tiles) {
+        tx = x->tile_x;
+        ty = x->tile_y;
+        return;
+    }
+    const long long pixels = (long long)x->width * x->height;
     tx = kDefaultTileX;
     ty = kDefaultTileY;
     long long best = -1;
@@ -705,41 +772,145 @@ void engine_tile(const fwrs_engine* e, long long pixels, int& tx, int& ty)
         }
 }
 
-hipKernelNodeParams tick_node_params(fwrs::TickArgs* a, void** slot)
+hipKernelNodeParams tick_node(TickSlot& sl, uint32_t grid)
 {
-    *slot = a;
     hipKernelNodeParams kp{};
     kp.func = fwrs::tick_kernel_entry();
-    kp.gridDim = dim3(a->total > 0 ? a->total : 1u);
+    kp.gridDim = dim3(grid);
     kp.blockDim = dim3(fwrs::kBlock);
     kp.sharedMemBytes = 0;
-    kp.kernelParams = slot;
+    kp.kernelParams = sl.kparams;
     kp.extra = nullptr;
     return kp;
 }
 
-// The graph for a tick of m launches: m kernel nodes in a chain.
-hipError_t engine_graph(fwrs_engine* e, int m, TickGraph** out)
+// The slot's graph: the copy of `bytes` of its table, then the kernel on
+// `grid` blocks.  A built graph is updated only where the tick's size differs
+// from the one it holds.  On failure nothing is left half built.
+hipError_t slot_graph(TickSlot& sl, size_t bytes, uint32_t grid)
 {
-    if ((int)e->graphs.size() < m) e->graphs.resize(m);
-    TickGraph& g = e->graphs[m - 1];
-    if (!g.exec) {
-        hipError_t err = hipGraphCreate(&g.graph, 0);
-        hipGraphNode_t prev = nullptr;
-        for (int c = 0; c < m && err == hipSuccess; ++c) {
-            void* slot;
-            hipKernelNodeParams kp = tick_node_params(&e->args[c], &slot);
-            hipGraphNode_t node = nullptr;
-            err = hipGraphAddKernelNode(&node, g.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
-            g.nodes.push_back(node);
-            prev = node;
+    if (sl.exec) {
+        hipError_t err = hipSuccess;
+        if (sl.copy_bytes != bytes) {
+            err = hipGraphExecMemcpyNodeSetParams1D(sl.exec, sl.copy, sl.dev, sl.host, bytes, hipMemcpyHostToDevice);
+            if (err == hipSuccess) sl.copy_bytes = bytes;
         }
-        if (err == hipSuccess) err = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
-        if (err != hipSuccess) return err;
+        if (err == hipSuccess && sl.grid != grid) {
+            hipKernelNodeParams kp = tick_node(sl, grid);
+            err = hipGraphExecKernelNodeSetParams(sl.exec, sl.kernel, &kp);
+            if (err == hipSuccess) sl.grid = grid;
+        }
+        return err;
     }
-    *out = &g;
+    hipError_t err = hipGraphCreate(&sl.graph, 0);
+    if (err == hipSuccess)
+        err = hipGraphAddMemcpyNode1D(&sl.copy, sl.graph, nullptr, 0, sl.dev, sl.host, bytes, hipMemcpyHostToDevice);
+    if (err == hipSuccess) {
+        hipKernelNodeParams kp = tick_node(sl, grid);
+        err = hipGraphAddKernelNode(&sl.kernel, sl.graph, &sl.copy, 1, &kp);
+    }
+    if (err == hipSuccess) err = hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+        (void)hipGetLastError();
+        slot_free(sl);
+        return err;
+    }
+    sl.copy_bytes = bytes;
+    sl.grid = grid;
     return hipSuccess;
 }
+
+// One tick of n frames on `stream`: validation, the table, the launch, the
+// contexts' frame counts.  Every context's frame enters the state of the
+// tick's launch or of none: on FWRS_E_HIP no context has advanced, except that
+// if only the final cross-stream ordering failed the tick ran and they did.
+int engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n, hipStream_t stream)
+{
+    if (n < 0 || n > e->max_frames || (n > 0 && !frames)) return FWRS_E_ARG;
+    for (int i = 0; i < n; ++i) {
+        const fwrs_frame& f = frames[i];
+        if (!f.ctx || !f.color || !f.level_map || !f.out || !gaze_ok(f.gaze_x, f.gaze_y)) return FWRS_E_ARG;
+        if (f.ctx->device != e->device) return FWRS_E_ARG;
+        if (f.ctx->t == 0xFFFFFFFFu || f.ctx->reproject) return FWRS_E_STATE;
+        for (int j = 0; j < i; ++j)
+            if (frames[j].ctx == f.ctx) return FWRS_E_ARG;
+    }
+    if (n == 0) return FWRS_OK;
+    DeviceGuard g(e->device);
+    if (!g.ok) return FWRS_E_HIP;
+    TickSlot& sl = e->slot[e->ticks % kRing];
+    if (sl.pending) {
+        if (hipEventSynchronize(sl.done) != hipSuccess) return FWRS_E_HIP;
+        sl.pending = false;
+    }
+    // Every other tick walks its work items last first (its frames in reverse
+    // order, each frame's items in reverse), so a tick starts on the state the
+    // previous one touched last, while it is still in the Infinity Cache.
+    const bool reverse = (e->ticks & 1u) != 0u;
+    fwrs::TickHead* head = static_cast<fwrs::TickHead*>(sl.host);
+    FrameDesc* descs = reinterpret_cast<FrameDesc*>(static_cast<char*>(sl.host) + fwrs::kTickDescOffset);
+    head->n = (uint32_t)n;
+    head->total = 0;
+    head->pad0 = head->pad1 = 0;
+    for (int slot_i = 0; slot_i < n; ++slot_i) {
+        const int i = reverse ? n - 1 - slot_i : slot_i;
+        const fwrs_frame& f = frames[i];
+        int tx, ty;
+        engine_tile(e, f.ctx, tx, ty);
+        FrameDesc& d = descs[slot_i];
+        d = make_desc(f.ctx, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, tx, ty);
+        e->ops[i] = fused_op(f.ctx);
+        d.op = (uint32_t)e->ops[i];
+        d.first = head->total;
+        d.rev = reverse ? 1u : 0u;
+        head->total += d.items;
+    }
+    // each context's earlier work on its own stream comes first
+    hipError_t err = hipSuccess;
+    bool foreign = false;
+    for (int i = 0; i < n && err == hipSuccess; ++i) {
+        fwrs_ctx* c = frames[i].ctx;
+        if (c->stream != stream) {
+            foreign = true;
+            err = order_after(stream, c->stream, c->order_ev);
+        }
+    }
+    const size_t bytes = fwrs::tick_table_bytes((size_t)n);
+    if (err == hipSuccess && e->use_graph) {
+        err = slot_graph(sl, bytes, head->total);
+        if (err == hipSuccess) err = hipGraphLaunch(sl.exec, stream);
+    } else if (err == hipSuccess) {
+        err = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream);
+        if (err == hipSuccess) err = fwrs::launch_tick(sl.dev, head->total, stream);
+    }
+    if (err == hipSuccess) err = hipEventRecord(sl.done, stream);
+    if (err != hipSuccess) {
+        (void)hipGetLastError();
+        return FWRS_E_HIP;
+    }
+    sl.pending = true;
+    e->ticks += 1u;
+    for (int i = 0; i < n; ++i) advance(frames[i].ctx, e->ops[i], frames[i].out);
+    // ... and its later work (and fwrs_destroy) waits for this tick
+    if (foreign) {
+        if (!e->done_ev && hipEventCreateWithFlags(&e->done_ev, hipEventDisableTiming) != hipSuccess) {
+            e->done_ev = nullptr;
+            err = hipErrorOutOfMemory;
+        }
+        if (err == hipSuccess) err = hipEventRecord(e->done_ev, stream);
+        for (int i = 0; i < n && err == hipSuccess; ++i)
+            if (frames[i].ctx->stream != stream) err = hipStreamWaitEvent(frames[i].ctx->stream, e->done_ev, 0);
+        if (err != hipSuccess) {
+            (void)hipGetLastError();
+            return FWRS_E_HIP;
+        }
+    }
+    return FWRS_OK;
+}
+
+// fwrs_tick's engines: one per device, made on first use, kept for the process.
+std::mutex g_tick_mutex;
+fwrs_engine* g_tick_engine[kMaxDevices] = {};
 
 }  // namespace
 
@@ -747,22 +918,20 @@ extern "C" {
 
 int fwrs_engine_create(void* hip_stream, int max_frames, int use_graph, fwrs_engine** out)
 {
-    if (!out || max_frames <= 0 || max_frames > 4096) return FWRS_E_ARG;
+    if (!out || max_frames <= 0 || max_frames > kTickMax) return FWRS_E_ARG;
     *out = nullptr;
     fwrs_engine* e = new (std::nothrow) fwrs_engine();
     if (!e) return FWRS_E_NOMEM;
     e->stream = (hipStream_t)hip_stream;
-    e->max_frames = max_frames;
     e->use_graph = use_graph ? 1 : 0;
     if (hipGetDevice(&e->device) != hipSuccess) {
         delete e;
         return FWRS_E_HIP;
     }
-    try {
-        e->args.resize((size_t)(max_frames + fwrs::kTickFrames - 1) / fwrs::kTickFrames);
-    } catch (const std::bad_alloc&) {
-        delete e;
-        return FWRS_E_NOMEM;
+    const int rc = engine_init(e, max_frames);
+    if (rc != FWRS_OK) {
+        engine_free(e);
+        return rc;
     }
     *out = e;
     return FWRS_OK;
@@ -784,89 +953,8 @@ int fwrs_engine_set_tile(fwrs_engine* e, long long min_pixels, int tile_x, int t
 
 int fwrs_engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n)
 {
-    if (!e || n < 0 || n > e->max_frames || (n > 0 && !frames)) return FWRS_E_ARG;
-    for (int i = 0; i < n; ++i) {
-        const fwrs_frame& f = frames[i];
-        if (!f.ctx || !f.color || !f.level_map || !f.out || !gaze_ok(f.gaze_x, f.gaze_y)) return FWRS_E_ARG;
-        if (f.ctx->device != e->device) return FWRS_E_ARG;
-        if (f.ctx->t == 0xFFFFFFFFu || f.ctx->reproject) return FWRS_E_STATE;
-        for (int j = 0; j < i; ++j)
-            if (frames[j].ctx == f.ctx) return FWRS_E_ARG;
-    }
-    if (n == 0) return FWRS_OK;
-    DeviceGuard g(e->device);
-    if (!g.ok) return FWRS_E_HIP;
-    const int m = (n + fwrs::kTickFrames - 1) / fwrs::kTickFrames;
-    // Every other tick walks its work items last first (launches in reverse
-    // order, each launch's items in reverse), so a tick starts on the state the
-    // previous one touched last, while it is still in the Infinity Cache.
-    const bool reverse = (e->ticks & 1u) != 0u;
-    for (int c = 0; c < m; ++c) {
-        fwrs::TickArgs& a = e->args[c];
-        const int chunk = reverse ? m - 1 - c : c;
-        a.n = 0;
-        a.total = 0;
-        a.reverse = reverse ? 1u : 0u;
-        for (int i = chunk * fwrs::kTickFrames; i < n && i < (chunk + 1) * fwrs::kTickFrames; ++i) {
-            const fwrs_frame& f = frames[i];
-            int tx, ty;
-            engine_tile(e, (long long)f.ctx->width * f.ctx->height, tx, ty);
-            a.descs[a.n] = make_desc(f.ctx, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, tx, ty);
-            a.descs[a.n].op = (uint32_t)fused_op(f.ctx);
-            a.begins[a.n] = a.total;
-            a.total += a.descs[a.n].items;
-            ++a.n;
-        }
-    }
-    // each context's earlier work on its own stream comes first
-    hipError_t err = hipSuccess;
-    bool foreign = false;
-    for (int i = 0; i < n && err == hipSuccess; ++i) {
-        fwrs_ctx* c = frames[i].ctx;
-        if (c->stream != e->stream) {
-            foreign = true;
-            err = order_after(e->stream, c->stream, c->order_ev);
-        }
-    }
-    if (err == hipSuccess && e->use_graph) {
-        TickGraph* tg = nullptr;
-        err = engine_graph(e, m, &tg);
-        for (int c = 0; c < m && err == hipSuccess; ++c) {
-            void* slot;
-            hipKernelNodeParams kp = tick_node_params(&e->args[c], &slot);
-            err = hipGraphExecKernelNodeSetParams(tg->exec, tg->nodes[c], &kp);
-        }
-        if (err == hipSuccess) err = hipGraphLaunch(tg->exec, e->stream);
-    } else {
-        for (int c = 0; c < m && err == hipSuccess; ++c) err = fwrs::launch_tick(e->args[c], e->stream);
-    }
-    if (err != hipSuccess) {
-        (void)hipGetLastError();
-        return FWRS_E_HIP;
-    }
-    e->ticks += 1u;
-    for (int c = 0; c < m; ++c) {
-        const int chunk = reverse ? m - 1 - c : c;
-        for (uint32_t i = 0; i < e->args[c].n; ++i) {
-            const fwrs_frame& f = frames[chunk * fwrs::kTickFrames + (int)i];
-            advance(f.ctx, (int)e->args[c].descs[i].op, f.out);
-        }
-    }
-    // ... and its later work (and fwrs_destroy) waits for this tick
-    if (foreign) {
-        if (!e->done_ev && hipEventCreateWithFlags(&e->done_ev, hipEventDisableTiming) != hipSuccess) {
-            e->done_ev = nullptr;
-            err = hipErrorOutOfMemory;
-        }
-        if (err == hipSuccess) err = hipEventRecord(e->done_ev, e->stream);
-        for (int i = 0; i < n && err == hipSuccess; ++i)
-            if (frames[i].ctx->stream != e->stream) err = hipStreamWaitEvent(frames[i].ctx->stream, e->done_ev, 0);
-        if (err != hipSuccess) {
-            (void)hipGetLastError();
-            return FWRS_E_HIP;
-        }
-    }
-    return FWRS_OK;
+    if (!e) return FWRS_E_ARG;
+    return engine_tick(e, frames, n, e->stream);
 }
 
 int fwrs_engine_destroy(fwrs_engine* e)
@@ -876,9 +964,36 @@ int fwrs_engine_destroy(fwrs_engine* e)
     {
         DeviceGuard g(e->device);
         if (hipStreamSynchronize(e->stream) != hipSuccess) rc = FWRS_E_HIP;
+        for (TickSlot& sl : e->slot)
+            if (sl.pending && hipEventSynchronize(sl.done) != hipSuccess) rc = FWRS_E_HIP;
         engine_free(e);
     }
     return rc;
+}
+
+int fwrs_tick(const fwrs_frame* frames, int n, void* hip_stream)
+{
+    if (n < 0 || n > kTickMax || (n > 0 && (!frames || !frames[0].ctx))) return FWRS_E_ARG;
+    if (n == 0) return FWRS_OK;
+    const int dev = frames[0].ctx->device;
+    if (dev < 0 || dev >= kMaxDevices) return FWRS_E_ARG;
+    std::lock_guard<std::mutex> lock(g_tick_mutex);
+    fwrs_engine*& e = g_tick_engine[dev];
+    if (!e) {
+        DeviceGuard g(dev);
+        if (!g.ok) return FWRS_E_HIP;
+        fwrs_engine* made = new (std::nothrow) fwrs_engine();
+        if (!made) return FWRS_E_NOMEM;
+        made->device = dev;
+        made->ctx_tiles = true;
+        const int rc = engine_init(made, kTickMax);
+        if (rc != FWRS_OK) {
+            engine_free(made);
+            return rc;
+        }
+        e = made;
+    }
+    return engine_tick(e, frames, n, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

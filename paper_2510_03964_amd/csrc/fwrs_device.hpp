@@ -28,7 +28,8 @@ struct Consts {
 };
 
 // Everything one frame of one context needs on the device.  Passed by value
-// to the single-frame kernels and stored in a device table for batched ticks.
+// to the single-frame kernels and stored in a device table for batched ticks
+// (where `first` is the tick's first work item of the frame).
 struct alignas(8) FrameDesc {
     const float* color;         // [H][W][3] f32, the new candidates
     const uint8_t* level;       // [H][W] u8 foveation level
@@ -44,6 +45,8 @@ struct alignas(8) FrameDesc {
     uint32_t seed, stream_id, bias;
     uint32_t op;                // what the batched kernel runs for this frame (an Op of the kernels)
     uint32_t tile_x_log2, tile_y_log2, tiles_x, items;  // launch geometry
+    uint32_t first;             // batched ticks: the frame's first work item in the tick
+    uint32_t rev;               // batched ticks: the frame's items are visited last first
 };
 
 // Reprojected frame (Sec. 4.3): the reservoirs are gathered from the previous
@@ -84,7 +87,6 @@ struct alignas(8) FovDesc {
 };
 
 constexpr int kBlock = 256;             // threads per block
-constexpr int kTickFrames = 24;         // frames per batched launch (descriptors travel as kernel arguments)
 constexpr int kStatSlots = 1024;        // spread of the slot-take counters
 constexpr uint32_t kBiasNone = 0u;
 constexpr uint32_t kBiasBernoulli = 1u;

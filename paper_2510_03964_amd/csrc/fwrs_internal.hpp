@@ -24,18 +24,33 @@ constexpr int kOpCached = 7;        // update + resolve, unchanged pixels from t
 constexpr int kOpFill = 9;          // kOpFused that also writes the resolve plane
 hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream);
 
-// Arguments of one batched launch: n frames, `total` work items, frame f owns
-// items [begins[f], begins[f + 1]); reverse != 0 visits the items last first.
-// Passed by value (< 4 KiB).
-struct TickArgs {
-    uint32_t n, total, reverse;
-    uint32_t begins[kTickFrames];
-    FrameDesc descs[kTickFrames];
+// A batched tick's table in device memory: this head, then (at kTickDescOffset)
+// the n frame descriptors in the order their work items are numbered
+// (descs[f].first increasing, descs[f].items > 0); `total` = the tick's work
+// items.
+struct alignas(16) TickHead {
+    uint32_t n, total, pad0, pad1;
 };
-static_assert(sizeof(TickArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+constexpr size_t kTickDescOffset = 16;
+static_assert(sizeof(TickHead) == kTickDescOffset, "descriptors follow the head");
+inline size_t tick_table_bytes(size_t n) { return kTickDescOffset + n * sizeof(FrameDesc); }
 
-// Batched kernel, one block per work item of the launch's frames.
-hipError_t launch_tick(const TickArgs& a, hipStream_t stream);
+// The batched kernel on `grid` blocks (block b takes work items b, b + grid,
+// ... of the table's tick; the engine launches one block per item).
+hipError_t launch_tick(const void* table, uint32_t grid, hipStream_t stream);
+// Its entry point, for HIP graph kernel nodes: arguments (const TickHead*, const FrameDesc*).
+void* tick_kernel_entry();
+
+// One launch of the table-fill kernel: writes `count` descriptors (kernel
+// arguments) to table slots at .. at + count - 1, and the head if write_head.
+constexpr int kFillFrames = 20;
+struct TickFill {
+    TickHead head;
+    uint32_t at, count, write_head, pad;
+    FrameDesc descs[kFillFrames];
+};
+static_assert(sizeof(TickFill) <= 4096, "kernel arguments are limited to 4 KiB");
+hipError_t launch_tick_fill(void* table, const TickFill& f, hipStream_t stream);
 
 // Reprojected frame: gather from the previous bank, dense write to this one.
 hipError_t launch_reproject(const ReprojDesc& r, hipStream_t stream);
@@ -53,7 +68,5 @@ hipError_t launch_foveated(const FovDesc& fd, int op, hipStream_t stream);
 
 hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t stream);
 
-// Entry point of the batched kernel, for HIP graph kernel nodes.
-void* tick_kernel_entry();
 
 }  // namespace fwrs

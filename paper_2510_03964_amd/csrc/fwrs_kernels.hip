@@ -465,11 +465,9 @@ __device__ __forceinline__ uint32_t pixel_per_slot(const FrameDesc& d, uint32_t 
 // Pixel of this thread in work item `item`; false outside the image (or past
 // the frame's last item).  The wave index is made explicit as a uniform value
 // so the tile arithmetic runs on the scalar unit.
-__device__ __forceinline__ bool item_pixel(const FrameDesc& d, uint32_t item, uint32_t& x, uint32_t& y)
+__device__ __forceinline__ bool item_pixel_of(const FrameDesc& d, uint32_t item, uint32_t wave, uint32_t lane,
+                                              uint32_t& x, uint32_t& y)
 {
-    const uint32_t tid = threadIdx.x;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const uint32_t lane = tid & 63u;
     const uint32_t tlog = d.tile_x_log2 + d.tile_y_log2;            // log2(threads per tile): 6..8
     const uint32_t waves_per_tile_log2 = tlog - 6u;
     const uint32_t tiles_per_item_log2 = 8u - tlog;
@@ -480,6 +478,12 @@ __device__ __forceinline__ bool item_pixel(const FrameDesc& d, uint32_t item, ui
     x = (tx << d.tile_x_log2) + (local & ((1u << d.tile_x_log2) - 1u));
     y = (ty << d.tile_y_log2) + (local >> d.tile_x_log2);
     return item < d.items && y < d.height && x < d.width;
+}
+
+__device__ __forceinline__ bool item_pixel(const FrameDesc& d, uint32_t item, uint32_t& x, uint32_t& y)
+{
+    const uint32_t tid = threadIdx.x;
+    return item_pixel_of(d, item, __builtin_amdgcn_readfirstlane(tid >> 6), tid & 63u, x, y);
 }
 
 // One work item (256 pixels, one per thread).
@@ -524,43 +528,80 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(FrameDesc d)
 }
 
 // ---------------------------------------------------------------------------
-// Batched tick: one block per work item of any of up to kTickFrames frames.
-// The descriptors travel in the kernel arguments (no upload before the
-// launch); begins[f] is the first item of frame f (increasing).  A block finds
-// its frame by counting the begins at or below its item (uniform, scalar),
-// then runs the same per-pixel code as the single-frame kernels.
+// Batched tick: one launch for all the frames of a tick, any number of them.
+// The frames' descriptors are a table in device memory (uniform data, read
+// with scalar loads), in the order the tick visits them; the tick's 256-pixel
+// work items are numbered frame after frame, and a frame whose `rev` is set
+// visits its own items last first (the host reverses the frame order and sets
+// `rev` on every other tick, so such a tick runs entirely backwards).  Block b
+// takes items b, b + G, b + 2G, ... (G = gridDim.x): the engine launches one
+// block per item, which measured faster than a persistent grid of resident
+// blocks looping over the items (the hardware's block dispatch balances the
+// uneven per-item cost of the pass better than a fixed stride), but any grid
+// gives the same results.  A block finds its first item's frame by binary
+// search over the frames' first items and follows the frames along with its
+// (increasing) items; each item then runs the same per-pixel code as the
+// single-frame kernels, for the frame's slot count and op (kFused, kCached or
+// kFill).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void tick_kernel(const TickArgs a)
+template <int K, int OP, bool PER_SLOT = false>
+__device__ __forceinline__ uint32_t process_wave(const FrameDesc& d, uint32_t item, uint32_t wave)
 {
-    if (blockIdx.x >= a.total) return;                // whole block
-    const uint32_t item = a.reverse ? a.total - 1u - blockIdx.x : blockIdx.x;
-    // frame = number of frames f >= 1 with begins[f] <= item; all begins are read
-    // at once (independent scalar loads), no chain of dependent loads
-    uint32_t lo = 0u;
-#pragma unroll
-    for (int f = 1; f < kTickFrames; ++f) lo += ((uint32_t)f < a.n && a.begins[f] <= item) ? 1u : 0u;
-    const FrameDesc& d = a.descs[lo];
-    const uint32_t local = item - a.begins[lo];
-    uint32_t n;
-    if (per_slot_mode(d.bias)) {
-        n = process_item<0, kFused, true>(d, local);
-        if (d.stats) add_stats(d.stats, n);
-        return;
-    }
-    // the frame's op (kFused, kCached or kFill) is uniform: a scalar branch
+    uint32_t x, y;
+    if (!item_pixel_of(d, item, wave, threadIdx.x & 63u, x, y)) return 0u;
+    if constexpr (PER_SLOT) return pixel_per_slot<K, OP>(d, x, y);
+    return pixel<K, OP>(d, x, y);
+}
+
+__device__ __forceinline__ uint32_t tick_item(const FrameDesc& d, uint32_t local, uint32_t wave)
+{
+    if (per_slot_mode(d.bias)) return process_wave<0, kFused, true>(d, local, wave);
+#define FWRS_TICK_OPS(KK)                                                                  \
+    return d.op == kCached ? process_wave<KK, kCached>(d, local, wave)                     \
+         : d.op == kFill ? process_wave<KK, kFill>(d, local, wave) : process_wave<KK, kFused>(d, local, wave)
     switch (d.k) {
-        case 1: n = d.op == kCached ? process_item<1, kCached>(d, local)
-                  : d.op == kFill ? process_item<1, kFill>(d, local) : process_item<1, kFused>(d, local); break;
-        case 2: n = d.op == kCached ? process_item<2, kCached>(d, local)
-                  : d.op == kFill ? process_item<2, kFill>(d, local) : process_item<2, kFused>(d, local); break;
-        case 4: n = d.op == kCached ? process_item<4, kCached>(d, local)
-                  : d.op == kFill ? process_item<4, kFill>(d, local) : process_item<4, kFused>(d, local); break;
-        case 8: n = d.op == kCached ? process_item<8, kCached>(d, local)
-                  : d.op == kFill ? process_item<8, kFill>(d, local) : process_item<8, kFused>(d, local); break;
-        default: n = d.op == kCached ? process_item<0, kCached>(d, local)
-                   : d.op == kFill ? process_item<0, kFill>(d, local) : process_item<0, kFused>(d, local); break;
+        case 1: FWRS_TICK_OPS(1);
+        case 2: FWRS_TICK_OPS(2);
+        case 4: FWRS_TICK_OPS(4);
+        case 8: FWRS_TICK_OPS(8);
+        default: FWRS_TICK_OPS(0);
     }
-    if (d.stats) add_stats(d.stats, n);
+#undef FWRS_TICK_OPS
+}
+
+__global__ __launch_bounds__(kBlock) void tick_kernel(const TickHead* __restrict__ head,
+                                                      const FrameDesc* __restrict__ descs)
+{
+    const uint32_t n = head->n, total = head->total;
+    uint32_t f = 0u;
+    for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+        if (item == blockIdx.x) {
+            uint32_t hi = n - 1u;                        // last frame whose first item <= item
+            while (f < hi) {
+                const uint32_t mid = (f + hi + 1u) >> 1;
+                if (descs[mid].first <= item) f = mid;
+                else hi = mid - 1u;
+            }
+        } else {
+            while (f + 1u < n && descs[f + 1u].first <= item) ++f;
+        }
+        const FrameDesc& d = descs[f];
+        uint32_t local = item - d.first;
+        if (d.rev) local = d.items - 1u - local;
+        const uint32_t v = tick_item(d, local, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+        if (d.stats) add_stats(d.stats, v);
+    }
+}
+
+// Writes descriptors carried as kernel arguments into a tick table.
+__global__ __launch_bounds__(64) void tick_fill_kernel(uint32_t* __restrict__ table, const TickFill f)
+{
+    constexpr uint32_t kDescWords = sizeof(FrameDesc) / 4;
+    static_assert(sizeof(FrameDesc) % 4 == 0, "descriptors are copied as words");
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(f.descs);
+    uint32_t* dst = table + kTickDescOffset / 4 + (size_t)f.at * kDescWords;
+    for (uint32_t i = threadIdx.x; i < f.count * kDescWords; i += blockDim.x) st<0u>(dst + i, src[i]);
+    if (f.write_head && threadIdx.x < 4u) st<0u>(table + threadIdx.x, reinterpret_cast<const uint32_t*>(&f.head)[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1070,10 +1111,18 @@ hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream)
     }
 }
 
-hipError_t launch_tick(const TickArgs& a, hipStream_t stream)
+hipError_t launch_tick(const void* table, uint32_t grid, hipStream_t stream)
 {
-    if (a.total == 0u) return hipSuccess;
-    hipLaunchKernelGGL(tick_kernel, dim3(a.total), dim3(kBlock), 0, stream, a);
+    if (grid == 0u) return hipSuccess;
+    const TickHead* head = static_cast<const TickHead*>(table);
+    const FrameDesc* descs = reinterpret_cast<const FrameDesc*>(static_cast<const char*>(table) + kTickDescOffset);
+    hipLaunchKernelGGL(tick_kernel, dim3(grid), dim3(kBlock), 0, stream, head, descs);
+    return hipGetLastError();
+}
+
+hipError_t launch_tick_fill(void* table, const TickFill& f, hipStream_t stream)
+{
+    hipLaunchKernelGGL(tick_fill_kernel, dim3(1), dim3(64), 0, stream, static_cast<uint32_t*>(table), f);
     return hipGetLastError();
 }
 

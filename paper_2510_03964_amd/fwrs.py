@@ -29,7 +29,7 @@ EXPORTS = (
     "fwrs_destroy", "fwrs_set_stream", "fwrs_reset", "fwrs_push_frame", "fwrs_resolve",
     "fwrs_push_frame_resolve", "fwrs_push_frame_resolve_incremental", "fwrs_push_frame_reproject",
     "fwrs_frame_index", "fwrs_get_state", "fwrs_download_state", "fwrs_get_stats",
-    "fwrs_set_tile", "fwrs_set_resolve_plane_from", "fwrs_sync", "fwrs_strerror", "fwrs_engine_create", "fwrs_engine_tick",
+    "fwrs_set_tile", "fwrs_set_resolve_plane_from", "fwrs_sync", "fwrs_strerror", "fwrs_tick", "fwrs_engine_create", "fwrs_engine_tick",
     "fwrs_engine_set_tile", "fwrs_engine_destroy", "fwrs_foveator_create", "fwrs_foveate",
     "fwrs_push_frame_foveated", "fwrs_foveator_destroy", "fwrs_method_constants", "fwrs_gauss_weights",
 )
@@ -128,6 +128,7 @@ def load(path: str | None = None):
         "fwrs_set_resolve_plane_from": (i, [vp, u32]),
         "fwrs_sync": (i, [vp]),
         "fwrs_strerror": (C.c_char_p, [i]),
+        "fwrs_tick": (i, [C.POINTER(Frame), i, vp]),
         "fwrs_engine_create": (i, [vp, i, i, C.POINTER(vp)]),
         "fwrs_engine_tick": (i, [vp, C.POINTER(Frame), i]),
         "fwrs_engine_set_tile": (i, [vp, C.c_longlong, i, i]),
@@ -396,6 +397,37 @@ class Reservoir:
         _check(self._L.fwrs_sync(self._h), "fwrs_sync")
 
 
+TICK_MAX = 4096
+
+
+def _fill_frames(buf, entries, capacity: int) -> int:
+    """Writes (Reservoir, color, level, gaze_x, gaze_y, out) entries into a ctypes Frame array."""
+    n = 0
+    for (res, color, level, gx, gy, out) in entries:
+        if n >= capacity:
+            raise ValueError("too many frames for one tick")
+        res._check_frame(color, level)
+        res._check_out(out)
+        fr = buf[n]
+        fr.ctx = res.handle
+        fr.color = _ptr(color)
+        fr.level_map = _ptr(level)
+        fr.gaze_x = float(gx)
+        fr.gaze_y = float(gy)
+        fr.out = _ptr(out)
+        n += 1
+    return n
+
+
+def tick(entries, stream=None) -> None:
+    """fwrs_tick: one batched launch advances every entry's context by one frame on `stream`.
+    entries: iterable of (Reservoir, color, level, gaze_x, gaze_y, out)."""
+    entries = list(entries)
+    buf = (Frame * max(1, len(entries)))()
+    n = _fill_frames(buf, entries, TICK_MAX)
+    _check(load().fwrs_tick(buf, n, _stream_handle(stream)), "fwrs_tick")
+
+
 class Engine:
     """Batched ticks: one kernel launch advances many contexts by one frame."""
 
@@ -425,20 +457,7 @@ class Engine:
 
     def tick(self, entries) -> None:
         """entries: iterable of (Reservoir, color, level, gaze_x, gaze_y, out)."""
-        n = 0
-        for (res, color, level, gx, gy, out) in entries:
-            if n >= self.max_frames:
-                raise ValueError("too many frames for this engine")
-            res._check_frame(color, level)
-            res._check_out(out)
-            fr = self._frames[n]
-            fr.ctx = res.handle
-            fr.color = _ptr(color)
-            fr.level_map = _ptr(level)
-            fr.gaze_x = float(gx)
-            fr.gaze_y = float(gy)
-            fr.out = _ptr(out)
-            n += 1
+        n = _fill_frames(self._frames, entries, self.max_frames)
         _check(self._L.fwrs_engine_tick(self._h, self._frames, n), "fwrs_engine_tick")
 
 

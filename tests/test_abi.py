@@ -124,6 +124,14 @@ def test_invalid_arguments_are_rejected_before_any_gpu_work():
     assert L.fwrs_destroy(None) == fwrs.OK
     assert L.fwrs_engine_destroy(None) == fwrs.OK
     assert L.fwrs_engine_create(None, 0, 0, C.byref(h)) == fwrs.E_ARG
+    assert L.fwrs_engine_create(None, 4097, 0, C.byref(h)) == fwrs.E_ARG
+    # fwrs_tick: an empty tick is a no-op; bad sizes and missing frames are rejected
+    frames = (fwrs.Frame * 2)()
+    assert L.fwrs_tick(None, 0, None) == fwrs.OK
+    assert L.fwrs_tick(None, 1, None) == fwrs.E_ARG
+    assert L.fwrs_tick(frames, -1, None) == fwrs.E_ARG
+    assert L.fwrs_tick(frames, 4097, None) == fwrs.E_ARG
+    assert L.fwrs_tick(frames, 2, None) == fwrs.E_ARG          # NULL contexts
     # foveation generator: argument checks come before any device work
     for args in [(0, 32, 5.0, 10.0, 0), (64, 32, 10.0, 5.0, 0), (64, 32, 5.0, 10.0, 7), (64, 32, float("nan"), 10.0, 0),
                  (64, 32, -1.0, 10.0, 0)]:

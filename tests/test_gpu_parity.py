@@ -449,6 +449,79 @@ def test_engine_ticks_over_several_launches(dev, use_graph):
     eng.close()
 
 
+def test_fwrs_tick_equals_plain_calls(dev):
+    """fwrs_tick (the batched call of the boundary) on a mix of sizes, slot counts, bias modes and
+    resolve-plane policies equals one fwrs_push_frame_resolve per entry, bit for bit, every tick;
+    the oracle agrees on every stream at the end."""
+    cases = [(256, 144, 2, fwrs.BIAS_BERNOULLI, 0), (200, 100, 4, fwrs.BIAS_BERNOULLI, None),
+             (96, 64, 8, fwrs.BIAS_BERNOULLI, 1), (37, 23, 3, fwrs.BIAS_NONE, 0), (160, 90, 4, fwrs.BIAS_FULL, None),
+             (64, 48, 4, fwrs.AES, None), (120, 60, 4, fwrs.BIAS_MEMORYLESS, 2), (33, 17, 16, fwrs.BIAS_BERNOULLI, 0)]
+    stream = torch.cuda.current_stream()
+    specs, srcs, tick_ctx, plain_ctx, orcs, outs_t, outs_p = [], [], [], [], [], [], []
+    for i, (w, h, k, bias, res_from) in enumerate(cases):
+        s = synth.StreamSpec(w, h, k, 7, 0.1 * w, 0.25 * w, 2.0, 3, 4.0, stream_id=20 + i)
+        p, q = _params(s, bias)
+        specs.append(s)
+        srcs.append(synth.FrameSource(s, device=dev))
+        tick_ctx.append(fwrs.Reservoir(w, h, k, p, stream=stream))
+        plain_ctx.append(fwrs.Reservoir(w, h, k, p, stream=stream))
+        if res_from is not None:
+            tick_ctx[-1].set_resolve_plane_from(res_from)
+        tick_ctx[-1].set_tile(*[(64, 1), (16, 16), (32, 8)][i % 3])
+        orcs.append(oracle.Oracle(w, h, k, q))
+        outs_t.append(torch.empty((h, w, 3), device=dev))
+        outs_p.append(torch.empty((h, w, 3), device=dev))
+    for t in range(7):
+        frames = [src.frame(t) for src in srcs]
+        fwrs.tick([(tick_ctx[i], *frames[i], outs_t[i]) for i in range(len(cases))], stream=stream)
+        for i in range(len(cases)):
+            plain_ctx[i].step(*frames[i], outs_p[i])
+            c, lev, gx, gy = frames[i]
+            orcs[i].push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+        torch.cuda.synchronize()
+        for i in range(len(cases)):
+            assert torch.equal(outs_t[i], outs_p[i]), f"tick {t} case {cases[i]}"
+    for i in range(len(cases)):
+        assert tick_ctx[i].frame_index == 7
+        _compare_state(tick_ctx[i].download(), plain_ctx[i].download(), f"case {cases[i]}")
+        _compare_state(tick_ctx[i].download(), orcs[i].state(), f"oracle case {cases[i]}")
+        _compare_out(outs_t[i].cpu().numpy(), orcs[i].resolve(), f"case {cases[i]}")
+        assert tick_ctx[i].stats() == plain_ctx[i].stats()
+
+
+@pytest.mark.parametrize("n,w,h", [(300, 24, 8), (48, 256, 256)])
+def test_tick_of_many_frames(dev, n, w, h):
+    """Ticks far beyond the old per-launch frame limit: 300 one-item frames (fewer items than the
+    persistent grid) and 48 frames of 256 items each (more: every block loops), through fwrs_tick and an
+    engine in graph mode, against plain launches, forward and reversed ticks."""
+    stream = torch.cuda.current_stream()
+    specs = [synth.StreamSpec(w, h, (1, 2, 4, 8, 5)[i % 5], 4, 0.2 * w, 0.5 * w, 1.0, 2, 2.0, stream_id=300 + i)
+             for i in range(n)]
+    srcs = [synth.FrameSource(s, device=dev) for s in specs]
+    eng = fwrs.Engine(n, stream=stream, use_graph=True)
+    a, b, c_ = [], [], []
+    for s in specs:
+        p, _ = _params(s)
+        a.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
+        b.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
+        c_.append(fwrs.Reservoir(s.width, s.height, s.k, p, stream=stream))
+    oa = [torch.empty((h, w, 3), device=dev) for _ in specs]
+    ob = [torch.empty((h, w, 3), device=dev) for _ in specs]
+    oc = [torch.empty((h, w, 3), device=dev) for _ in specs]
+    for t in range(4):
+        frames = [src.frame(t) for src in srcs]
+        fwrs.tick([(a[i], *frames[i], oa[i]) for i in range(n)], stream=stream)
+        eng.tick([(b[i], *frames[i], ob[i]) for i in range(n)])
+        for i in range(n):
+            c_[i].step(*frames[i], oc[i])
+    torch.cuda.synchronize()
+    for i in range(n):
+        assert torch.equal(oa[i], oc[i]) and torch.equal(ob[i], oc[i]), f"frame {i}"
+        assert a[i].stats() == c_[i].stats() and b[i].stats() == c_[i].stats()
+    _compare_state(a[n // 2].download(), c_[n // 2].download(), "middle context")
+    eng.close()
+
+
 def test_engine_stream_alone_equals_stream_in_mix(dev):
     specs = _mix_specs()
     stream = torch.cuda.current_stream()
