@@ -360,6 +360,21 @@ typedef struct fwrs_frame {
  * ordering failed (the tick ran and every context advanced). */
 int fwrs_tick(const fwrs_frame* frames, int n, void* hip_stream);
 
+/* fwrs_tick for callers that cannot allocate device or pinned memory (code
+ * that must not call hipMalloc: under HIP graph capture, in tight serving
+ * loops, or in harnesses that forbid it).  Same arguments and results as
+ * fwrs_tick, for at most 256 entries (FWRS_E_ARG beyond, before any device
+ * work).  The descriptor table lives in a fixed 43 KB array in device memory
+ * that the library holds for the process's lifetime -- one per GPU, shared by
+ * every call on that GPU -- and is written by small kernels whose arguments
+ * carry the descriptors, on hip_stream, before the batched kernel: a call
+ * allocates nothing and copies nothing from host memory.  Calls on one GPU
+ * must not overlap: a call on another stream while an earlier one may still
+ * run races on the shared table (calls on one stream are ordered by it).
+ * Unlike fwrs_tick it does not order the tick against the contexts' own
+ * streams: the caller does.  Other errors as fwrs_tick. */
+int fwrs_tick_noalloc(const fwrs_frame* frames, int n, void* hip_stream);
+
 /* An engine: fwrs_tick with its own ring, a fixed stream, a tile table per
  * resolution class and optionally HIP graphs. */
 typedef struct fwrs_engine fwrs_engine;

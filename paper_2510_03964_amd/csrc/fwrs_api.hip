@@ -824,17 +824,26 @@ hipError_t slot_graph(TickSlot& sl, size_t bytes, uint32_t grid)
 // contexts' frame counts.  Every context's frame enters the state of the
 // tick's launch or of none: on FWRS_E_HIP no context has advanced, except that
 // if only the final cross-stream ordering failed the tick ran and they did.
-int engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n, hipStream_t stream)
+// The checks every batched call makes before any device work: FWRS_OK, or the
+// status to return.
+int check_tick(const fwrs_frame* frames, int n, int max_frames, int device)
 {
-    if (n < 0 || n > e->max_frames || (n > 0 && !frames)) return FWRS_E_ARG;
+    if (n < 0 || n > max_frames || (n > 0 && !frames)) return FWRS_E_ARG;
     for (int i = 0; i < n; ++i) {
         const fwrs_frame& f = frames[i];
         if (!f.ctx || !f.color || !f.level_map || !f.out || !gaze_ok(f.gaze_x, f.gaze_y)) return FWRS_E_ARG;
-        if (f.ctx->device != e->device) return FWRS_E_ARG;
+        if (f.ctx->device != device) return FWRS_E_ARG;
         if (f.ctx->t == 0xFFFFFFFFu || f.ctx->reproject) return FWRS_E_STATE;
         for (int j = 0; j < i; ++j)
             if (frames[j].ctx == f.ctx) return FWRS_E_ARG;
     }
+    return FWRS_OK;
+}
+
+int engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n, hipStream_t stream)
+{
+    const int rc = check_tick(frames, n, e->max_frames, e->device);
+    if (rc != FWRS_OK) return rc;
     if (n == 0) return FWRS_OK;
     DeviceGuard g(e->device);
     if (!g.ok) return FWRS_E_HIP;
@@ -994,6 +1003,108 @@ int fwrs_tick(const fwrs_frame* frames, int n, void* hip_stream)
         e = made;
     }
     return engine_tick(e, frames, n, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// fwrs_tick_noalloc: fwrs_tick for callers that cannot allocate.  Its tick
+// table lives in `scratch`, a file-scope device array (each GPU holds its own
+// copy until the process ends), and is written by fill kernels whose
+// arguments carry the descriptors, so a call allocates nothing and copies
+// nothing from host memory.  In host code `scratch` names no device address:
+// each device's address comes from hipGetSymbolAddress (once per device, with
+// that device current) and only that address is used.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kStaticTickFrames = 256;
+constexpr size_t kStaticTickBytes = fwrs::kTickDescOffset + kStaticTickFrames * sizeof(FrameDesc);
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticTickBytes];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+void* g_scratch[kMaxDevices] = {};      // each device's address of `scratch`
+uint32_t g_scratch_ticks[kMaxDevices] = {};
+
+// The address of `scratch` on device `dev` (the current device): looked up on
+// the first call on that device.
+hipError_t scratch_table(int dev, void** out)
+{
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (err != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return err != hipSuccess ? err : hipErrorInvalidSymbol;
+        }
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwrs_tick_noalloc(const fwrs_frame* frames, int n, void* hip_stream)
+{
+    if (n > kStaticTickFrames) return FWRS_E_ARG;
+    if (n < 0 || (n > 0 && (!frames || !frames[0].ctx))) return FWRS_E_ARG;
+    if (n == 0) return FWRS_OK;
+    const int dev = frames[0].ctx->device;
+    if (dev < 0 || dev >= kMaxDevices) return FWRS_E_ARG;
+    const int rc = check_tick(frames, n, kStaticTickFrames, dev);
+    if (rc != FWRS_OK) return rc;
+    hipStream_t stream = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    DeviceGuard g(dev);
+    if (!g.ok) return FWRS_E_HIP;
+    void* table = nullptr;
+    if (scratch_table(dev, &table) != hipSuccess) return FWRS_E_HIP;
+    // the tick's layout (as in fwrs_tick: every other call on a device runs backwards)
+    const bool reverse = (g_scratch_ticks[dev] & 1u) != 0u;
+    int ops[kStaticTickFrames];
+    fwrs::TickFill fill{};
+    fill.head.n = (uint32_t)n;
+    for (int slot_i = 0; slot_i < n; ++slot_i) {
+        const fwrs_frame& f = frames[reverse ? n - 1 - slot_i : slot_i];
+        fill.head.total += make_desc(f.ctx, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, f.ctx->tile_x,
+                                     f.ctx->tile_y).items;
+    }
+    // the descriptors, kFillFrames per fill launch, then the batched kernel
+    hipError_t err = hipSuccess;
+    uint32_t first = 0;
+    for (int at = 0; at < n && err == hipSuccess; at += fwrs::kFillFrames) {
+        fill.at = (uint32_t)at;
+        fill.count = (uint32_t)std::min(fwrs::kFillFrames, n - at);
+        fill.write_head = at == 0 ? 1u : 0u;
+        for (uint32_t c = 0; c < fill.count; ++c) {
+            const int i = reverse ? n - 1 - (at + (int)c) : at + (int)c;
+            const fwrs_frame& f = frames[i];
+            FrameDesc& d = fill.descs[c];
+            d = make_desc(f.ctx, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, f.ctx->tile_x, f.ctx->tile_y);
+            ops[i] = fused_op(f.ctx);
+            d.op = (uint32_t)ops[i];
+            d.first = first;
+            d.rev = reverse ? 1u : 0u;
+            first += d.items;
+        }
+        err = fwrs::launch_tick_fill(table, fill, stream);
+    }
+    if (err == hipSuccess) err = fwrs::launch_tick(table, fill.head.total, stream);
+    if (err != hipSuccess) {
+        (void)hipGetLastError();
+        return FWRS_E_HIP;
+    }
+    g_scratch_ticks[dev] += 1u;
+    for (int i = 0; i < n; ++i) advance(frames[i].ctx, ops[i], frames[i].out);
+    return FWRS_OK;
 }
 
 }  // extern "C"

@@ -29,7 +29,7 @@ EXPORTS = (
     "fwrs_destroy", "fwrs_set_stream", "fwrs_reset", "fwrs_push_frame", "fwrs_resolve",
     "fwrs_push_frame_resolve", "fwrs_push_frame_resolve_incremental", "fwrs_push_frame_reproject",
     "fwrs_frame_index", "fwrs_get_state", "fwrs_download_state", "fwrs_get_stats",
-    "fwrs_set_tile", "fwrs_set_resolve_plane_from", "fwrs_sync", "fwrs_strerror", "fwrs_tick", "fwrs_engine_create", "fwrs_engine_tick",
+    "fwrs_set_tile", "fwrs_set_resolve_plane_from", "fwrs_sync", "fwrs_strerror", "fwrs_tick", "fwrs_tick_noalloc", "fwrs_engine_create", "fwrs_engine_tick",
     "fwrs_engine_set_tile", "fwrs_engine_destroy", "fwrs_foveator_create", "fwrs_foveate",
     "fwrs_push_frame_foveated", "fwrs_foveator_destroy", "fwrs_method_constants", "fwrs_gauss_weights",
 )
@@ -129,6 +129,7 @@ def load(path: str | None = None):
         "fwrs_sync": (i, [vp]),
         "fwrs_strerror": (C.c_char_p, [i]),
         "fwrs_tick": (i, [C.POINTER(Frame), i, vp]),
+        "fwrs_tick_noalloc": (i, [C.POINTER(Frame), i, vp]),
         "fwrs_engine_create": (i, [vp, i, i, C.POINTER(vp)]),
         "fwrs_engine_tick": (i, [vp, C.POINTER(Frame), i]),
         "fwrs_engine_set_tile": (i, [vp, C.c_longlong, i, i]),
@@ -426,6 +427,20 @@ def tick(entries, stream=None) -> None:
     buf = (Frame * max(1, len(entries)))()
     n = _fill_frames(buf, entries, TICK_MAX)
     _check(load().fwrs_tick(buf, n, _stream_handle(stream)), "fwrs_tick")
+
+
+TICK_NOALLOC_MAX = 256
+
+
+def tick_noalloc(entries, stream=None) -> None:
+    """fwrs_tick_noalloc: fwrs_tick through the library's fixed device table (at most 256
+    entries; allocates nothing).  The caller orders the tick against the contexts' streams."""
+    entries = list(entries)
+    if len(entries) > TICK_NOALLOC_MAX:
+        raise ValueError(f"at most {TICK_NOALLOC_MAX} entries per fwrs_tick_noalloc call")
+    buf = (Frame * max(1, len(entries)))()
+    n = _fill_frames(buf, entries, TICK_NOALLOC_MAX)
+    _check(load().fwrs_tick_noalloc(buf, n, _stream_handle(stream)), "fwrs_tick_noalloc")
 
 
 class Engine:
