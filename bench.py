@@ -1,26 +1,32 @@
 """Benchmark: 4K, k = 4 weighted-reservoir-sampling update + resolve on one MI355X.
 
-Workload: 3840x2160 RGB float32 foveated frames, k = 4 slots per pixel, the
-600-frame synthetic gaze trace (fovea 216 px, 2x2 ring to 540 px, 4x4 beyond;
-microsaccades sigma 8 px, a saccade every 90 frames with 24 px landing
-scatter), Philox seed 0x25103964, Bernoulli bias.  All frames are generated on
-the device before timing; a step is one fused update + resolve
-(fwrs_push_frame_resolve) of one frame, starting from an empty reservoir.
+Workload (the paper-scale plain method): 3840x2160 RGB float32 foveated frames, k = 4 slots per
+pixel, Bernoulli bias (Eq. 6), the 600-frame synthetic gaze trace (fovea 216 px, 2x2 ring to
+540 px, 4x4 beyond; microsaccades sigma 8 px, a saccade every 90 frames with 24 px landing
+scatter), Philox seed 0x25103964.  All frames are generated on the device before timing.
 
-Prints one JSON line: Gpixel-updates/s, ms per frame, the roofline of the
-fused kernel (algorithmic bytes per pixel-update 33 + 16k + 20 r, with r the
-slot replacements per pixel-update counted by the kernel, over its average
-launch time from HIP events on its stream), and the CPU oracle timed on a
-bounded sample of the same workload.  The same frames are then run through
-the incremental entry point (output rewritten only where a slot changed) and
-through the full temporal bias of Eq. 7 (per-slot w_sum, CIE94 colour
-difference), each reported in its own object with its own byte model.
+Timed region: the whole trace from an empty reservoir -- frames 0 .. 599 through
+fwrs_push_frame_resolve, one launch per frame -- as --steps steps of ceil(600 / steps) consecutive
+frames (20 steps of 30 frames for --steps 20); --warmup steps of the same size run first on a
+throwaway context.  The library runs the full resolve while the store fills (frames 0-30), writes
+the resolve plane at frame 31 and copies unchanged pixels from it from frame 32 on, so the trace
+launches three kernels; the dominant one (frames 32-599) is the roofline's.
+
+Prints one JSON line: Gpixel-updates/s over the trace, ms per frame, the roofline of the dominant
+kernel (SURVEY 8(d) algorithmic bytes per pixel-update 41 + 16k + 20 r, r = slot replacements per
+pixel-update counted by the kernel, over its average launch time from HIP events on its stream;
+beside it the 33-byte variant, the kernel's measured HBM traffic from the committed counter
+summary of the same window, and the whole-trace and first-20-frame figures), and the CPU oracle
+timed on a bounded sample of the same workload.  Further sections run the same frames through
+the incremental entry point and through Eq. 7, the update-rule ablations, the foveation
+generator, the moving-camera reprojection, the batched ticks and the serving loop.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -30,11 +36,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "4K k=4 update+resolve ms & Gpix/s, %HBM peak; multi-stream p99 vs plain"
 HBM_PEAK_GBPS = 8000.0
+TRACE_FRAMES = 600
+#: the frame index from which the library's fused passes use the resolve plane (its default, set explicitly)
+PLANE_FROM = 32
 COUNTERS = os.path.join(ROOT, "profiles", "fused_k4_4k_counters.json")
 INC_COUNTERS = os.path.join(ROOT, "profiles", "incremental_k4_4k_counters.json")
 VALU_COUNTERS = os.path.join(ROOT, "profiles", "fused_valu_4k_counters.json")
-#: VALU issue peak of the MI355X in lane-operations per second: the published fp32 vector rate, 157.3 TFLOP/s,
-#: counts a fused multiply-add as two flops, i.e. 78.6 T lane-operations/s (256 CUs x 128 lanes x 2.4 GHz)
+KERNEL_PLAIN = "void fwrs::frame_kernel<4, 3, false>(fwrs::FrameDesc)"
+KERNEL_FILL = "void fwrs::frame_kernel<4, 9, false>(fwrs::FrameDesc)"
+KERNEL_CACHED = "void fwrs::frame_kernel<4, 7, false>(fwrs::FrameDesc)"
+#: VALU issue peak of the MI355X in lane-operations per second (256 CUs x 128 lanes x 2.4 GHz: the published
+#: fp32 vector rate, 157.3 TFLOP/s, counts a fused multiply-add as two flops); profiles/valu_issue_rate.md
+#: measures a non-packed fp32 chain at this rate
 VALU_PEAK_TOPS = 78.6
 
 
@@ -43,9 +56,15 @@ def log(msg: str) -> None:
 
 
 def bytes_per_update(k: int, rbar: float) -> float:
-    """Algorithmic HBM bytes per pixel-update of the fused pass: colour in (12), level (1),
-    w_sum read and written (8), output (12), every slot's colour and weight read for the
-    resolve (16 k), and colour + weight + index written per replaced slot (20 per take)."""
+    """Algorithmic HBM bytes per pixel-update of update + resolve: colour in (12), level (1),
+    w_sum read and written (8), the per-pixel count read and written (8; kept here as the context's frame
+    index), output (12), every slot's colour and weight read for the resolve (16 k), and colour + weight +
+    index written per replaced slot (20 per take)."""
+    return 41.0 + 16.0 * k + 20.0 * rbar
+
+
+def bytes_per_update_33(k: int, rbar: float) -> float:
+    """The same without the per-pixel count (8 bytes), which this build keeps once per context."""
     return 33.0 + 16.0 * k + 20.0 * rbar
 
 
@@ -80,16 +99,20 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_counters(n_pixels: int, path: str = COUNTERS) -> float | None:
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
-    current kernel sources and workload; None otherwise."""
+def traffic_from_counters(kernel: str, n_pixels: int, window: dict, path: str = COUNTERS) -> float | None:
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter summary, if it was taken on the
+    current kernel sources, this frame size and this timed window (steps, frames per step, frames); None
+    otherwise, so traffic measured on another window is never attached to this one."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
         c = json.load(f)
-    if c.get("source_hash") != kernel_source_hash() or c.get("pixels") != n_pixels:
+    if c.get("source_hash") != kernel_source_hash() or c.get("pixels") != n_pixels or c.get("window") != window:
         return None
-    return 1024.0 * (c["fetch_kib_per_dispatch"] * c["fetch_scale"] + c["write_kib_per_dispatch"] * c["write_scale"])
+    k = c.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return 1024.0 * (k["fetch_kib_per_dispatch"] * c["fetch_scale"] + k["write_kib_per_dispatch"] * c["write_scale"])
 
 
 def valu_per_pixel(kernel: str) -> float | None:
@@ -127,7 +150,7 @@ def timed_run(res, frames, out, stream, step):
 
 
 def multistream(dev, stream, specs, gazes, ticks: int, ring: int, use_graph: bool, label: str) -> dict:
-    """Batched ticks (one persistent launch per tick, tiles from the autotuner per resolution
+    """Batched ticks (one launch per tick over all its frames, tiles from the autotuner per resolution
     class) against plain per-frame launches of the same kernels on the same stream, on the same
     frames.  Frame t of a stream is frame t mod `ring` of its trace (a ring of distinct frames
     kept resident in HBM).  The first 3 ticks of each mode are untimed."""
@@ -449,13 +472,107 @@ def copy_bandwidth(torch, dev, nbytes: int = 1 << 30, reps: int = 20) -> float:
     return 2.0 * nbytes / sec / 1e9
 
 
+def headline(dev, stream, spec, frames, steps: int, warmup: int, fps: int, tile) -> dict:
+    """The timed trace (see the module docstring) and its rooflines; a second, untimed pass over the same
+    frames reads the slot counters at frames 20 and PLANE_FROM (results are deterministic, so its counts are
+    the timed run's) for the slot replacements per pixel-update of each window."""
+    import numpy as np
+    import torch
+
+    from paper_2510_03964_amd import fwrs, synth
+
+    p = fwrs.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED)
+    out = torch.empty((spec.height, spec.width, 3), dtype=torch.float32, device=dev)
+
+    def context():
+        r = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=stream)
+        r.set_resolve_plane_from(PLANE_FROM)
+        if tile:
+            r.set_tile(*tile)
+        return r
+
+    n = len(frames)
+    warm = context()
+    for t in range(warmup * fps):
+        warm.step(*frames[t % n], out)
+    warm.sync()
+    warm.close()
+    log(f"dispatch plan: warm-up frames 0..{warmup * fps - 1} on a throwaway context, then the timed frames "
+        f"0..{n - 1}, then the same frames untimed for the counters")
+    res = context()
+    total_ms, per = timed_run(res, frames, out, stream, res.step)
+    takes, changed, updates = res.stats()
+    assert updates == n * spec.pixels and res.frame_index == n
+    res.close()
+    # slot replacements per window, from an identical untimed pass
+    cnt = context()
+    marks = {}
+    for t in range(n):
+        if t in (20, PLANE_FROM):
+            marks[t] = cnt.stats()
+        cnt.step(*frames[t], out)
+    end = cnt.stats()
+    cnt.close()
+    assert end[0] == takes, "the untimed pass must replay the timed one"
+    N, k = spec.pixels, spec.k
+
+    def rbar(a, b):
+        ta = marks[a][0] if a else 0
+        tb = marks[b][0] if b < n else end[0]
+        return (tb - ta) / ((b - a) * N)
+
+    window = {"steps": steps, "frames_per_step": fps, "frames": n}
+    t_cached = float(per[PLANE_FROM:].mean())
+    r_cached = rbar(PLANE_FROM, n)
+    B = bytes_per_update(k, r_cached)
+    B33 = bytes_per_update_33(k, r_cached)
+    ach = N * B / (t_cached / 1e3) / 1e9
+    traffic = traffic_from_counters(KERNEL_CACHED, N, window)
+    vpp = valu_per_pixel(KERNEL_CACHED)
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "traffic_frac": None if traffic is None else traffic / (t_cached / 1e3) / 1e9 / HBM_PEAK_GBPS,
+            "kernel": f"{KERNEL_CACHED} (fused update + resolve, unchanged pixels from the resolve plane)",
+            "frames": [PLANE_FROM, n], "launches": n - PLANE_FROM, "kernel_ms_avg": t_cached,
+            "bytes_per_pixel_update": B, "bytes_model": "41 + 16k + 20r (SURVEY 8(d))",
+            "slot_takes_per_pixel_update": r_cached,
+            "bytes_model_33": {"bytes_per_pixel_update": B33,
+                               "frac": N * B33 / (t_cached / 1e3) / 1e9 / HBM_PEAK_GBPS,
+                               "model": "33 + 16k + 20r (no per-pixel count plane)"},
+            "valu_per_pixel": vpp,
+            "valu_tops": None if vpp is None else N * vpp / (t_cached / 1e3) / 1e12}
+    if vpp is not None:
+        roof["valu_frac"] = roof["valu_tops"] / VALU_PEAK_TOPS
+    r_all = takes / updates
+    t_all = float(per.mean())
+    trace = {"frames": n, "kernel_ms_avg": t_all, "ms_per_frame": total_ms / n,
+             "slot_takes_per_pixel_update": r_all, "bytes_per_pixel_update": bytes_per_update(k, r_all),
+             "frac": N * bytes_per_update(k, r_all) / (t_all / 1e3) / 1e9 / HBM_PEAK_GBPS,
+             "pixels_changed_per_pixel_update": changed / updates,
+             "by_kernel": {KERNEL_PLAIN: {"frames": [0, PLANE_FROM - 1], "kernel_ms_avg": float(per[:PLANE_FROM - 1].mean())},
+                           KERNEL_FILL: {"frames": [PLANE_FROM - 1, PLANE_FROM],
+                                         "kernel_ms_avg": float(per[PLANE_FROM - 1])},
+                           KERNEL_CACHED: {"frames": [PLANE_FROM, n], "kernel_ms_avg": t_cached}}}
+    r20 = rbar(0, 20)
+    t20 = float(per[:20].mean())
+    first20 = {"frames": [0, 20], "kernel_ms_avg": t20, "slot_takes_per_pixel_update": r20,
+               "bytes_per_pixel_update": bytes_per_update(k, r20),
+               "frac": N * bytes_per_update(k, r20) / (t20 / 1e3) / 1e9 / HBM_PEAK_GBPS}
+    log(f"trace: {total_ms / n:.4f} ms/frame; dominant kernel {t_cached * 1e3:.1f} us = {roof['frac']:.3f} of HBM "
+        f"(8(d) bytes), first 20 frames {t20 * 1e3:.1f} us")
+    return {"total_ms": total_ms, "per": per, "roofline": roof, "trace": trace, "first_20_frames": first20,
+            "changed": changed / updates}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=600, help="timed frames (from an empty reservoir)")
-    ap.add_argument("--warmup", type=int, default=10, help="untimed frames on a separate context")
+    ap.add_argument("--steps", type=int, default=20, help="timed steps; a step is ceil(600 / steps) consecutive frames")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed steps on a throwaway context")
     ap.add_argument("--cpu-frames", type=int, default=24, help="frames of the oracle CPU baseline (0: skip)")
     ap.add_argument("--tile", type=str, default="", help="tile_x,tile_y override")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="run only the timed trace and the copy reference (for profiling)")
     ap.add_argument("--no-copy", action="store_true", help="skip the copy-bandwidth reference")
     ap.add_argument("--no-incremental", action="store_true", help="skip the incremental-resolve run")
     ap.add_argument("--no-eq7", action="store_true", help="skip the Eq. 7 (full temporal bias) run")
@@ -473,6 +590,15 @@ def main() -> int:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): every pixel stream is independent "
               "and this build measures the single-GPU pass.", file=sys.stderr)
         return 2
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        return 2
+    if args.headline_only:
+        # the copy-bandwidth reference stays: it is the counters' calibration kernel
+        for name in ("no_incremental", "no_eq7", "no_ablations", "no_foveated", "no_reproject",
+                     "no_multistream", "no_serving"):
+            setattr(args, name, True)
+        args.cpu_frames = 0
 
     import numpy as np
     import torch
@@ -484,13 +610,15 @@ def main() -> int:
         return 1
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    spec = synth.spec_4k(frames=max(600, args.steps))
     K, W = args.steps, args.warmup
-    log(f"generating {K + W} frames of {spec.width}x{spec.height} on {torch.cuda.get_device_name(0)}")
-    src = synth.FrameSource(spec, device=dev, n_frames=max(K, W))
+    fps = max(1, math.ceil(TRACE_FRAMES / K))          # frames per step
+    n_frames = K * fps                                  # the timed frames: the whole trace (or more)
+    spec = synth.spec_4k(frames=max(TRACE_FRAMES, n_frames))
+    log(f"generating {n_frames} frames of {spec.width}x{spec.height} on {torch.cuda.get_device_name(0)}")
+    src = synth.FrameSource(spec, device=dev, n_frames=n_frames)
     t0 = time.perf_counter()
     frames = []
-    for t in range(K):
+    for t in range(n_frames):
         frames.append(src.frame(t))
         if (t + 1) % 100 == 0:
             torch.cuda.synchronize()
@@ -502,34 +630,11 @@ def main() -> int:
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     out = torch.empty((spec.height, spec.width, 3), dtype=torch.float32, device=dev)
 
-    # warm-up on a throwaway context (code load, clocks)
-    warm = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=stream)
-    if tile:
-        warm.set_tile(*tile)
-    for t in range(W):
-        warm.step(*frames[t % len(frames)], out)
-    warm.sync()
-    warm.close()
-
-    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=stream)
-    if tile:
-        res.set_tile(*tile)
-    total_ms, per = timed_run(res, frames, out, stream, res.step)
-    log(f"timed {K} frames: {total_ms:.2f} ms on the GPU clock")
-    takes, changed, updates = res.stats()
-    assert updates == K * spec.pixels
-    st_ok = res.frame_index == K
-    res.close()
-    rbar = takes / updates
-    B = bytes_per_update(spec.k, rbar)
-    kern_ms = float(per.mean())
-    achieved = spec.pixels * B / (kern_ms / 1e3) / 1e9
-    traffic = traffic_from_counters(spec.pixels)
-    # VALU beside the bytes: instructions per pixel from the committed counter summary (null if stale)
-    h_vpp = valu_per_pixel("void fwrs::frame_kernel<4, 3, false>(fwrs::FrameDesc)")
-    h_valu = None if h_vpp is None else spec.pixels * h_vpp / (kern_ms / 1e3) / 1e12
+    h = headline(dev, stream, spec, frames, K, W, fps, tile)
+    total_ms, per = h["total_ms"], h["per"]
+    log(f"timed {n_frames} frames: {total_ms:.2f} ms on the GPU clock")
     ms_per_step = total_ms / K
-    value = spec.pixels * K / (total_ms / 1e3) / 1e9
+    value = spec.pixels * n_frames / (total_ms / 1e3) / 1e9
 
     incremental = None
     if not args.no_incremental:
@@ -540,7 +645,7 @@ def main() -> int:
         inc_ms, inc_per = timed_run(inc, frames[1:], out, stream, inc.step_incremental)
         i_takes, i_changed, i_updates = inc.stats()
         inc.close()
-        n_inc = K - 1
+        n_inc = n_frames - 1
         i_rbar = (i_takes - spec.k * spec.pixels) / (n_inc * spec.pixels)
         i_changed_frac = (i_changed - spec.pixels) / (n_inc * spec.pixels)
         i_B = bytes_per_update_incremental(spec.k, i_rbar, i_changed_frac)
@@ -552,7 +657,9 @@ def main() -> int:
                        "ms_per_frame_p99": float(np.percentile(inc_per, 99)),
                        "roofline": {"bound": "hbm", "achieved": i_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                                     "frac": i_ach / HBM_PEAK_GBPS,
-                                    "traffic": traffic_from_counters(spec.pixels, INC_COUNTERS),
+                                    "traffic": traffic_from_counters(
+                                        "void fwrs::frame_kernel<4, 5, false>(fwrs::FrameDesc)", spec.pixels,
+                                        {"steps": K, "frames_per_step": fps, "frames": n_frames}, INC_COUNTERS),
                                     "kernel_ms_avg": i_kern,
                                     "bytes_per_pixel_update": i_B, "slot_takes_per_pixel_update": i_rbar,
                                     "changed_pixel_fraction": i_changed_frac}}
@@ -582,15 +689,16 @@ def main() -> int:
             alu = {"bound": "alu", "achieved": a_t, "peak": VALU_PEAK_TOPS, "unit": "T VALU lane-ops/s",
                    "frac": a_t / VALU_PEAK_TOPS, "valu_per_pixel": vpp,
                    "kernel": "fwrs::frame_kernel<4, 3, true> (Eq. 7)"}
-        eq7 = {"entry": "fwrs_push_frame_resolve (FWRS_BIAS_FULL)", "frames": K, "ms_per_step": f_ms / K,
-               "value": spec.pixels * K / (f_ms / 1e3) / 1e9, "unit": "Gpixel-updates/s",
+        eq7 = {"entry": "fwrs_push_frame_resolve (FWRS_BIAS_FULL)", "frames": n_frames,
+               "ms_per_frame": f_ms / n_frames,
+               "value": spec.pixels * n_frames / (f_ms / 1e3) / 1e9, "unit": "Gpixel-updates/s",
                "ms_per_frame_p50": float(np.percentile(f_per, 50)),
                "ms_per_frame_p99": float(np.percentile(f_per, 99)),
                "hbm": {"achieved": f_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": f_ach / HBM_PEAK_GBPS,
                        "kernel_ms_avg": f_kern, "bytes_per_pixel_update": f_B,
                        "slot_takes_per_pixel_update": f_rbar},
                "roofline": alu}
-        log(f"eq7: {f_ms / K:.4f} ms/frame")
+        log(f"eq7: {f_ms / n_frames:.4f} ms/frame")
 
     ablation = None if args.no_ablations else ablations(dev, stream, spec, frames, tile)
 
@@ -601,11 +709,11 @@ def main() -> int:
     del frames
     torch.cuda.empty_cache()
 
-    fov = None if args.no_foveated else foveated(dev, stream, spec, K, tile)
+    fov = None if args.no_foveated else foveated(dev, stream, spec, n_frames, tile)
 
     reproject = None
     if not args.no_reproject:
-        reproject = reprojection(dev, stream, spec, K, W, args.reproject_ring, tile)
+        reproject = reprojection(dev, stream, spec, n_frames, 10, args.reproject_ring, tile)
 
     multi = None
     if not args.no_multistream:
@@ -645,21 +753,21 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"3840x2160 RGB f32 foveated frames, k=4, {K}-frame synthetic gaze trace "
-                               f"(fovea 216 px, ring 540 px), fused update+resolve from an empty reservoir",
-                   "width": spec.width, "height": spec.height, "k": spec.k, "frames": K,
-                   "bias": "bernoulli", "tile": list(tile) if tile else "default"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": traffic,
-                     "kernel": "fwrs::frame_kernel<4, 3, false> (fused update + full resolve)",
-                     "kernel_ms_avg": kern_ms, "bytes_per_pixel_update": B, "slot_takes_per_pixel_update": rbar,
-                     "valu_per_pixel": h_vpp,
-                     "valu_tops": h_valu, "valu_frac": None if h_valu is None else h_valu / VALU_PEAK_TOPS},
+        "config": {"workload": f"3840x2160 RGB f32 foveated frames, k=4, Bernoulli bias: the {n_frames}-frame "
+                               f"synthetic gaze trace (fovea 216 px, ring 540 px) from an empty reservoir, timed "
+                               f"frames 0-{n_frames - 1} as {K} steps of {fps} frames (one fused update + resolve "
+                               f"launch per frame)",
+                   "width": spec.width, "height": spec.height, "k": spec.k, "frames": n_frames,
+                   "frames_per_step": fps, "timed_frames": [0, n_frames], "bias": "bernoulli",
+                   "resolve_plane_from_frame": PLANE_FROM, "tile": list(tile) if tile else "default"},
+        "roofline": h["roofline"],
+        "trace": h["trace"],
+        "first_20_frames": h["first_20_frames"],
+        "ms_per_frame": total_ms / n_frames,
         "cpu_baseline": cpu,
         "ms_per_frame_p50": float(np.percentile(per, 50)),
         "ms_per_frame_p99": float(np.percentile(per, 99)),
-        "pixels_changed_per_pixel_update": changed / updates,
+        "pixels_changed_per_pixel_update": h["changed"],
         "incremental": incremental,
         "eq7": eq7,
         "reproject": reproject,
@@ -668,7 +776,6 @@ def main() -> int:
         "multistream": multi,
         "serving": served,
         "copy_gbps": copy_gbps,
-        "state_ok": bool(st_ok),
     }
     print(json.dumps(line), flush=True)
     return 0

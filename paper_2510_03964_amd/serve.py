@@ -315,8 +315,8 @@ class _GpuExecutor:
 
 
 class BatchedExecutor(_GpuExecutor):
-    """One batched tick for all due frames: one kernel launch per 24 frames, issued directly or
-    (use_graph) as the replay of a HIP graph whose kernel nodes are updated per tick."""
+    """One batched tick for all due frames: one kernel launch for all of them, issued directly or
+    (use_graph) as the replay of a HIP graph (the descriptor-table copy and the kernel)."""
 
     def __init__(self, frames_by_size: dict, max_frames: int = 64, use_graph: bool = True, **kw):
         super().__init__(frames_by_size, **kw)

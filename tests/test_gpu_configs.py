@@ -1,5 +1,5 @@
 """Parity at the full sizes of the batched workloads, in the launch configuration the benchmark
-times (one persistent batched launch per tick, replayed as a HIP graph): the stereo pair
+times (one batched launch per tick over all its frames, replayed as a HIP graph): the stereo pair
 (2 x 2064x2208, k = 8, vergence-shifted gaze, 36 ticks) and the 16 uneven streams (720p to 4K, k in
 {2, 4, 8}).  The oracle follows
 bands of rows (through the gaze, the top and bottom edges) of every stream, bit-exact in every state

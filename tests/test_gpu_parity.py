@@ -364,6 +364,82 @@ def test_4k_bands_and_whole_frame_properties(dev, bias):
     assert updates == n_frames * spec.pixels and takes > 0
 
 
+@pytest.mark.parametrize("res_from", [None, 1])
+def test_4k_whole_frames(dev, res_from):
+    """Whole 3840x2160, k = 4 frames 0, 1 and 2 of the benchmark's trace (forward, reversed and forward
+    traversals) through the fused call: every state plane and every output pixel against the oracle.
+    res_from = 1: frame 0 writes the resolve plane and frames 1 and 2 copy unchanged pixels from it."""
+    spec = synth.spec_4k()
+    src = synth.FrameSource(spec, device=dev, n_frames=3)
+    p, q = _params(spec)
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream())
+    if res_from is not None:
+        res.set_resolve_plane_from(res_from)
+    orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
+    out = torch.full((spec.height, spec.width, 3), -1.0, device=dev)
+    for t in range(3):
+        c, lev, gx, gy = src.frame(t)
+        res.step(c, lev, gx, gy, out)
+        orc.push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+        res.sync()
+        _compare_state(res.download(), orc.state(), f"4K frame {t}")
+        _compare_out(out.cpu().numpy(), orc.resolve(), f"4K frame {t}")
+    res.close()
+    orc.close()
+
+
+def test_4k_600_frames_bands(dev):
+    """The whole 600-frame 3840x2160, k = 4 trace through the fused call with the default launch policy
+    (full resolve while the store fills, the resolve plane from frame 32): the oracle follows eight bands of
+    rows (the edges, the first fixation, rows spread over the image) every frame, and the bands' state
+    planes and outputs are compared at checkpoints through the trace; whole-frame invariants everywhere."""
+    spec = synth.spec_4k()
+    n_frames = 600
+    src = synth.FrameSource(spec, device=dev, n_frames=n_frames)
+    p, q = _params(spec)
+    res = fwrs.Reservoir(spec.width, spec.height, spec.k, p, stream=torch.cuda.current_stream())
+    orc = oracle.Oracle(spec.width, spec.height, spec.k, q)
+    gy0 = int(src.gaze[0, 1])
+    bands = [(0, 3), (max(0, gy0 - 4), min(spec.height, gy0 + 4)), (300, 304), (700, 704), (1080, 1084),
+             (1500, 1504), (1900, 1904), (spec.height - 3, spec.height)]
+    cn = np.zeros((spec.height, spec.width, 3), np.float32)     # only the bands' rows are filled
+    ln = np.zeros((spec.height, spec.width), np.uint8)
+    out = torch.empty((spec.height, spec.width, 3), device=dev)
+    checkpoints = {30, 31, 32, 99, 199, 299, 399, 499, n_frames - 1}
+    for t in range(n_frames):
+        c, lev, gx, gy = src.frame(t)
+        res.step(c, lev, gx, gy, out)
+        for (y0, y1) in bands:
+            cn[y0:y1] = c[y0:y1].cpu().numpy()
+            ln[y0:y1] = lev[y0:y1].cpu().numpy()
+            orc.push_rows(cn, ln, gx, gy, y0, y1)
+        orc.advance()
+        if t in checkpoints:
+            res.sync()
+            st, so = res.download(), orc.state()
+            ref = orc.resolve()
+            o = out.cpu().numpy()
+            for (y0, y1) in bands:
+                sl = slice(y0, y1)
+                where = f"4K rows {y0}-{y1} frame {t}"
+                np.testing.assert_array_equal(st.idx[:, sl], so.idx[:, sl], err_msg=where)
+                np.testing.assert_array_equal(st.cnt[sl], so.cnt[sl], err_msg=where)
+                for name in ("wsum", "wt", "col", "wslot"):
+                    a, b = getattr(st, name), getattr(so, name)
+                    a = a[sl] if a.ndim == 2 else (a[:, sl] if a.ndim == 3 else a[:, :, sl])
+                    b = b[sl] if b.ndim == 2 else (b[:, sl] if b.ndim == 3 else b[:, :, sl])
+                    np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32), err_msg=f"{name} {where}")
+                _compare_out(o[sl], ref[sl], where)
+            assert np.all(st.cnt == t + 1) and np.all(st.idx <= t)
+            assert np.all(st.wt > 0) and np.all(st.wt <= 1)
+            assert np.isfinite(o).all() and o.min() >= 0.0 and o.max() <= 1.0
+            del st, so, ref, o
+    takes, changed, updates = res.stats()
+    assert updates == n_frames * spec.pixels and 0 < changed <= takes
+    res.close()
+    orc.close()
+
+
 # ---------------------------------------------------------------------------
 # Batched engine
 # ---------------------------------------------------------------------------
@@ -416,9 +492,9 @@ def test_engine_tick_matches_oracle_and_plain_launches(dev, use_graph):
 
 
 @pytest.mark.parametrize("use_graph", [False, True])
-def test_engine_ticks_over_several_launches(dev, use_graph):
-    """40 contexts per tick: a tick is split into two launches of at most 24 frames, and every other tick walks
-    the launches and their items in reverse.  Every context's output and state equal plain launches."""
+def test_engine_ticks_of_forty_contexts(dev, use_graph):
+    """40 contexts per tick (one launch over all their items), and every other tick walks
+    its frames and their items in reverse.  Every context's output and state equal plain launches."""
     ks = (1, 2, 3, 4, 8)
     specs = [synth.StreamSpec(48 + 8 * (i % 3), 32, ks[i % len(ks)], 4, 4.0, 10.0, 1.0, 2, 2.0, stream_id=100 + i)
              for i in range(40)]
@@ -491,9 +567,9 @@ def test_fwrs_tick_equals_plain_calls(dev):
 
 @pytest.mark.parametrize("n,w,h", [(300, 24, 8), (48, 256, 256)])
 def test_tick_of_many_frames(dev, n, w, h):
-    """Ticks far beyond the old per-launch frame limit: 300 one-item frames (fewer items than the
-    persistent grid) and 48 frames of 256 items each (more: every block loops), through fwrs_tick and an
-    engine in graph mode, against plain launches, forward and reversed ticks."""
+    """Ticks of many frames: 300 one-item frames and 48 frames of 256 items each (12288 blocks in one
+    launch), through fwrs_tick and an engine in graph mode, against plain launches, forward and reversed
+    ticks."""
     stream = torch.cuda.current_stream()
     specs = [synth.StreamSpec(w, h, (1, 2, 4, 8, 5)[i % 5], 4, 0.2 * w, 0.5 * w, 1.0, 2, 2.0, stream_id=300 + i)
              for i in range(n)]
