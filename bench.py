@@ -45,10 +45,11 @@ VALU_COUNTERS = os.path.join(ROOT, "profiles", "fused_valu_4k_counters.json")
 KERNEL_PLAIN = "void fwrs::frame_kernel<4, 3, false>(fwrs::FrameDesc)"
 KERNEL_FILL = "void fwrs::frame_kernel<4, 9, false>(fwrs::FrameDesc)"
 KERNEL_CACHED = "void fwrs::frame_kernel<4, 7, false>(fwrs::FrameDesc)"
-#: VALU issue peak of the MI355X in lane-operations per second (256 CUs x 128 lanes x 2.4 GHz: the published
-#: fp32 vector rate, 157.3 TFLOP/s, counts a fused multiply-add as two flops); profiles/valu_issue_rate.md
-#: measures a non-packed fp32 chain at this rate
-VALU_PEAK_TOPS = 78.6
+#: VALU issue peak of the MI355X for non-packed instructions, in lane-operations per second: one wave64
+#: instruction per compute unit and clock, 256 CUs x 64 lanes x 2.4 GHz (profiles/valu_issue_rate.md measures
+#: non-packed fp32 fma / mul / add at 0.92-0.98 of it; the published 157.3 TFLOP/s fp32 vector rate counts packed
+#: instructions, which the library does not issue, and a fused multiply-add as two flops)
+VALU_PEAK_TOPS = 39.3
 
 
 def log(msg: str) -> None:
@@ -688,6 +689,11 @@ def main() -> int:
             a_t = spec.pixels * vpp / (f_kern / 1e3) / 1e12
             alu = {"bound": "alu", "achieved": a_t, "peak": VALU_PEAK_TOPS, "unit": "T VALU lane-ops/s",
                    "frac": a_t / VALU_PEAK_TOPS, "valu_per_pixel": vpp,
+                   "wave_insts_per_cu_clock": a_t * 1e12 / 64.0 / 256.0 / 2.4e9,
+                   "note": "all VALU instructions (SQ_INSTS_VALU) against one non-packed wave64 instruction per CU "
+                           "and clock; a frac above 1 means the kernel's mix (integer, select, move and fp64 "
+                           "instructions beside fp32) issues faster than the single-operation microbenchmark: "
+                           "the pass runs at the VALU issue limit",
                    "kernel": "fwrs::frame_kernel<4, 3, true> (Eq. 7)"}
         eq7 = {"entry": "fwrs_push_frame_resolve (FWRS_BIAS_FULL)", "frames": n_frames,
                "ms_per_frame": f_ms / n_frames,
