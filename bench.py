@@ -224,13 +224,14 @@ def multistream(dev, stream, specs, gazes, ticks: int, ring: int, use_graph: boo
     return result
 
 
-def serving(dev, stream, time_scale: float, fps_scale: float, ring: int, label: str) -> dict:
+def serving(dev, stream, time_scale: float, fps_scale: float, ring: int, label: str, max_group: int = 8) -> dict:
     """32 sessions arriving as a Poisson process (mean 1/s; lifetime U[10, 60] s; 1920x1080 or
     3840x2160; k in {4, 8}; 72, 90 or 120 Hz), arrivals and lifetimes compressed by `time_scale`
     (same concurrency and offered load, shorter run), frame rates multiplied by `fps_scale`.
-    Reservoir budget 64 GB.  The same session mix runs through the batched executor (one direct
-    batched launch per tick: graph replay adds a few microseconds per tick on this GPU) and the
-    plain one (one launch per frame)."""
+    Reservoir budget 64 GB.  The same session mix and scheduler (each tick takes up to `max_group`
+    due frames of every session) run through the batched executor (one direct batched launch per
+    tick, a session's several frames in it as one group; graph replay adds a few microseconds per
+    tick on this GPU) and the plain one (one launch per frame)."""
     import torch
 
     from paper_2510_03964_amd import autotune, serve, synth
@@ -249,16 +250,16 @@ def serving(dev, stream, time_scale: float, fps_scale: float, ring: int, label: 
     offered = sum(s.pixels * s.fps * s.lifetime_s for s in sessions) / (
         max(s.arrival_s + s.lifetime_s for s in sessions) - min(s.arrival_s for s in sessions)) / 1e9
     out = {"sessions": len(sessions), "time_scale": time_scale, "fps_scale": fps_scale,
-           "offered_gpix_per_s_avg": offered, "budget_gb": 64}
+           "offered_gpix_per_s_avg": offered, "budget_gb": 64, "max_group": max_group}
     for mode in ("batched", "plain"):
-        ex = (serve.BatchedExecutor(rings, max_frames=64, stream=stream, tiles=tiles, use_graph=False)
+        ex = (serve.BatchedExecutor(rings, max_frames=32 * max_group, stream=stream, tiles=tiles, use_graph=False)
               if mode == "batched"
               else serve.PlainExecutor(rings, stream=stream, tiles=tiles))
-        st = serve.Scheduler(ex, budget_bytes=64 * 10**9, max_active=32).run(sessions)
+        st = serve.Scheduler(ex, budget_bytes=64 * 10**9, max_active=32, max_group=max_group).run(sessions)
         out[mode] = st.summary()
         log(f"{label} {mode}: {out[mode]['frames']} frames, {out[mode]['gpix_per_s']:.2f} Gpix/s, "
             f"p50 {out[mode]['latency_ms_p50']:.3f} ms, p99 {out[mode]['latency_ms_p99']:.3f} ms, "
-            f"{out[mode]['frames_per_tick']:.2f} frames/tick")
+            f"{out[mode]['frames_per_tick']:.2f} frames/tick, largest group {st.max_group}")
         del ex
         torch.cuda.synchronize()
     out["batched_over_plain_throughput"] = out["batched"]["gpix_per_s"] / out["plain"]["gpix_per_s"]

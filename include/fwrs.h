@@ -333,8 +333,19 @@ const char* fwrs_strerror(int status);
  * from pinned host memory on the tick's stream).  Sec. 3.2 and 4.1 make every
  * pixel of every stream an independent reservoir, so the order in which a tick
  * visits them never changes a result: each entry's results are bit-identical
- * to calling fwrs_push_frame_resolve once per entry.  A context may appear at
- * most once per tick. */
+ * to calling fwrs_push_frame_resolve once per entry, in the entries' order.
+ * A context may appear several times in one tick: its entries are its next
+ * consecutive frames, in the order they appear (other contexts' entries may
+ * come between them), and run as one group, in which each pixel reads its
+ * stored state once, applies the frames in turn and writes each frame's
+ * output to that entry's `out`, and writes its state back once (for slot
+ * counts 1, 2, 4 and 8 with one w_sum per pixel; otherwise each frame passes
+ * through the store in turn).  A serving loop that has fallen behind can so
+ * run a session's overdue frames for much less memory traffic per frame.
+ * A context's entries may share one `out`, which then ends up holding the last
+ * one's output (each pixel's frames run in order in one thread); otherwise an
+ * entry's buffers must not overlap another entry's `out` or any context's
+ * store. */
 typedef struct fwrs_frame {
     fwrs_ctx* ctx;
     const float* color;
@@ -354,8 +365,9 @@ typedef struct fwrs_frame {
  * until the process ends; a call waits (on the host) only if the ring's
  * oldest tick is still running.  Thread-safe.
  * FWRS_E_ARG: n outside [0, 4096], frames NULL with n > 0, a NULL field or
- * non-finite gaze, a context repeated, contexts on different devices.
- * FWRS_E_STATE: as fwrs_push_frame.  FWRS_E_HIP: the copy of the table or the
+ * non-finite gaze, contexts on different devices.  FWRS_E_STATE: as
+ * fwrs_push_frame, also if a context's entries would take its frame index
+ * past 2^32 - 1.  On either no context advances.  FWRS_E_HIP: the copy of the table or the
  * launch failed (no context advanced), or only the final cross-stream
  * ordering failed (the tick ran and every context advanced). */
 int fwrs_tick(const fwrs_frame* frames, int n, void* hip_stream);
@@ -364,7 +376,7 @@ int fwrs_tick(const fwrs_frame* frames, int n, void* hip_stream);
  * that must not call hipMalloc: under HIP graph capture, in tight serving
  * loops, or in harnesses that forbid it).  Same arguments and results as
  * fwrs_tick, for at most 256 entries (FWRS_E_ARG beyond, before any device
- * work).  The descriptor table lives in a fixed 43 KB array in device memory
+ * work).  The descriptor table lives in a fixed 46 KiB array in device memory
  * that the library holds for the process's lifetime -- one per GPU, shared by
  * every call on that GPU -- and is written by small kernels whose arguments
  * carry the descriptors, on hip_stream, before the batched kernel: a call

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -184,6 +185,9 @@ struct fwrs_ctx {
     bool resolved = false;
     int tile_x = kDefaultTileX, tile_y = kDefaultTileY;
     hipEvent_t order_ev = nullptr;   // marks this context's stream for work on other streams
+    // batched ticks: the layout pass that last met this context, and its group there
+    uint64_t tick_mark = 0;
+    int tick_group = 0;
 };
 
 namespace {
@@ -260,24 +264,35 @@ FrameDesc make_desc(const fwrs_ctx* x, const float* color, const uint8_t* level,
 bool gaze_ok(float gx, float gy) { return std::isfinite(gx) && std::isfinite(gy); }
 
 // The kernel op of a fused frame (update + resolve of every pixel) of context x
-// at its current frame index: from the resolve plane once it is valid and the
-// store is past its filling frames, filling the plane on the frame before.
-int fused_op(const fwrs_ctx* x)
+// at frame index t with the resolve plane valid or not (res_valid): from the
+// resolve plane once it is valid and the store is past its filling frames,
+// filling the plane on the frame before.
+int fused_op_at(const fwrs_ctx* x, uint32_t t, bool res_valid)
 {
     if (!x->res) return fwrs::kOpFused;
-    if (x->res_valid && x->t >= x->res_from) return fwrs::kOpCached;
-    return x->t + 1u >= x->res_from ? fwrs::kOpFill : fwrs::kOpFused;
+    if (res_valid && t >= x->res_from) return fwrs::kOpCached;
+    return t + 1u >= x->res_from ? fwrs::kOpFill : fwrs::kOpFused;
+}
+
+int fused_op(const fwrs_ctx* x) { return fused_op_at(x, x->t, x->res_valid); }
+
+// Whether the plane holds every pixel's resolve after a frame run as `op` on x.
+bool plane_after(const fwrs_ctx* x, int op)
+{
+    // kOpPush, kOpFused and kOpIncremental change records without the plane;
+    // a group leaves it whole wherever it is kept
+    return op == fwrs::kOpCached || op == fwrs::kOpFill || (op == fwrs::kOpGroup && x->res);
 }
 
 // After a successful launch of `op` on x: the frame count, the record of the
-// last resolve target and the validity of the resolve plane.
+// last resolve target and the validity of the resolve plane.  (A group of
+// frames advances x once per frame, in order.)
 void advance(fwrs_ctx* x, int op, const float* out)
 {
     if (op != fwrs::kOpResolve) {
         x->t += 1u;
         x->pixel_updates += (uint64_t)x->width * (uint64_t)x->height;
-        // kOpPush, kOpFused and kOpIncremental change records without the plane
-        x->res_valid = op == fwrs::kOpCached || op == fwrs::kOpFill;
+        x->res_valid = plane_after(x, op);
     }
     if (op != fwrs::kOpPush && out) {   // every op that leaves `out` holding the resolve
         x->resolved_out = out;
@@ -670,21 +685,127 @@ struct TileClass {
     int tx, ty;
 };
 
+// A slot's HIP graph for one of the batched kernels: the table's copy, then the kernel.
+struct TickGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy = nullptr;
+    hipGraphNode_t kernel = nullptr;
+    size_t copy_bytes = 0;              // bytes the copy node moves
+    uint32_t grid = 0;                  // the kernel's grid
+};
+
 struct TickSlot {
     void* host = nullptr;               // pinned table
     void* dev = nullptr;                // device table
     hipEvent_t done = nullptr;          // end of the slot's latest tick
     bool pending = false;               // `done` recorded, not yet waited for
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy = nullptr;
-    hipGraphNode_t kernel = nullptr;
-    size_t copy_bytes = 0;              // bytes the graph's copy node moves
-    uint32_t grid = 0;                  // the graph's kernel grid
+    TickGraph graph[2];                 // for ticks without / with groups (the two kernels)
     const void* head_arg = nullptr;     // the kernel node's argument values
     const void* descs_arg = nullptr;
     void* kparams[2] = {nullptr, nullptr};
 };
+
+// The checks every batched call makes on each entry before any device work:
+// FWRS_OK, or the status to return.  (A context's entries as a whole are
+// checked when the tick is laid out.)
+int check_tick(const fwrs_frame* frames, int n, int max_frames, int device)
+{
+    if (n < 0 || n > max_frames || (n > 0 && !frames)) return FWRS_E_ARG;
+    for (int i = 0; i < n; ++i) {
+        const fwrs_frame& f = frames[i];
+        if (!f.ctx || !f.color || !f.level_map || !f.out || !gaze_ok(f.gaze_x, f.gaze_y)) return FWRS_E_ARG;
+        if (f.ctx->device != device) return FWRS_E_ARG;
+        if (f.ctx->t == 0xFFFFFFFFu || f.ctx->reproject) return FWRS_E_STATE;
+    }
+    return FWRS_OK;
+}
+
+// Scratch of the tick layout for up to m entries: kTickWorkInts * m ints.
+constexpr size_t kTickWorkInts = 6;
+struct TickWork {
+    int* group;     // [entry] its context's group
+    int* count;     // [group] entries
+    int* pos;       // [group] entries laid out so far
+    int* slot;      // [group] the leader's table index
+    int* base;      // [group] table index of the group's second frame
+    int* plane;     // [group] whether the resolve plane is whole before the entry being laid out
+    TickWork(int* w, size_t m)
+        : group(w), count(w + m), pos(w + 2 * m), slot(w + 3 * m), base(w + 4 * m), plane(w + 5 * m) {}
+};
+
+// Whether pixel_group runs x's groups: compile-time slot counts and one w_sum per pixel.
+bool group_kernel(const fwrs_ctx* x)
+{
+    return (x->k == 1 || x->k == 2 || x->k == 4 || x->k == 8) && !fwrs::per_slot_mode(x->prm.bias_mode);
+}
+
+std::atomic<uint64_t> g_tick_marks{0};
+
+// Lays out the tick of frames[0 .. n) (each entry checked by check_tick): the
+// table's head and descriptors, and the op each entry runs as (ops[i], the
+// op its context then advances by).  The entries of one context are its
+// consecutive frames in the order given and form one group; groups are
+// visited in the order of their first entries, reversed (each group's items
+// too) if `reverse`.  FWRS_E_STATE if a context's frames would run past the
+// last frame index.
+template <typename TileFn>
+int layout_tick(const fwrs_frame* frames, int n, bool reverse, TileFn tile, TickWork w, fwrs::TickHead* head,
+                FrameDesc* descs, int* ops)
+{
+    const uint64_t mark = g_tick_marks.fetch_add(1u, std::memory_order_relaxed) + 1u;
+    int groups = 0;
+    for (int i = 0; i < n; ++i) {
+        fwrs_ctx* x = frames[i].ctx;
+        if (x->tick_mark != mark) {
+            x->tick_mark = mark;
+            x->tick_group = groups;
+            w.count[groups] = 0;
+            w.pos[groups] = 0;
+            w.plane[groups] = x->res_valid ? 1 : 0;
+            ++groups;
+        }
+        w.group[i] = x->tick_group;
+        w.count[x->tick_group] += 1;
+        if ((uint64_t)x->t + (uint64_t)w.count[x->tick_group] > 0xFFFFFFFFull) return FWRS_E_STATE;
+    }
+    int later = groups;
+    for (int s = 0; s < groups; ++s) {
+        const int g = reverse ? groups - 1 - s : s;
+        w.slot[g] = s;
+        w.base[g] = later;
+        later += w.count[g] - 1;
+    }
+    for (int i = 0; i < n; ++i) {
+        const fwrs_frame& f = frames[i];
+        fwrs_ctx* x = f.ctx;
+        const int g = w.group[i];
+        const int nf = w.count[g];
+        const int at = w.pos[g]++;
+        int tx, ty;
+        tile(x, tx, ty);
+        FrameDesc& d = descs[at == 0 ? w.slot[g] : w.base[g] + at - 1];
+        d = make_desc(x, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, tx, ty);
+        d.t = x->t + (uint32_t)at;
+        const bool plane = w.plane[g] != 0;
+        const int op = nf > 1 && group_kernel(x) ? fwrs::kOpGroup : fused_op_at(x, d.t, plane);
+        w.plane[g] = plane_after(x, op) ? 1 : 0;
+        ops[i] = op;
+        d.op = (uint32_t)op;
+        d.res_ok = plane ? 1u : 0u;
+        d.rev = reverse ? 1u : 0u;
+        d.nf = at == 0 ? (uint32_t)nf : 1u;
+        d.more = at == 0 ? (uint32_t)w.base[g] : 0u;
+    }
+    head->n = (uint32_t)groups;
+    head->total = 0;
+    head->pad0 = head->pad1 = 0;
+    for (int s = 0; s < groups; ++s) {
+        descs[s].first = head->total;
+        head->total += descs[s].items;
+    }
+    return FWRS_OK;
+}
 
 }  // namespace
 
@@ -697,6 +818,7 @@ struct fwrs_engine {
     size_t table_bytes = 0;
     std::vector<TileClass> classes;
     std::vector<int> ops;               // op of each frame of the tick being issued
+    std::vector<int> work;              // the tick layout's scratch (TickWork)
     TickSlot slot[kRing];
     hipEvent_t done_ev = nullptr;       // end of the latest tick, for contexts on other streams
     uint32_t ticks = 0;                 // ticks issued (odd ticks run in reverse order)
@@ -704,22 +826,17 @@ struct fwrs_engine {
 
 namespace {
 
-void slot_free(TickSlot& sl)
+void graph_free(TickGraph& g)
 {
-    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
-    if (sl.graph) (void)hipGraphDestroy(sl.graph);
-    sl.exec = nullptr;
-    sl.graph = nullptr;
-    sl.copy = nullptr;
-    sl.kernel = nullptr;
-    sl.copy_bytes = 0;
-    sl.grid = 0;
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = TickGraph{};
 }
 
 void engine_free(fwrs_engine* e)
 {
     for (TickSlot& sl : e->slot) {
-        slot_free(sl);
+        for (TickGraph& g : sl.graph) graph_free(g);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.dev) (void)hipFree(sl.dev);
         if (sl.host) (void)hipHostFree(sl.host);
@@ -735,6 +852,7 @@ int engine_init(fwrs_engine* e, int max_frames)
     e->table_bytes = fwrs::tick_table_bytes((size_t)max_frames);
     try {
         e->ops.resize((size_t)max_frames);
+        e->work.resize(kTickWorkInts * (size_t)max_frames);
     } catch (const std::bad_alloc&) {
         return FWRS_E_NOMEM;
     }
@@ -772,10 +890,10 @@ void engine_tile(const fwrs_engine* e, const fwrs_ctx* x, int& tx, int& ty)
         }
 }
 
-hipKernelNodeParams tick_node(TickSlot& sl, uint32_t grid)
+hipKernelNodeParams tick_node(TickSlot& sl, bool groups, uint32_t grid)
 {
     hipKernelNodeParams kp{};
-    kp.func = fwrs::tick_kernel_entry();
+    kp.func = fwrs::tick_kernel_entry(groups);
     kp.gridDim = dim3(grid);
     kp.blockDim = dim3(fwrs::kBlock);
     kp.sharedMemBytes = 0;
@@ -784,39 +902,41 @@ hipKernelNodeParams tick_node(TickSlot& sl, uint32_t grid)
     return kp;
 }
 
-// The slot's graph: the copy of `bytes` of its table, then the kernel on
-// `grid` blocks.  A built graph is updated only where the tick's size differs
-// from the one it holds.  On failure nothing is left half built.
-hipError_t slot_graph(TickSlot& sl, size_t bytes, uint32_t grid)
+// The slot's graph for the kernel with or without groups: the copy of `bytes`
+// of its table, then the kernel on `grid` blocks.  A built graph is updated
+// only where the tick's size differs from the one it holds.  On failure
+// nothing is left half built.
+hipError_t slot_graph(TickSlot& sl, bool groups, size_t bytes, uint32_t grid)
 {
-    if (sl.exec) {
+    TickGraph& g = sl.graph[groups ? 1 : 0];
+    if (g.exec) {
         hipError_t err = hipSuccess;
-        if (sl.copy_bytes != bytes) {
-            err = hipGraphExecMemcpyNodeSetParams1D(sl.exec, sl.copy, sl.dev, sl.host, bytes, hipMemcpyHostToDevice);
-            if (err == hipSuccess) sl.copy_bytes = bytes;
+        if (g.copy_bytes != bytes) {
+            err = hipGraphExecMemcpyNodeSetParams1D(g.exec, g.copy, sl.dev, sl.host, bytes, hipMemcpyHostToDevice);
+            if (err == hipSuccess) g.copy_bytes = bytes;
         }
-        if (err == hipSuccess && sl.grid != grid) {
-            hipKernelNodeParams kp = tick_node(sl, grid);
-            err = hipGraphExecKernelNodeSetParams(sl.exec, sl.kernel, &kp);
-            if (err == hipSuccess) sl.grid = grid;
+        if (err == hipSuccess && g.grid != grid) {
+            hipKernelNodeParams kp = tick_node(sl, groups, grid);
+            err = hipGraphExecKernelNodeSetParams(g.exec, g.kernel, &kp);
+            if (err == hipSuccess) g.grid = grid;
         }
         return err;
     }
-    hipError_t err = hipGraphCreate(&sl.graph, 0);
+    hipError_t err = hipGraphCreate(&g.graph, 0);
     if (err == hipSuccess)
-        err = hipGraphAddMemcpyNode1D(&sl.copy, sl.graph, nullptr, 0, sl.dev, sl.host, bytes, hipMemcpyHostToDevice);
+        err = hipGraphAddMemcpyNode1D(&g.copy, g.graph, nullptr, 0, sl.dev, sl.host, bytes, hipMemcpyHostToDevice);
     if (err == hipSuccess) {
-        hipKernelNodeParams kp = tick_node(sl, grid);
-        err = hipGraphAddKernelNode(&sl.kernel, sl.graph, &sl.copy, 1, &kp);
+        hipKernelNodeParams kp = tick_node(sl, groups, grid);
+        err = hipGraphAddKernelNode(&g.kernel, g.graph, &g.copy, 1, &kp);
     }
-    if (err == hipSuccess) err = hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0);
+    if (err == hipSuccess) err = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
     if (err != hipSuccess) {
         (void)hipGetLastError();
-        slot_free(sl);
+        graph_free(g);
         return err;
     }
-    sl.copy_bytes = bytes;
-    sl.grid = grid;
+    g.copy_bytes = bytes;
+    g.grid = grid;
     return hipSuccess;
 }
 
@@ -824,22 +944,6 @@ hipError_t slot_graph(TickSlot& sl, size_t bytes, uint32_t grid)
 // contexts' frame counts.  Every context's frame enters the state of the
 // tick's launch or of none: on FWRS_E_HIP no context has advanced, except that
 // if only the final cross-stream ordering failed the tick ran and they did.
-// The checks every batched call makes before any device work: FWRS_OK, or the
-// status to return.
-int check_tick(const fwrs_frame* frames, int n, int max_frames, int device)
-{
-    if (n < 0 || n > max_frames || (n > 0 && !frames)) return FWRS_E_ARG;
-    for (int i = 0; i < n; ++i) {
-        const fwrs_frame& f = frames[i];
-        if (!f.ctx || !f.color || !f.level_map || !f.out || !gaze_ok(f.gaze_x, f.gaze_y)) return FWRS_E_ARG;
-        if (f.ctx->device != device) return FWRS_E_ARG;
-        if (f.ctx->t == 0xFFFFFFFFu || f.ctx->reproject) return FWRS_E_STATE;
-        for (int j = 0; j < i; ++j)
-            if (frames[j].ctx == f.ctx) return FWRS_E_ARG;
-    }
-    return FWRS_OK;
-}
-
 int engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n, hipStream_t stream)
 {
     const int rc = check_tick(frames, n, e->max_frames, e->device);
@@ -858,22 +962,9 @@ int engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n, hipStream_t str
     const bool reverse = (e->ticks & 1u) != 0u;
     fwrs::TickHead* head = static_cast<fwrs::TickHead*>(sl.host);
     FrameDesc* descs = reinterpret_cast<FrameDesc*>(static_cast<char*>(sl.host) + fwrs::kTickDescOffset);
-    head->n = (uint32_t)n;
-    head->total = 0;
-    head->pad0 = head->pad1 = 0;
-    for (int slot_i = 0; slot_i < n; ++slot_i) {
-        const int i = reverse ? n - 1 - slot_i : slot_i;
-        const fwrs_frame& f = frames[i];
-        int tx, ty;
-        engine_tile(e, f.ctx, tx, ty);
-        FrameDesc& d = descs[slot_i];
-        d = make_desc(f.ctx, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, tx, ty);
-        e->ops[i] = fused_op(f.ctx);
-        d.op = (uint32_t)e->ops[i];
-        d.first = head->total;
-        d.rev = reverse ? 1u : 0u;
-        head->total += d.items;
-    }
+    const int lrc = layout_tick(frames, n, reverse, [e](const fwrs_ctx* x, int& tx, int& ty) { engine_tile(e, x, tx, ty); },
+                                TickWork(e->work.data(), (size_t)e->max_frames), head, descs, e->ops.data());
+    if (lrc != FWRS_OK) return lrc;
     // each context's earlier work on its own stream comes first
     hipError_t err = hipSuccess;
     bool foreign = false;
@@ -885,12 +976,13 @@ int engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n, hipStream_t str
         }
     }
     const size_t bytes = fwrs::tick_table_bytes((size_t)n);
+    const bool groups = head->n < (uint32_t)n;      // some context has several frames
     if (err == hipSuccess && e->use_graph) {
-        err = slot_graph(sl, bytes, head->total);
-        if (err == hipSuccess) err = hipGraphLaunch(sl.exec, stream);
+        err = slot_graph(sl, groups, bytes, head->total);
+        if (err == hipSuccess) err = hipGraphLaunch(sl.graph[groups ? 1 : 0].exec, stream);
     } else if (err == hipSuccess) {
         err = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream);
-        if (err == hipSuccess) err = fwrs::launch_tick(sl.dev, head->total, stream);
+        if (err == hipSuccess) err = fwrs::launch_tick(sl.dev, head->total, groups, stream);
     }
     if (err == hipSuccess) err = hipEventRecord(sl.done, stream);
     if (err != hipSuccess) {
@@ -1070,34 +1162,24 @@ int fwrs_tick_noalloc(const fwrs_frame* frames, int n, void* hip_stream)
     // the tick's layout (as in fwrs_tick: every other call on a device runs backwards)
     const bool reverse = (g_scratch_ticks[dev] & 1u) != 0u;
     int ops[kStaticTickFrames];
+    int work[kTickWorkInts * kStaticTickFrames];
+    FrameDesc descs[kStaticTickFrames];
     fwrs::TickFill fill{};
-    fill.head.n = (uint32_t)n;
-    for (int slot_i = 0; slot_i < n; ++slot_i) {
-        const fwrs_frame& f = frames[reverse ? n - 1 - slot_i : slot_i];
-        fill.head.total += make_desc(f.ctx, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, f.ctx->tile_x,
-                                     f.ctx->tile_y).items;
-    }
+    const int lrc = layout_tick(frames, n, reverse, [](const fwrs_ctx* x, int& tx, int& ty) {
+        tx = x->tile_x;
+        ty = x->tile_y;
+    }, TickWork(work, kStaticTickFrames), &fill.head, descs, ops);
+    if (lrc != FWRS_OK) return lrc;
     // the descriptors, kFillFrames per fill launch, then the batched kernel
     hipError_t err = hipSuccess;
-    uint32_t first = 0;
     for (int at = 0; at < n && err == hipSuccess; at += fwrs::kFillFrames) {
         fill.at = (uint32_t)at;
         fill.count = (uint32_t)std::min(fwrs::kFillFrames, n - at);
         fill.write_head = at == 0 ? 1u : 0u;
-        for (uint32_t c = 0; c < fill.count; ++c) {
-            const int i = reverse ? n - 1 - (at + (int)c) : at + (int)c;
-            const fwrs_frame& f = frames[i];
-            FrameDesc& d = fill.descs[c];
-            d = make_desc(f.ctx, f.color, f.level_map, f.gaze_x, f.gaze_y, f.out, f.ctx->tile_x, f.ctx->tile_y);
-            ops[i] = fused_op(f.ctx);
-            d.op = (uint32_t)ops[i];
-            d.first = first;
-            d.rev = reverse ? 1u : 0u;
-            first += d.items;
-        }
+        std::memcpy(fill.descs, descs + at, fill.count * sizeof(FrameDesc));
         err = fwrs::launch_tick_fill(table, fill, stream);
     }
-    if (err == hipSuccess) err = fwrs::launch_tick(table, fill.head.total, stream);
+    if (err == hipSuccess) err = fwrs::launch_tick(table, fill.head.total, fill.head.n < (uint32_t)n, stream);
     if (err != hipSuccess) {
         (void)hipGetLastError();
         return FWRS_E_HIP;

@@ -29,7 +29,11 @@ struct Consts {
 
 // Everything one frame of one context needs on the device.  Passed by value
 // to the single-frame kernels and stored in a device table for batched ticks
-// (where `first` is the tick's first work item of the frame).
+// (where `first` is the tick's first work item of the frame).  In a batched
+// tick the consecutive frames of one context form a group: the table holds the
+// group's first frame (the leader, which owns the work items) among the other
+// leaders and its nf - 1 later frames after all the leaders, from index `more`
+// on; each pixel then runs all nf frames in order.
 struct alignas(8) FrameDesc {
     const float* color;         // [H][W][3] f32, the new candidates
     const uint8_t* level;       // [H][W] u8 foveation level
@@ -47,6 +51,10 @@ struct alignas(8) FrameDesc {
     uint32_t tile_x_log2, tile_y_log2, tiles_x, items;  // launch geometry
     uint32_t first;             // batched ticks: the frame's first work item in the tick
     uint32_t rev;               // batched ticks: the frame's items are visited last first
+    uint32_t nf;                // batched ticks, leaders: frames in the group (1: the frame alone)
+    uint32_t more;              // batched ticks, leaders: table index of the group's second frame
+    uint32_t res_ok;            // the resolve plane holds every pixel's resolve before this frame
+    uint32_t pad_;
 };
 
 // Reprojected frame (Sec. 4.3): the reservoirs are gathered from the previous

@@ -22,24 +22,27 @@ constexpr int kOpFused = 3;         // update + resolve of every pixel from its 
 constexpr int kOpIncremental = 5;   // update + resolve of the changed pixels only
 constexpr int kOpCached = 7;        // update + resolve, unchanged pixels from the resolve plane
 constexpr int kOpFill = 9;          // kOpFused that also writes the resolve plane
+constexpr int kOpGroup = 11;        // batched ticks: a group's frames with the pixel state held in registers
 hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream);
 
 // A batched tick's table in device memory: this head, then (at kTickDescOffset)
-// the n frame descriptors in the order their work items are numbered
-// (descs[f].first increasing, descs[f].items > 0); `total` = the tick's work
-// items.
+// the n group leaders' descriptors in the order their work items are numbered
+// (descs[f].first increasing, descs[f].items > 0), then the groups' later
+// frames (descs[leader.more .. leader.more + leader.nf - 2] for each leader);
+// `total` = the tick's work items.
 struct alignas(16) TickHead {
     uint32_t n, total, pad0, pad1;
 };
 constexpr size_t kTickDescOffset = 16;
 static_assert(sizeof(TickHead) == kTickDescOffset, "descriptors follow the head");
-inline size_t tick_table_bytes(size_t n) { return kTickDescOffset + n * sizeof(FrameDesc); }
+inline size_t tick_table_bytes(size_t frames) { return kTickDescOffset + frames * sizeof(FrameDesc); }
 
 // The batched kernel on `grid` blocks (block b takes work items b, b + grid,
-// ... of the table's tick; the engine launches one block per item).
-hipError_t launch_tick(const void* table, uint32_t grid, hipStream_t stream);
-// Its entry point, for HIP graph kernel nodes: arguments (const TickHead*, const FrameDesc*).
-void* tick_kernel_entry();
+// ... of the table's tick; the engine launches one block per item); `groups`:
+// the table has groups (some leader with nf > 1).
+hipError_t launch_tick(const void* table, uint32_t grid, bool groups, hipStream_t stream);
+// Its entry points, for HIP graph kernel nodes: arguments (const TickHead*, const FrameDesc*).
+void* tick_kernel_entry(bool groups);
 
 // One launch of the table-fill kernel: writes `count` descriptors (kernel
 // arguments) to table slots at .. at + count - 1, and the head if write_head.

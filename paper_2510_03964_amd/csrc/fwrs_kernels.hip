@@ -46,7 +46,7 @@ namespace fwrs {
 // the plane, making it valid for the kCached frames that follow.
 enum Op : int {
     kPush = kOpPush, kResolve = kOpResolve, kFused = kOpFused, kIncremental = kOpIncremental, kCached = kOpCached,
-    kFill = kOpFill,
+    kFill = kOpFill, kGroup = kOpGroup,
 };
 
 enum : uint32_t {
@@ -171,6 +171,26 @@ __device__ __forceinline__ uint32_t decide_any(const FrameDesc& d, uint32_t p, f
 #define FWRS_RES_EARLY 1
 #endif
 
+// The resolve of a record held in registers: sum_j w_j col_j / sum_j w_j, the
+// sums taken in slot order; 0 for a record with no weight (only the empty
+// reservoir: every kept weight is > 0).
+template <int R>
+__device__ __forceinline__ void resolve_slots(const float4 (&r)[R], float& q0, float& q1, float& q2)
+{
+    float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        S = S + r[j].x;
+        a0 = a0 + r[j].x * r[j].y;
+        a1 = a1 + r[j].x * r[j].z;
+        a2 = a2 + r[j].x * r[j].w;
+    }
+    const float rs = S > 0.0f ? 1.0f / S : 0.0f;
+    q0 = a0 * rs;
+    q1 = a1 * rs;
+    q2 = a2 * rs;
+}
+
 // ---------------------------------------------------------------------------
 // One pixel.  K > 0 keeps the pixel's whole record in registers; K == 0
 // (any slot count up to kMaxK) streams the record one slot at a time.
@@ -280,16 +300,10 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
         const bool recompute = (OP != kIncremental && OP != kCached) || tk != 0u;
         float* o = d.out + 3 * (size_t)p;
         if (recompute) {
-            float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
             if (K) {
-#pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    S = S + r[j].x;
-                    a0 = a0 + r[j].x * r[j].y;
-                    a1 = a1 + r[j].x * r[j].z;
-                    a2 = a2 + r[j].x * r[j].w;
-                }
+                resolve_slots<R>(r, q0, q1, q2);
             } else {
+                float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
                 for (int j = 0; j < kk; ++j) {
                     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
                     if ((tk >> j) & 1u) {
@@ -304,12 +318,12 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
                     a1 = a1 + v.x * v.z;
                     a2 = a2 + v.x * v.w;
                 }
+                // S == 0 only before the first frame (every kept weight is > 0): output 0.
+                const float rs = S > 0.0f ? 1.0f / S : 0.0f;
+                q0 = a0 * rs;
+                q1 = a1 * rs;
+                q2 = a2 * rs;
             }
-            // S == 0 only before the first frame (every kept weight is > 0): output 0.
-            const float rs = S > 0.0f ? 1.0f / S : 0.0f;
-            q0 = a0 * rs;
-            q1 = a1 * rs;
-            q2 = a2 * rs;
             if (kKeepsRes) {
                 st<kNtResSt>(res + 0, q0);
                 st<kNtResSt>(res + 1, q1);
@@ -333,6 +347,109 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
             }
     }
     return __popc(tk) + (tk ? 0x10000u : 0u);
+}
+
+// ---------------------------------------------------------------------------
+// One pixel over a group of consecutive frames of one context (batched ticks;
+// K > 0 slots, one w_sum per pixel): d0 is the group's first frame, later[f - 1]
+// its frame f.  The pixel's state stays in registers from the group's first
+// frame to its last -- w_sum, the pixel's resolve (read from the resolve plane
+// where that holds it, else computed from the record, which is then read up
+// front) and, from the first replacement on, the whole record -- so the store
+// is read once and written once per group.  Each frame runs the single-frame
+// arithmetic in the same order (the Philox words of its own frame index, the
+// Eq. 4 weight at its own gaze, the bias, the Alg. 2 decision per slot, the
+// resolve of a changed pixel in slot order) and writes its own output; at the
+// end go w_sum, the replaced slots' records and frame indices, and the
+// resolve plane (where the pixel changed, or everywhere if it did not hold the
+// resolve), so the results are those of the frames run one by one, bit for bit.
+// Adds the replaced slots and the frames in which the pixel changed.
+// ---------------------------------------------------------------------------
+template <int K>
+__device__ __forceinline__ void pixel_group(const FrameDesc& d0, const FrameDesc* __restrict__ later, uint32_t x,
+                                            uint32_t y, uint32_t& slots, uint32_t& changed)
+{
+    const uint32_t p = y * d0.width + x;
+    float4* rec = reinterpret_cast<float4*>(d0.rec) + (size_t)p * K;
+    uint32_t* idx = d0.idx + (size_t)p * K;
+    float* res = d0.res + 3 * (size_t)p;
+    const bool keep = d0.res != nullptr;
+    const bool empty = d0.t == 0u;              // the empty store: every slot zero, nothing to read
+    const bool from_plane = keep && d0.res_ok != 0u && !empty;
+
+    float W1 = ld<kNtWsumLd>(d0.wsum + p);
+    float4 r[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) r[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    float q0 = 0.f, q1 = 0.f, q2 = 0.f;
+    bool have = true;                           // the record is in registers
+    if (from_plane) {
+        q0 = ld<kNtResLd>(res + 0);
+        q1 = ld<kNtResLd>(res + 1);
+        q2 = ld<kNtResLd>(res + 2);
+        have = false;
+    } else if (!empty) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) r[j] = ld4<kNtRecLd>(rec + j);
+        resolve_slots<K>(r, q0, q1, q2);
+    }
+    uint32_t dirty = 0u;                        // slots replaced in the group
+    uint32_t tj[K];                             // their last replacement's frame index
+#pragma unroll
+    for (int j = 0; j < K; ++j) tj[j] = 0u;
+
+    for (uint32_t f = 0; f < d0.nf; ++f) {
+        const FrameDesc& d = f == 0u ? d0 : later[f - 1u];
+        const uint32_t lv = ld<kNtLevel>(d.level + p);
+        const Words<K> words = philox_words<K>(d, p);
+        const float dx = ((float)x + 0.5f) - d.gx;
+        const float dy = ((float)y + 0.5f) - d.gy;
+        float e = 0.f;
+        const float outside = weight_outside(d.c, dx * dx + dy * dy, e);
+        const float w = select_eq4(d.c, outside, e, lv);
+        const float W1b = bias_shared(W1, w, d.bias, d.c.decay);
+        const float s = W1b + w;
+        const uint32_t tk = decide_words<K>(words, W1b, s);
+        W1 = s;
+        if (tk) {
+            const float* color = d.color + 3 * (size_t)p;
+            const float4 fresh = make_float4(w, ld<kNtColor>(color + 0), ld<kNtColor>(color + 1),
+                                             ld<kNtColor>(color + 2));
+            if (!have) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    if (!((tk >> j) & 1u)) r[j] = ld4<kNtRecLd>(rec + j);
+                have = true;
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if ((tk >> j) & 1u) {
+                    r[j] = fresh;
+                    tj[j] = d.t;
+                }
+            dirty |= tk;
+            resolve_slots<K>(r, q0, q1, q2);
+            slots += (uint32_t)__popc(tk);
+            changed += 1u;
+        }
+        float* o = d.out + 3 * (size_t)p;
+        st<kNtOut>(o + 0, q0);
+        st<kNtOut>(o + 1, q1);
+        st<kNtOut>(o + 2, q2);
+    }
+
+    st<kNtWsumSt>(d0.wsum + p, W1);
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if ((dirty >> j) & 1u) {
+            st4<kNtRecSt>(rec + j, r[j]);
+            st<kNtIdxSt>(idx + j, tj[j]);
+        }
+    if (keep && (dirty != 0u || !from_plane)) {
+        st<kNtResSt>(res + 0, q0);
+        st<kNtResSt>(res + 1, q1);
+        st<kNtResSt>(res + 2, q2);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -496,6 +613,22 @@ __device__ __forceinline__ uint32_t process_item(const FrameDesc& d, uint32_t it
     return pixel<K, OP, FOV>(d, x, y, fs);
 }
 
+// add_stats for counts beyond its packed fields' range (a group of frames):
+// replaced slots and changed pixel-frames as separate wave sums.
+__device__ __forceinline__ void add_stats_wide(unsigned long long* stats, uint32_t slots, uint32_t changed)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        slots += __shfl_xor(slots, off);
+        changed += __shfl_xor(changed, off);
+    }
+    if ((threadIdx.x & 63u) == 0u && changed) {
+        const uint32_t slot = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) & (kStatSlots - 1);
+        atomicAdd(stats + 3 * slot, (unsigned long long)slots);
+        atomicAdd(stats + 3 * slot + 1, (unsigned long long)changed);
+    }
+}
+
 __device__ __forceinline__ void add_stats(unsigned long long* stats, uint32_t v)
 {
     // v = replaced slots + 2^16 * (pixel changed) + 2^24 * (pixel flushed).  Wave sum (at
@@ -530,19 +663,23 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(FrameDesc d)
 // ---------------------------------------------------------------------------
 // Batched tick: one launch for all the frames of a tick, any number of them.
 // The frames' descriptors are a table in device memory (uniform data, read
-// with scalar loads), in the order the tick visits them; the tick's 256-pixel
-// work items are numbered frame after frame, and a frame whose `rev` is set
-// visits its own items last first (the host reverses the frame order and sets
-// `rev` on every other tick, so such a tick runs entirely backwards).  Block b
-// takes items b, b + G, b + 2G, ... (G = gridDim.x): the engine launches one
-// block per item, which measured faster than a persistent grid of resident
-// blocks looping over the items (the hardware's block dispatch balances the
-// uneven per-item cost of the pass better than a fixed stride), but any grid
-// gives the same results.  A block finds its first item's frame by binary
-// search over the frames' first items and follows the frames along with its
-// (increasing) items; each item then runs the same per-pixel code as the
-// single-frame kernels, for the frame's slot count and op (kFused, kCached or
-// kFill).
+// with scalar loads).  The consecutive frames of one context in a tick form a
+// group, whose first frame (the leader) stands for it among the table's
+// leaders, in the order the tick visits them; the tick's 256-pixel work items
+// are numbered leader after leader, and a leader whose `rev` is set visits its
+// own items last first (the host reverses the group order and sets `rev` on
+// every other tick, so such a tick runs entirely backwards).  Block b takes
+// items b, b + G, b + 2G, ... (G = gridDim.x): the engine launches one block
+// per item, which measured faster than a persistent grid of resident blocks
+// looping over the items (the hardware's block dispatch balances the uneven
+// per-item cost of the pass better than a fixed stride), but any grid gives
+// the same results.  A block finds its first item's leader by binary search
+// over the leaders' first items and follows the leaders along with its
+// (increasing) items.  An item of a lone frame runs the single-frame per-pixel
+// code for the frame's slot count and op (kFused, kCached or kFill); an item
+// of a group runs pixel_group (op kGroup), or else (run-time slot counts,
+// per-slot modes) each of the group's frames in turn through the store, every
+// pixel in the same thread, so each frame reads what the one before wrote.
 // ---------------------------------------------------------------------------
 template <int K, int OP, bool PER_SLOT = false>
 __device__ __forceinline__ uint32_t process_wave(const FrameDesc& d, uint32_t item, uint32_t wave)
@@ -569,6 +706,37 @@ __device__ __forceinline__ uint32_t tick_item(const FrameDesc& d, uint32_t local
 #undef FWRS_TICK_OPS
 }
 
+// One work item of a group of d.nf > 1 frames (d its leader).
+__device__ __forceinline__ void tick_group_item(const FrameDesc& d, const FrameDesc* __restrict__ descs,
+                                                uint32_t local, uint32_t wave)
+{
+    const FrameDesc* later = descs + d.more;
+    if (d.op == kGroup) {
+        uint32_t x, y, slots = 0u, changed = 0u;
+        if (item_pixel_of(d, local, wave, threadIdx.x & 63u, x, y)) {
+            switch (d.k) {
+                case 1: pixel_group<1>(d, later, x, y, slots, changed); break;
+                case 2: pixel_group<2>(d, later, x, y, slots, changed); break;
+                case 4: pixel_group<4>(d, later, x, y, slots, changed); break;
+                case 8: pixel_group<8>(d, later, x, y, slots, changed); break;
+                default: break;                          // the host sets kGroup only for k in {1, 2, 4, 8}
+            }
+        }
+        if (d.stats) add_stats_wide(d.stats, slots, changed);
+        return;
+    }
+    for (uint32_t f = 0; f < d.nf; ++f) {
+        const FrameDesc& df = f == 0u ? d : later[f - 1u];
+        const uint32_t v = tick_item(df, local, wave);
+        if (df.stats) add_stats(df.stats, v);
+    }
+}
+
+// GROUPS: the tick has groups.  A group of k = 8 frames holds a whole record
+// across its frames, which takes more registers than any single-frame path;
+// ticks without groups run the instantiation without that path, at the
+// single-frame paths' occupancy.
+template <bool GROUPS>
 __global__ __launch_bounds__(kBlock) void tick_kernel(const TickHead* __restrict__ head,
                                                       const FrameDesc* __restrict__ descs)
 {
@@ -576,7 +744,7 @@ __global__ __launch_bounds__(kBlock) void tick_kernel(const TickHead* __restrict
     uint32_t f = 0u;
     for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
         if (item == blockIdx.x) {
-            uint32_t hi = n - 1u;                        // last frame whose first item <= item
+            uint32_t hi = n - 1u;                        // last leader whose first item <= item
             while (f < hi) {
                 const uint32_t mid = (f + hi + 1u) >> 1;
                 if (descs[mid].first <= item) f = mid;
@@ -588,8 +756,13 @@ __global__ __launch_bounds__(kBlock) void tick_kernel(const TickHead* __restrict
         const FrameDesc& d = descs[f];
         uint32_t local = item - d.first;
         if (d.rev) local = d.items - 1u - local;
-        const uint32_t v = tick_item(d, local, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
-        if (d.stats) add_stats(d.stats, v);
+        const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        if (GROUPS && d.nf > 1u) {
+            tick_group_item(d, descs, local, wave);
+        } else {
+            const uint32_t v = tick_item(d, local, wave);
+            if (d.stats) add_stats(d.stats, v);
+        }
     }
 }
 
@@ -1111,12 +1284,13 @@ hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream)
     }
 }
 
-hipError_t launch_tick(const void* table, uint32_t grid, hipStream_t stream)
+hipError_t launch_tick(const void* table, uint32_t grid, bool groups, hipStream_t stream)
 {
     if (grid == 0u) return hipSuccess;
     const TickHead* head = static_cast<const TickHead*>(table);
     const FrameDesc* descs = reinterpret_cast<const FrameDesc*>(static_cast<const char*>(table) + kTickDescOffset);
-    hipLaunchKernelGGL(tick_kernel, dim3(grid), dim3(kBlock), 0, stream, head, descs);
+    if (groups) hipLaunchKernelGGL(tick_kernel<true>, dim3(grid), dim3(kBlock), 0, stream, head, descs);
+    else hipLaunchKernelGGL(tick_kernel<false>, dim3(grid), dim3(kBlock), 0, stream, head, descs);
     return hipGetLastError();
 }
 
@@ -1242,7 +1416,10 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t stream
     return hipGetLastError();
 }
 
-void* tick_kernel_entry() { return reinterpret_cast<void*>(&tick_kernel); }
+void* tick_kernel_entry(bool groups)
+{
+    return groups ? reinterpret_cast<void*>(&tick_kernel<true>) : reinterpret_cast<void*>(&tick_kernel<false>);
+}
 
 
 }  // namespace fwrs

@@ -421,7 +421,8 @@ def _fill_frames(buf, entries, capacity: int) -> int:
 
 
 def tick(entries, stream=None) -> None:
-    """fwrs_tick: one batched launch advances every entry's context by one frame on `stream`.
+    """fwrs_tick: one batched launch advances every entry's context by one frame per entry on
+    `stream` (a context's several entries are its consecutive frames, in order, run as one group).
     entries: iterable of (Reservoir, color, level, gaze_x, gaze_y, out)."""
     entries = list(entries)
     buf = (Frame * max(1, len(entries)))()
@@ -444,7 +445,7 @@ def tick_noalloc(entries, stream=None) -> None:
 
 
 class Engine:
-    """Batched ticks: one kernel launch advances many contexts by one frame."""
+    """Batched ticks: one kernel launch advances many contexts, each by one frame per entry."""
 
     def __init__(self, max_frames: int, stream=None, use_graph: bool = False):
         self._L = load()

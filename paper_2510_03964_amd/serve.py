@@ -5,10 +5,12 @@ own resolution, slot count k and frame rate.  A session is admitted when its
 reservoir store (``fwrs_state_bytes``) fits in the remaining HBM budget and a
 slot is free; otherwise it waits in a FIFO queue.  Frame i of an admitted
 session is due at admit_time + i / fps.  Continuous batching: whenever fewer
-than `max_inflight` ticks are on the GPU, the loop gathers the oldest due frame
-of every active session and submits them together as one batched tick
-(``fwrs_engine_tick``); frames that come due while the GPU is busy ride along
-in the next tick, so batches grow with the load.  Sessions that end release
+than `max_inflight` ticks are on the GPU, the loop gathers the due frames of
+every active session -- up to `max_group` consecutive ones per session, oldest
+first -- and submits them together as one batched tick (``fwrs_engine_tick``,
+in which a session's several frames run as one group that reads and writes
+its reservoir once); frames that come due while the GPU is busy ride along in
+the next tick, so batches grow with the load.  Sessions that end release
 their memory and the queue is re-examined.  Each frame's latency is completion - due time; the
 deadline is one 90 Hz frame (11.1 ms).
 
@@ -96,6 +98,7 @@ class ServeStats:
     max_active: int
     ticks: int
     max_batch: int = 0
+    max_group: int = 0
     queue_wait_s: list = field(default_factory=list)
 
     def summary(self) -> dict:
@@ -109,6 +112,7 @@ class ServeStats:
             "deadline_ms": DEADLINE_MS, "deadline_misses": self.deadline_misses,
             "sessions_admitted": self.admitted, "sessions_never_admitted": self.rejected,
             "max_queue": self.max_queue, "max_active": self.max_active, "max_batch": self.max_batch,
+            "max_frames_of_a_session_per_tick": self.max_group,
             "frames_per_tick": self.frames / self.ticks if self.ticks else 0.0,
             "queue_wait_s_max": max(self.queue_wait_s) if self.queue_wait_s else 0.0,
         }
@@ -121,18 +125,22 @@ class Scheduler:
       state_bytes(spec) -> int
       open(spec) -> handle            (allocates the session's reservoir)
       close(handle)
-      submit(list[(handle, frame_index)]) -> tick id   (asynchronous)
+      submit(list[(handle, frame_index)]) -> tick id   (asynchronous; a session's frames
+                                                       consecutive and in order)
       poll() -> list[(tick id, completion time in the clock's seconds)]
       drain() -> same as poll, after waiting for all submitted work
       max_batch (optional attribute) -> the most frames one submit may carry
     """
 
     def __init__(self, executor, budget_bytes: int, max_active: int = 64, max_inflight: int = 2,
-                 clock=time.perf_counter, sleep=time.sleep):
+                 max_group: int = 1, clock=time.perf_counter, sleep=time.sleep):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
         self.max_inflight = int(max_inflight)
+        self.max_group = int(max_group)
+        if self.max_group < 1:
+            raise ValueError("max_group must be at least 1")
         self.clock = clock
         self.sleep = sleep
 
@@ -148,7 +156,7 @@ class Scheduler:
         records: list[FrameRecord] = []
         tick_frames: dict[int, list[int]] = {}
         queue_wait = []
-        stats = dict(admitted=0, max_queue=0, max_active=0, ticks=0, max_batch=0)
+        stats = dict(admitted=0, max_queue=0, max_active=0, ticks=0, max_batch=0, max_group=0)
         t0 = self.clock()
         now = 0.0
         horizon = until_s if until_s is not None else max((s.arrival_s + s.lifetime_s for s in pending), default=0.0)
@@ -187,26 +195,40 @@ class Scheduler:
                 stats["admitted"] += 1
             stats["max_queue"] = max(stats["max_queue"], len(queue))
             stats["max_active"] = max(stats["max_active"], len(active))
-            # continuous batching: the oldest due frame of every active session, once the GPU
-            # has room for another tick
+            # continuous batching: every active session's due frames (at most max_group, oldest
+            # first), once the GPU has room for another tick
             batch = []
             if len(tick_frames) < self.max_inflight:
                 for a in active.values():
-                    if a.due_s(a.next_frame) <= now and a.due_s(a.next_frame) < a.end_s:
-                        batch.append(a)
+                    m = 0
+                    while m < self.max_group and a.due_s(a.next_frame + m) <= now and \
+                            a.due_s(a.next_frame + m) < a.end_s:
+                        m += 1
+                    if m:
+                        batch.append([a, m])
                 cap = getattr(ex, "max_batch", None)
-                if cap is not None and len(batch) > cap:    # the rest stay due for the next tick
-                    batch.sort(key=lambda a: a.due_s(a.next_frame))
-                    batch = batch[:cap]
+                if cap is not None and sum(m for _, m in batch) > cap:   # the rest stay due for the next tick
+                    batch.sort(key=lambda am: am[0].due_s(am[0].next_frame))
+                    left, kept = cap, []
+                    for a, m in batch:
+                        if left == 0:
+                            break
+                        kept.append([a, min(m, left)])
+                        left -= kept[-1][1]
+                    batch = kept
             if batch:
-                stats["max_batch"] = max(stats["max_batch"], len(batch))
-                tick = ex.submit([(a.handle, a.next_frame) for a in batch])
+                n_frames = sum(m for _, m in batch)
+                stats["max_batch"] = max(stats["max_batch"], n_frames)
+                stats["max_group"] = max(stats["max_group"], max(m for _, m in batch))
+                tick = ex.submit([(a.handle, a.next_frame + j) for a, m in batch for j in range(m)])
                 stats["ticks"] += 1
                 idx = []
-                for a in batch:
-                    records.append(FrameRecord(a.spec.sid, a.next_frame, a.due_s(a.next_frame), now, tick))
-                    idx.append(len(records) - 1)
-                    a.next_frame += 1
+                for a, m in batch:
+                    for j in range(m):
+                        i = a.next_frame + j
+                        records.append(FrameRecord(a.spec.sid, i, a.due_s(i), now, tick))
+                        idx.append(len(records) - 1)
+                    a.next_frame += m
                 tick_frames[tick] = idx
             finish_completed(ex.poll())
             if pi >= len(pending) and not queue and not active:
@@ -238,7 +260,7 @@ class Scheduler:
                           deadline_misses=int(np.count_nonzero(lat > DEADLINE_MS)), admitted=stats["admitted"],
                           rejected=len(sessions) - stats["admitted"], max_queue=stats["max_queue"],
                           max_active=stats["max_active"], ticks=stats["ticks"], max_batch=stats["max_batch"],
-                          queue_wait_s=queue_wait)
+                          max_group=stats["max_group"], queue_wait_s=queue_wait)
 
 
 # ---------------------------------------------------------------------------
@@ -315,8 +337,9 @@ class _GpuExecutor:
 
 
 class BatchedExecutor(_GpuExecutor):
-    """One batched tick for all due frames: one kernel launch for all of them, issued directly or
-    (use_graph) as the replay of a HIP graph (the descriptor-table copy and the kernel)."""
+    """One batched tick for all due frames: one kernel launch for all of them (a session's several
+    frames as one group), issued directly or (use_graph) as the replay of a HIP graph (the
+    descriptor-table copy and the kernel)."""
 
     def __init__(self, frames_by_size: dict, max_frames: int = 64, use_graph: bool = True, **kw):
         super().__init__(frames_by_size, **kw)

@@ -565,6 +565,92 @@ def test_fwrs_tick_equals_plain_calls(dev):
         assert tick_ctx[i].stats() == plain_ctx[i].stats()
 
 
+def _group_schedule(n_ctx, n_frames, seed):
+    """Ticks of a group-tick run: each a list of (context, frame index) in which every context's
+    entries are its next consecutive frames (1 to 6 of them, drawn per tick), interleaved across
+    contexts at random but in order within each context."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    done = [0] * n_ctx
+    ticks = []
+    while min(done) < n_frames:
+        queues = []
+        for i in range(n_ctx):
+            m = min(int(rng.choice([1, 1, 2, 3, 4, 6])), n_frames - done[i])
+            queues.append([(i, done[i] + j) for j in range(m)])
+            done[i] += m
+        entries = []
+        while any(queues):
+            live = [q for q in queues if q]
+            entries.append(live[int(rng.integers(len(live)))].pop(0))
+        ticks.append(entries)
+    return ticks
+
+
+@pytest.mark.parametrize("api", ["tick", "engine_graph", "engine_direct", "noalloc"])
+def test_tick_groups_equal_plain_calls(dev, api):
+    """Ticks in which a context appears several times -- its consecutive frames, run as one group
+    (the pixel state held in registers across the group's frames for k in {1, 2, 4, 8} with one
+    w_sum per pixel; each frame through the store in turn otherwise) -- equal one
+    fwrs_push_frame_resolve per frame, bit for bit: every frame's output, the state and the
+    counters, from the empty store on and through the resolve plane's switch-over (inside groups
+    too); the oracle agrees on every stream at the end."""
+    nf = 40
+    cases = [(256, 144, 2, fwrs.BIAS_BERNOULLI, 0), (200, 100, 4, fwrs.BIAS_BERNOULLI, None),
+             (96, 64, 8, fwrs.BIAS_BERNOULLI, 3), (130, 70, 8, fwrs.BIAS_BERNOULLI, None),
+             (37, 23, 3, fwrs.BIAS_NONE, 0), (160, 90, 4, fwrs.BIAS_FULL, None), (64, 48, 4, fwrs.AES, None),
+             (120, 60, 4, fwrs.BIAS_MEMORYLESS, 2), (33, 17, 16, fwrs.BIAS_BERNOULLI, 0),
+             (50, 40, 1, fwrs.BIAS_NONE, 5), (72, 40, 4, fwrs.BIAS_BERNOULLI, "no plane")]
+    stream = torch.cuda.current_stream()
+    tick_ctx, plain_ctx, orcs, frames, outs_t, outs_p = [], [], [], [], [], []
+    for i, (w, h, k, bias, res_from) in enumerate(cases):
+        s = synth.StreamSpec(w, h, k, nf, 0.1 * w, 0.25 * w, 2.0, 3, 4.0, stream_id=40 + i)
+        p, q = _params(s, bias)
+        if res_from == "no plane":
+            p.flags = fwrs.FLAG_NO_RESOLVE_PLANE
+        tick_ctx.append(fwrs.Reservoir(w, h, k, p, stream=stream))
+        plain_ctx.append(fwrs.Reservoir(w, h, k, p, stream=stream))
+        if isinstance(res_from, int):
+            tick_ctx[-1].set_resolve_plane_from(res_from)
+            plain_ctx[-1].set_resolve_plane_from(res_from)
+        tick_ctx[-1].set_tile(*[(64, 1), (16, 16), (32, 8)][i % 3])
+        orcs.append(oracle.Oracle(w, h, k, q))
+        src = synth.FrameSource(s, device=dev, n_frames=nf)
+        frames.append([src.frame(t) for t in range(nf)])
+        outs_t.append(torch.full((nf, h, w, 3), -1.0, device=dev))
+        outs_p.append(torch.full((nf, h, w, 3), -2.0, device=dev))
+    eng = fwrs.Engine(128, stream=stream, use_graph=api == "engine_graph") if api.startswith("engine") else None
+    ticks = _group_schedule(len(cases), nf, seed=7)
+    assert max(len(e) for e in ticks) <= fwrs.TICK_NOALLOC_MAX
+    assert any(len(e) > len({i for i, _ in e}) for e in ticks)
+    for entries in ticks:
+        batch = [(tick_ctx[i], *frames[i][t], outs_t[i][t]) for (i, t) in entries]
+        if api == "tick":
+            fwrs.tick(batch, stream=stream)
+        elif api == "noalloc":
+            fwrs.tick_noalloc(batch, stream=stream)
+        else:
+            eng.tick(batch)
+    for i in range(len(cases)):
+        for t in range(nf):
+            plain_ctx[i].step(*frames[i][t], outs_p[i][t])
+            c, lev, gx, gy = frames[i][t]
+            orcs[i].push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+    torch.cuda.synchronize()
+    if eng is not None:
+        eng.close()
+    for i, case in enumerate(cases):
+        for t in range(nf):
+            assert torch.equal(outs_t[i][t], outs_p[i][t]), f"frame {t} case {case} ({api})"
+        assert tick_ctx[i].frame_index == nf
+        _compare_state(tick_ctx[i].download(), plain_ctx[i].download(), f"case {case} ({api})")
+        _compare_state(tick_ctx[i].download(), orcs[i].state(), f"oracle case {case} ({api})")
+        _compare_out(outs_t[i][nf - 1].cpu().numpy(), orcs[i].resolve(), f"case {case} ({api})")
+        assert tick_ctx[i].stats() == plain_ctx[i].stats(), f"case {case} ({api})"
+        tick_ctx[i].close()
+        plain_ctx[i].close()
+        orcs[i].close()
+
+
 @pytest.mark.parametrize("n,w,h", [(300, 24, 8), (48, 256, 256)])
 def test_tick_of_many_frames(dev, n, w, h):
     """Ticks of many frames: 300 one-item frames and 48 frames of 256 items each (12288 blocks in one
@@ -631,13 +717,15 @@ def test_engine_rejects_bad_ticks(dev):
     c = torch.zeros((16, 32, 3), device=dev)
     lev = torch.zeros((16, 32), dtype=torch.uint8, device=dev)
     out = torch.empty_like(c)
-    with pytest.raises(fwrs.FwrsError):
-        eng.tick([(r, c, lev, 1.0, 1.0, out), (r, c, lev, 1.0, 1.0, out)])   # repeated context
     with pytest.raises(ValueError):
         eng.tick([(r, c, lev, 1.0, 1.0, out)] * 3)                            # over capacity
     with pytest.raises(fwrs.FwrsError):
         eng.tick([(r, c, lev, float("nan"), 1.0, out)])
+    with pytest.raises(fwrs.FwrsError):                                       # one bad entry of a group
+        eng.tick([(r, c, lev, 1.0, 1.0, out), (r, c, lev, 1.0, float("inf"), out)])
     assert r.frame_index == 0
+    eng.tick([(r, c, lev, 1.0, 1.0, out), (r, c, lev, 1.0, 1.0, out)])       # a context's two frames
+    assert r.frame_index == 2
     with pytest.raises(fwrs.FwrsError):
         r.set_tile(3, 8)
     eng.close()

@@ -29,17 +29,26 @@ def _rings(dev, sizes, n=8):
     return rings
 
 
-@pytest.mark.parametrize("executor", ["batched", "plain"])
-def test_each_session_alone_equals_in_the_mix(dev, executor):
+@pytest.mark.parametrize("executor,max_group", [("batched", 1), ("plain", 1), ("batched", 6), ("plain", 6)])
+def test_each_session_alone_equals_in_the_mix(dev, executor, max_group):
+    """max_group 6 with frame rates above what the loop keeps up with: ticks carry several frames
+    of a session (one group in the batched executor), and the outputs are still those of the
+    session run alone."""
     sizes = ((128, 64), (96, 48))
+    fps = (150.0, 240.0) if max_group == 1 else (6000.0, 9000.0)
     sessions = serve.poisson_sessions(n=6, rate_per_s=20.0, seed=11, lifetime_s=(0.15, 0.4), sizes=sizes,
-                                      ks=(2, 3, 4), fps=(150.0, 240.0))
+                                      ks=(2, 3, 4, 8), fps=fps)
+    if max_group > 1:
+        sessions = [serve.SessionSpec(s.sid, s.arrival_s, s.lifetime_s / 4, s.width, s.height, s.k, s.fps)
+                    for s in sessions]
     rings = _rings(dev, sizes)
     stream = torch.cuda.current_stream()
-    ex = (serve.BatchedExecutor(rings, max_frames=8, stream=stream) if executor == "batched"
+    ex = (serve.BatchedExecutor(rings, max_frames=64, stream=stream) if executor == "batched"
           else serve.PlainExecutor(rings, stream=stream))
-    sched = serve.Scheduler(ex, budget_bytes=1 << 30, max_active=8)
+    sched = serve.Scheduler(ex, budget_bytes=1 << 30, max_active=8, max_group=max_group)
     st = sched.run(sessions)
+    if max_group > 1:
+        assert st.max_group > 1, "no tick carried several frames of a session"
     assert st.frames == sum(sched.frames_done.values()) and st.frames > 0
     assert st.latency_ms.size == st.frames
     for s in sessions:

@@ -183,3 +183,49 @@ def test_ticks_never_exceed_the_executors_batch_limit():
             assert seen.get(sid, -1) == i - 1
             seen[sid] = i
     assert st.frames == sum(len(f) for _, f in ex.log) and st.admitted == len(sessions)
+
+
+def _check_order(log, max_group):
+    """Every session's frames once, in order; in a tick a session's frames are consecutive and at
+    most max_group of them."""
+    seen = {}
+    most = 0
+    for _, frames in log:
+        per = {}
+        for sid, i in frames:
+            assert seen.get(sid, -1) == i - 1, "frames of a session in order, none skipped"
+            seen[sid] = i
+            per[sid] = per.get(sid, 0) + 1
+        most = max([most] + list(per.values()))
+        assert all(v <= max_group for v in per.values())
+    return seen, most
+
+
+def test_groups_take_a_sessions_due_frames_together():
+    """max_group > 1: when the device falls behind, a tick takes up to max_group of a session's due
+    frames (consecutive, oldest first), and still every frame once, in order."""
+    sessions = _small_mix(n=8, scale=0.05)
+    clk = VirtualClock()
+    ex = FakeExecutor(clk, 2e-6)
+    st = serve.Scheduler(ex, 1 << 40, max_active=8, max_group=4, clock=clk, sleep=clk.sleep).run(sessions)
+    _, most = _check_order(ex.log, 4)
+    assert most == 4, "a busy device makes sessions fall behind: groups fill up"
+    assert st.frames == sum(len(f) for _, f in ex.log) and st.admitted == len(sessions)
+    # the same sessions on a fast device: no frame waits, so no groups form
+    clk = VirtualClock()
+    fast = FakeExecutor(clk, 1e-13)
+    serve.Scheduler(fast, 1 << 40, max_active=8, max_group=4, clock=clk, sleep=clk.sleep).run(sessions)
+    assert _check_order(fast.log, 4)[1] == 1
+
+
+def test_groups_respect_the_executors_batch_limit():
+    sessions = _small_mix(n=12, scale=0.02)
+    clk = VirtualClock()
+    ex = FakeExecutor(clk, 1e-6)
+    ex.max_batch = 5
+    st = serve.Scheduler(ex, 1 << 40, max_active=12, max_group=3, clock=clk, sleep=clk.sleep).run(sessions)
+    assert max(len(f) for _, f in ex.log) <= 5 and st.max_batch <= 5
+    _check_order(ex.log, 3)
+    assert st.frames == sum(len(f) for _, f in ex.log) and st.admitted == len(sessions)
+    with pytest.raises(ValueError):
+        serve.Scheduler(ex, 1 << 40, max_group=0)
