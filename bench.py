@@ -224,6 +224,49 @@ def multistream(dev, stream, specs, gazes, ticks: int, ring: int, use_graph: boo
     return result
 
 
+def group_ticks(dev, stream, spec, frames, tile, ks=(4, 8), sizes=(1, 2, 4, 8), n: int = 96, warm: int = 40) -> dict:
+    """A session's consecutive frames as one group: one 4K stream, past its resolve-plane switch
+    (`warm` untimed frames first), runs the next n resident frames through fwrs_tick as groups of
+    F consecutive frames (one launch per group) and, on a second context, as one plain launch per
+    frame; milliseconds per frame on the GPU clock for each slot count k and group size F."""
+    import torch
+
+    from paper_2510_03964_amd import fwrs, synth
+
+    result = {"width": spec.width, "height": spec.height, "frames": n, "warm_frames": warm}
+    for k in ks:
+        p = fwrs.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED)
+        row = {}
+        for F in (0, *sizes):                      # F = 0: plain launches
+            r = fwrs.Reservoir(spec.width, spec.height, k, p, stream=stream)
+            if tile:
+                r.set_tile(*tile)
+            out = torch.empty((spec.height, spec.width, 3), dtype=torch.float32, device=dev)
+            for t in range(warm):
+                r.step(*frames[t], out)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record(stream)
+            if F == 0:
+                for t in range(warm, warm + n):
+                    r.step(*frames[t], out)
+            else:
+                for g in range(warm, warm + n, F):
+                    fwrs.tick([(r, *frames[t], out) for t in range(g, min(g + F, warm + n))], stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / n
+            row["plain" if F == 0 else f"group_{F}"] = {"ms_per_frame": ms,
+                                                        "gpix_per_s": spec.pixels / (ms / 1e3) / 1e9}
+            r.close()
+        for F in sizes:
+            row[f"group_{F}"]["speedup_over_plain"] = row["plain"]["ms_per_frame"] / row[f"group_{F}"]["ms_per_frame"]
+        result[f"k{k}"] = row
+        log(f"groups k={k}: plain {row['plain']['ms_per_frame']:.4f} ms/frame, " +
+            ", ".join(f"F={F} {row[f'group_{F}']['ms_per_frame']:.4f}" for F in sizes))
+    return result
+
+
 def serving(dev, stream, time_scale: float, fps_scale: float, ring: int, label: str, max_group: int = 8) -> dict:
     """32 sessions arriving as a Poisson process (mean 1/s; lifetime U[10, 60] s; 1920x1080 or
     3840x2160; k in {4, 8}; 72, 90 or 120 Hz), arrivals and lifetimes compressed by `time_scale`
@@ -584,6 +627,7 @@ def main() -> int:
     ap.add_argument("--reproject-ring", type=int, default=240, help="distinct moving frames kept resident")
     ap.add_argument("--no-multistream", action="store_true", help="skip the batched-vs-plain runs")
     ap.add_argument("--ring", type=int, default=48, help="distinct frames per stream kept resident (multistream)")
+    ap.add_argument("--no-groups", action="store_true", help="skip the grouped-frames run")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving runs")
     ap.add_argument("--serving-scale", type=float, default=0.25, help="time compression of the serving run")
     args = ap.parse_args()
@@ -598,7 +642,7 @@ def main() -> int:
     if args.headline_only:
         # the copy-bandwidth reference stays: it is the counters' calibration kernel
         for name in ("no_incremental", "no_eq7", "no_ablations", "no_foveated", "no_reproject",
-                     "no_multistream", "no_serving"):
+                     "no_multistream", "no_groups", "no_serving"):
             setattr(args, name, True)
         args.cpu_frames = 0
 
@@ -709,6 +753,8 @@ def main() -> int:
 
     ablation = None if args.no_ablations else ablations(dev, stream, spec, frames, tile)
 
+    groups = None if args.no_groups else group_ticks(dev, stream, spec, frames, tile)
+
     copy_gbps = None if args.no_copy else copy_bandwidth(torch, dev)
 
     host = [(c.cpu().numpy(), lev.cpu().numpy(), gx, gy) for (c, lev, gx, gy) in frames[:args.cpu_frames]]
@@ -740,7 +786,7 @@ def main() -> int:
     if not args.no_serving:
         torch.cuda.empty_cache()
         served = {"paced": serving(dev, stream, args.serving_scale, 1.0, 24, "serving"),
-                  "saturated": serving(dev, stream, 0.4 * args.serving_scale, 4.0, 24, "saturated")}
+                  "saturated": serving(dev, stream, 0.4 * args.serving_scale, 8.0, 24, "saturated")}
 
     cpu = None
     if args.cpu_frames > 0:
@@ -781,6 +827,7 @@ def main() -> int:
         "ablations": ablation,
         "foveated": fov,
         "multistream": multi,
+        "groups": groups,
         "serving": served,
         "copy_gbps": copy_gbps,
     }

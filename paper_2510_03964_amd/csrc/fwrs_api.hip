@@ -700,7 +700,7 @@ struct TickSlot {
     void* dev = nullptr;                // device table
     hipEvent_t done = nullptr;          // end of the slot's latest tick
     bool pending = false;               // `done` recorded, not yet waited for
-    TickGraph graph[2];                 // for ticks without / with groups (the two kernels)
+    TickGraph graph[fwrs::kTickKinds];  // one per kind of tick (the batched kernel's instantiations)
     const void* head_arg = nullptr;     // the kernel node's argument values
     const void* descs_arg = nullptr;
     void* kparams[2] = {nullptr, nullptr};
@@ -743,16 +743,17 @@ bool group_kernel(const fwrs_ctx* x)
 std::atomic<uint64_t> g_tick_marks{0};
 
 // Lays out the tick of frames[0 .. n) (each entry checked by check_tick): the
-// table's head and descriptors, and the op each entry runs as (ops[i], the
-// op its context then advances by).  The entries of one context are its
+// table's head and descriptors, the op each entry runs as (ops[i], the op its
+// context then advances by) and the batched kernel's kind for the table.  The entries of one context are its
 // consecutive frames in the order given and form one group; groups are
 // visited in the order of their first entries, reversed (each group's items
 // too) if `reverse`.  FWRS_E_STATE if a context's frames would run past the
 // last frame index.
 template <typename TileFn>
 int layout_tick(const fwrs_frame* frames, int n, bool reverse, TileFn tile, TickWork w, fwrs::TickHead* head,
-                FrameDesc* descs, int* ops)
+                FrameDesc* descs, int* ops, int& kind)
 {
+    kind = fwrs::kTickAlone;
     const uint64_t mark = g_tick_marks.fetch_add(1u, std::memory_order_relaxed) + 1u;
     int groups = 0;
     for (int i = 0; i < n; ++i) {
@@ -790,6 +791,8 @@ int layout_tick(const fwrs_frame* frames, int n, bool reverse, TileFn tile, Tick
         const bool plane = w.plane[g] != 0;
         const int op = nf > 1 && group_kernel(x) ? fwrs::kOpGroup : fused_op_at(x, d.t, plane);
         w.plane[g] = plane_after(x, op) ? 1 : 0;
+        if (nf > 1 && kind != fwrs::kTickGroups8)
+            kind = op == fwrs::kOpGroup && x->k == 8 ? fwrs::kTickGroups8 : fwrs::kTickGroups;
         ops[i] = op;
         d.op = (uint32_t)op;
         d.res_ok = plane ? 1u : 0u;
@@ -890,10 +893,10 @@ void engine_tile(const fwrs_engine* e, const fwrs_ctx* x, int& tx, int& ty)
         }
 }
 
-hipKernelNodeParams tick_node(TickSlot& sl, bool groups, uint32_t grid)
+hipKernelNodeParams tick_node(TickSlot& sl, int kind, uint32_t grid)
 {
     hipKernelNodeParams kp{};
-    kp.func = fwrs::tick_kernel_entry(groups);
+    kp.func = fwrs::tick_kernel_entry(kind);
     kp.gridDim = dim3(grid);
     kp.blockDim = dim3(fwrs::kBlock);
     kp.sharedMemBytes = 0;
@@ -902,13 +905,12 @@ hipKernelNodeParams tick_node(TickSlot& sl, bool groups, uint32_t grid)
     return kp;
 }
 
-// The slot's graph for the kernel with or without groups: the copy of `bytes`
-// of its table, then the kernel on `grid` blocks.  A built graph is updated
-// only where the tick's size differs from the one it holds.  On failure
-// nothing is left half built.
-hipError_t slot_graph(TickSlot& sl, bool groups, size_t bytes, uint32_t grid)
+// The slot's graph for a kind of tick: the copy of `bytes` of its table, then
+// the kernel on `grid` blocks.  A built graph is updated only where the tick's
+// size differs from the one it holds.  On failure nothing is left half built.
+hipError_t slot_graph(TickSlot& sl, int kind, size_t bytes, uint32_t grid)
 {
-    TickGraph& g = sl.graph[groups ? 1 : 0];
+    TickGraph& g = sl.graph[kind];
     if (g.exec) {
         hipError_t err = hipSuccess;
         if (g.copy_bytes != bytes) {
@@ -916,7 +918,7 @@ hipError_t slot_graph(TickSlot& sl, bool groups, size_t bytes, uint32_t grid)
             if (err == hipSuccess) g.copy_bytes = bytes;
         }
         if (err == hipSuccess && g.grid != grid) {
-            hipKernelNodeParams kp = tick_node(sl, groups, grid);
+            hipKernelNodeParams kp = tick_node(sl, kind, grid);
             err = hipGraphExecKernelNodeSetParams(g.exec, g.kernel, &kp);
             if (err == hipSuccess) g.grid = grid;
         }
@@ -926,7 +928,7 @@ hipError_t slot_graph(TickSlot& sl, bool groups, size_t bytes, uint32_t grid)
     if (err == hipSuccess)
         err = hipGraphAddMemcpyNode1D(&g.copy, g.graph, nullptr, 0, sl.dev, sl.host, bytes, hipMemcpyHostToDevice);
     if (err == hipSuccess) {
-        hipKernelNodeParams kp = tick_node(sl, groups, grid);
+        hipKernelNodeParams kp = tick_node(sl, kind, grid);
         err = hipGraphAddKernelNode(&g.kernel, g.graph, &g.copy, 1, &kp);
     }
     if (err == hipSuccess) err = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
@@ -962,8 +964,9 @@ int engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n, hipStream_t str
     const bool reverse = (e->ticks & 1u) != 0u;
     fwrs::TickHead* head = static_cast<fwrs::TickHead*>(sl.host);
     FrameDesc* descs = reinterpret_cast<FrameDesc*>(static_cast<char*>(sl.host) + fwrs::kTickDescOffset);
+    int kind = fwrs::kTickAlone;
     const int lrc = layout_tick(frames, n, reverse, [e](const fwrs_ctx* x, int& tx, int& ty) { engine_tile(e, x, tx, ty); },
-                                TickWork(e->work.data(), (size_t)e->max_frames), head, descs, e->ops.data());
+                                TickWork(e->work.data(), (size_t)e->max_frames), head, descs, e->ops.data(), kind);
     if (lrc != FWRS_OK) return lrc;
     // each context's earlier work on its own stream comes first
     hipError_t err = hipSuccess;
@@ -976,13 +979,12 @@ int engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n, hipStream_t str
         }
     }
     const size_t bytes = fwrs::tick_table_bytes((size_t)n);
-    const bool groups = head->n < (uint32_t)n;      // some context has several frames
     if (err == hipSuccess && e->use_graph) {
-        err = slot_graph(sl, groups, bytes, head->total);
-        if (err == hipSuccess) err = hipGraphLaunch(sl.graph[groups ? 1 : 0].exec, stream);
+        err = slot_graph(sl, kind, bytes, head->total);
+        if (err == hipSuccess) err = hipGraphLaunch(sl.graph[kind].exec, stream);
     } else if (err == hipSuccess) {
         err = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream);
-        if (err == hipSuccess) err = fwrs::launch_tick(sl.dev, head->total, groups, stream);
+        if (err == hipSuccess) err = fwrs::launch_tick(sl.dev, head->total, kind, stream);
     }
     if (err == hipSuccess) err = hipEventRecord(sl.done, stream);
     if (err != hipSuccess) {
@@ -1165,10 +1167,11 @@ int fwrs_tick_noalloc(const fwrs_frame* frames, int n, void* hip_stream)
     int work[kTickWorkInts * kStaticTickFrames];
     FrameDesc descs[kStaticTickFrames];
     fwrs::TickFill fill{};
+    int kind = fwrs::kTickAlone;
     const int lrc = layout_tick(frames, n, reverse, [](const fwrs_ctx* x, int& tx, int& ty) {
         tx = x->tile_x;
         ty = x->tile_y;
-    }, TickWork(work, kStaticTickFrames), &fill.head, descs, ops);
+    }, TickWork(work, kStaticTickFrames), &fill.head, descs, ops, kind);
     if (lrc != FWRS_OK) return lrc;
     // the descriptors, kFillFrames per fill launch, then the batched kernel
     hipError_t err = hipSuccess;
@@ -1179,7 +1182,7 @@ int fwrs_tick_noalloc(const fwrs_frame* frames, int n, void* hip_stream)
         std::memcpy(fill.descs, descs + at, fill.count * sizeof(FrameDesc));
         err = fwrs::launch_tick_fill(table, fill, stream);
     }
-    if (err == hipSuccess) err = fwrs::launch_tick(table, fill.head.total, fill.head.n < (uint32_t)n, stream);
+    if (err == hipSuccess) err = fwrs::launch_tick(table, fill.head.total, kind, stream);
     if (err != hipSuccess) {
         (void)hipGetLastError();
         return FWRS_E_HIP;

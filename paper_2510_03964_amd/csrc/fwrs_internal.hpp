@@ -38,11 +38,16 @@ static_assert(sizeof(TickHead) == kTickDescOffset, "descriptors follow the head"
 inline size_t tick_table_bytes(size_t frames) { return kTickDescOffset + frames * sizeof(FrameDesc); }
 
 // The batched kernel on `grid` blocks (block b takes work items b, b + grid,
-// ... of the table's tick; the engine launches one block per item); `groups`:
-// the table has groups (some leader with nf > 1).
-hipError_t launch_tick(const void* table, uint32_t grid, bool groups, hipStream_t stream);
+// ... of the table's tick; the engine launches one block per item), in the
+// instantiation for the kind of tick the table holds: no groups (no leader
+// with nf > 1), groups, or groups among which one with op kOpGroup and k = 8.
+constexpr int kTickAlone = 0;
+constexpr int kTickGroups = 1;
+constexpr int kTickGroups8 = 2;
+constexpr int kTickKinds = 3;
+hipError_t launch_tick(const void* table, uint32_t grid, int kind, hipStream_t stream);
 // Its entry points, for HIP graph kernel nodes: arguments (const TickHead*, const FrameDesc*).
-void* tick_kernel_entry(bool groups);
+void* tick_kernel_entry(int kind);
 
 // One launch of the table-fill kernel: writes `count` descriptors (kernel
 // arguments) to table slots at .. at + count - 1, and the head if write_head.

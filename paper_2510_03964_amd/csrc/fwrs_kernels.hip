@@ -363,64 +363,30 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
 // end go w_sum, the replaced slots' records and frame indices, and the
 // resolve plane (where the pixel changed, or everywhere if it did not hold the
 // resolve), so the results are those of the frames run one by one, bit for bit.
+//
+// The frames are software-pipelined so that no frame waits for its own loads:
+// a frame's level is read one frame ahead, and a frame is applied (slots
+// replaced, resolve, output) one frame after its decision, once the next
+// frame's loads are in flight.  The decision chain needs only w_sum and the
+// level, so deciding frame f before applying frame f - 1 changes nothing.
+// The colour load is issued by every pixel (those that take nothing read the
+// frame's first texel, one line per wave), so no load sits in a branch and
+// each wait covers exactly the loads it needs.
 // Adds the replaced slots and the frames in which the pixel changed.
 // ---------------------------------------------------------------------------
 template <int K>
-__device__ __forceinline__ void pixel_group(const FrameDesc& d0, const FrameDesc* __restrict__ later, uint32_t x,
-                                            uint32_t y, uint32_t& slots, uint32_t& changed)
-{
-    const uint32_t p = y * d0.width + x;
-    float4* rec = reinterpret_cast<float4*>(d0.rec) + (size_t)p * K;
-    uint32_t* idx = d0.idx + (size_t)p * K;
-    float* res = d0.res + 3 * (size_t)p;
-    const bool keep = d0.res != nullptr;
-    const bool empty = d0.t == 0u;              // the empty store: every slot zero, nothing to read
-    const bool from_plane = keep && d0.res_ok != 0u && !empty;
-
-    float W1 = ld<kNtWsumLd>(d0.wsum + p);
+struct GroupPixel {
     float4 r[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) r[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-    float q0 = 0.f, q1 = 0.f, q2 = 0.f;
-    bool have = true;                           // the record is in registers
-    if (from_plane) {
-        q0 = ld<kNtResLd>(res + 0);
-        q1 = ld<kNtResLd>(res + 1);
-        q2 = ld<kNtResLd>(res + 2);
-        have = false;
-    } else if (!empty) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) r[j] = ld4<kNtRecLd>(rec + j);
-        resolve_slots<K>(r, q0, q1, q2);
-    }
+    uint32_t tj[K];                             // the replaced slots' last frame index
     uint32_t dirty = 0u;                        // slots replaced in the group
-    uint32_t tj[K];                             // their last replacement's frame index
-#pragma unroll
-    for (int j = 0; j < K; ++j) tj[j] = 0u;
+    float q0 = 0.f, q1 = 0.f, q2 = 0.f;         // the resolve as of the last applied frame
 
-    for (uint32_t f = 0; f < d0.nf; ++f) {
-        const FrameDesc& d = f == 0u ? d0 : later[f - 1u];
-        const uint32_t lv = ld<kNtLevel>(d.level + p);
-        const Words<K> words = philox_words<K>(d, p);
-        const float dx = ((float)x + 0.5f) - d.gx;
-        const float dy = ((float)y + 0.5f) - d.gy;
-        float e = 0.f;
-        const float outside = weight_outside(d.c, dx * dx + dy * dy, e);
-        const float w = select_eq4(d.c, outside, e, lv);
-        const float W1b = bias_shared(W1, w, d.bias, d.c.decay);
-        const float s = W1b + w;
-        const uint32_t tk = decide_words<K>(words, W1b, s);
-        W1 = s;
+    // Frame d's decision tk (weight w, colour c) becomes part of the record.
+    __device__ __forceinline__ void apply(const FrameDesc& d, uint32_t p, uint32_t tk, float w, float c0, float c1,
+                                          float c2, uint32_t& slots, uint32_t& changed)
+    {
         if (tk) {
-            const float* color = d.color + 3 * (size_t)p;
-            const float4 fresh = make_float4(w, ld<kNtColor>(color + 0), ld<kNtColor>(color + 1),
-                                             ld<kNtColor>(color + 2));
-            if (!have) {
-#pragma unroll
-                for (int j = 0; j < K; ++j)
-                    if (!((tk >> j) & 1u)) r[j] = ld4<kNtRecLd>(rec + j);
-                have = true;
-            }
+            const float4 fresh = make_float4(w, c0, c1, c2);
 #pragma unroll
             for (int j = 0; j < K; ++j)
                 if ((tk >> j) & 1u) {
@@ -437,18 +403,89 @@ __device__ __forceinline__ void pixel_group(const FrameDesc& d0, const FrameDesc
         st<kNtOut>(o + 1, q1);
         st<kNtOut>(o + 2, q2);
     }
+};
+
+template <int K>
+__device__ __forceinline__ void pixel_group(const FrameDesc& d0, const FrameDesc* __restrict__ later, uint32_t x,
+                                            uint32_t y, uint32_t& slots, uint32_t& changed)
+{
+    const uint32_t p = y * d0.width + x;
+    const uint32_t nf = d0.nf;
+    float4* rec = reinterpret_cast<float4*>(d0.rec) + (size_t)p * K;
+    uint32_t* idx = d0.idx + (size_t)p * K;
+    float* res = d0.res + 3 * (size_t)p;
+    const bool keep = d0.res != nullptr;
+    const bool empty = d0.t == 0u;              // the empty store: every slot zero, nothing to read
+    const bool from_plane = keep && d0.res_ok != 0u && !empty;
+
+    GroupPixel<K> g;
+    float W1 = ld<kNtWsumLd>(d0.wsum + p);
+    uint32_t lv = ld<kNtLevel>(d0.level + p);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        g.r[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        g.tj[j] = 0u;
+    }
+    bool have = true;                           // the record is in registers (or on its way)
+    if (from_plane) {
+        g.q0 = ld<kNtResLd>(res + 0);
+        g.q1 = ld<kNtResLd>(res + 1);
+        g.q2 = ld<kNtResLd>(res + 2);
+        have = false;
+    } else if (!empty) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) g.r[j] = ld4<kNtRecLd>(rec + j);
+        resolve_slots<K>(g.r, g.q0, g.q1, g.q2);
+    }
+
+    // the decided frame still to apply
+    uint32_t ptk = 0u;
+    float pw = 0.f, pc0 = 0.f, pc1 = 0.f, pc2 = 0.f;
+    for (uint32_t f = 0; f < nf; ++f) {
+        const FrameDesc& d = f == 0u ? d0 : later[f - 1u];
+        uint32_t lv_next = 0u;
+        if (f + 1u < nf) lv_next = ld<kNtLevel>(later[f].level + p);
+        // the decision: Eq. 4 weight, bias, Alg. 2 per slot
+        const float dx = ((float)x + 0.5f) - d.gx;
+        const float dy = ((float)y + 0.5f) - d.gy;
+        float e = 0.f;
+        const float outside = weight_outside(d.c, dx * dx + dy * dy, e);
+        const float w = select_eq4(d.c, outside, e, lv);
+        const float W1b = bias_shared(W1, w, d.bias, d.c.decay);
+        const float s = W1b + w;
+        const uint32_t tk = decide_words<K>(philox_words<K>(d, p), W1b, s);
+        W1 = s;
+        // its colour, and at the pixel's first replacement the slots it keeps
+        const float* cp = d.color + (tk ? 3 * (size_t)p : 0);
+        const float c0 = ld<kNtColor>(cp + 0), c1 = ld<kNtColor>(cp + 1), c2 = ld<kNtColor>(cp + 2);
+        // the previous frame
+        if (f) g.apply(f == 1u ? d0 : later[f - 2u], p, ptk, pw, pc0, pc1, pc2, slots, changed);
+        if (tk && !have) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (!((tk >> j) & 1u)) g.r[j] = ld4<kNtRecLd>(rec + j);
+            have = true;
+        }
+        ptk = tk;
+        pw = w;
+        pc0 = c0;
+        pc1 = c1;
+        pc2 = c2;
+        lv = lv_next;
+    }
+    g.apply(nf == 1u ? d0 : later[nf - 2u], p, ptk, pw, pc0, pc1, pc2, slots, changed);
 
     st<kNtWsumSt>(d0.wsum + p, W1);
 #pragma unroll
     for (int j = 0; j < K; ++j)
-        if ((dirty >> j) & 1u) {
-            st4<kNtRecSt>(rec + j, r[j]);
-            st<kNtIdxSt>(idx + j, tj[j]);
+        if ((g.dirty >> j) & 1u) {
+            st4<kNtRecSt>(rec + j, g.r[j]);
+            st<kNtIdxSt>(idx + j, g.tj[j]);
         }
-    if (keep && (dirty != 0u || !from_plane)) {
-        st<kNtResSt>(res + 0, q0);
-        st<kNtResSt>(res + 1, q1);
-        st<kNtResSt>(res + 2, q2);
+    if (keep && (g.dirty != 0u || !from_plane)) {
+        st<kNtResSt>(res + 0, g.q0);
+        st<kNtResSt>(res + 1, g.q1);
+        st<kNtResSt>(res + 2, g.q2);
     }
 }
 
@@ -706,7 +743,8 @@ __device__ __forceinline__ uint32_t tick_item(const FrameDesc& d, uint32_t local
 #undef FWRS_TICK_OPS
 }
 
-// One work item of a group of d.nf > 1 frames (d its leader).
+// One work item of a group of d.nf > 1 frames (d its leader); G as tick_kernel's.
+template <int G>
 __device__ __forceinline__ void tick_group_item(const FrameDesc& d, const FrameDesc* __restrict__ descs,
                                                 uint32_t local, uint32_t wave)
 {
@@ -718,8 +756,9 @@ __device__ __forceinline__ void tick_group_item(const FrameDesc& d, const FrameD
                 case 1: pixel_group<1>(d, later, x, y, slots, changed); break;
                 case 2: pixel_group<2>(d, later, x, y, slots, changed); break;
                 case 4: pixel_group<4>(d, later, x, y, slots, changed); break;
-                case 8: pixel_group<8>(d, later, x, y, slots, changed); break;
-                default: break;                          // the host sets kGroup only for k in {1, 2, 4, 8}
+                default:                                 // the host sets kGroup only for k in {1, 2, 4, 8}
+                    if constexpr (G == kTickGroups8) pixel_group<8>(d, later, x, y, slots, changed);
+                    break;
             }
         }
         if (d.stats) add_stats_wide(d.stats, slots, changed);
@@ -732,11 +771,12 @@ __device__ __forceinline__ void tick_group_item(const FrameDesc& d, const FrameD
     }
 }
 
-// GROUPS: the tick has groups.  A group of k = 8 frames holds a whole record
-// across its frames, which takes more registers than any single-frame path;
-// ticks without groups run the instantiation without that path, at the
-// single-frame paths' occupancy.
-template <bool GROUPS>
+// G: what the tick holds (kTickAlone: no groups; kTickGroups: groups, none run
+// as kGroup with k = 8; kTickGroups8: some are).  A group holds its pixels'
+// whole records across its frames, which takes more registers than the
+// single-frame paths (at k = 8 far more), so each kind of tick runs the
+// instantiation with only the paths it needs, at the best occupancy they allow.
+template <int G>
 __global__ __launch_bounds__(kBlock) void tick_kernel(const TickHead* __restrict__ head,
                                                       const FrameDesc* __restrict__ descs)
 {
@@ -757,8 +797,8 @@ __global__ __launch_bounds__(kBlock) void tick_kernel(const TickHead* __restrict
         uint32_t local = item - d.first;
         if (d.rev) local = d.items - 1u - local;
         const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        if (GROUPS && d.nf > 1u) {
-            tick_group_item(d, descs, local, wave);
+        if (G != kTickAlone && d.nf > 1u) {
+            tick_group_item<G>(d, descs, local, wave);
         } else {
             const uint32_t v = tick_item(d, local, wave);
             if (d.stats) add_stats(d.stats, v);
@@ -1284,13 +1324,17 @@ hipError_t launch_frame(const FrameDesc& d, int op, hipStream_t stream)
     }
 }
 
-hipError_t launch_tick(const void* table, uint32_t grid, bool groups, hipStream_t stream)
+hipError_t launch_tick(const void* table, uint32_t grid, int kind, hipStream_t stream)
 {
     if (grid == 0u) return hipSuccess;
     const TickHead* head = static_cast<const TickHead*>(table);
     const FrameDesc* descs = reinterpret_cast<const FrameDesc*>(static_cast<const char*>(table) + kTickDescOffset);
-    if (groups) hipLaunchKernelGGL(tick_kernel<true>, dim3(grid), dim3(kBlock), 0, stream, head, descs);
-    else hipLaunchKernelGGL(tick_kernel<false>, dim3(grid), dim3(kBlock), 0, stream, head, descs);
+    if (kind == kTickGroups8)
+        hipLaunchKernelGGL(tick_kernel<kTickGroups8>, dim3(grid), dim3(kBlock), 0, stream, head, descs);
+    else if (kind == kTickGroups)
+        hipLaunchKernelGGL(tick_kernel<kTickGroups>, dim3(grid), dim3(kBlock), 0, stream, head, descs);
+    else
+        hipLaunchKernelGGL(tick_kernel<kTickAlone>, dim3(grid), dim3(kBlock), 0, stream, head, descs);
     return hipGetLastError();
 }
 
@@ -1416,9 +1460,11 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t stream
     return hipGetLastError();
 }
 
-void* tick_kernel_entry(bool groups)
+void* tick_kernel_entry(int kind)
 {
-    return groups ? reinterpret_cast<void*>(&tick_kernel<true>) : reinterpret_cast<void*>(&tick_kernel<false>);
+    if (kind == kTickGroups8) return reinterpret_cast<void*>(&tick_kernel<kTickGroups8>);
+    if (kind == kTickGroups) return reinterpret_cast<void*>(&tick_kernel<kTickGroups>);
+    return reinterpret_cast<void*>(&tick_kernel<kTickAlone>);
 }
 
 
