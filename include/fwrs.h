@@ -360,10 +360,13 @@ typedef struct fwrs_frame {
  * its fwrs_set_tile says.  A context whose own stream is another one is
  * ordered by events: the tick waits for the work already enqueued on that
  * stream, and later work there (fwrs_destroy's wait included) waits for the
- * tick.  The descriptor table lives in a ring of pinned host and device
- * buffers that the library allocates for each device on first use and keeps
- * until the process ends; a call waits (on the host) only if the ring's
- * oldest tick is still running.  Thread-safe.
+ * tick.  A tick of at most 21 entries carries its descriptor table in the
+ * kernel's arguments: one launch, nothing copied.  A larger tick's table
+ * lives in a ring of pinned host and device buffers that the library
+ * allocates for each device on first use and keeps until the process ends,
+ * and is copied to the device on the stream before the launch; a call waits
+ * (on the host) only if the ring's oldest such tick is still running.
+ * Thread-safe.
  * FWRS_E_ARG: n outside [0, 4096], frames NULL with n > 0, a NULL field or
  * non-finite gaze, contexts on different devices.  FWRS_E_STATE: as
  * fwrs_push_frame, also if a context's entries would take its frame index
@@ -379,8 +382,10 @@ int fwrs_tick(const fwrs_frame* frames, int n, void* hip_stream);
  * work).  The descriptor table lives in a fixed 46 KiB array in device memory
  * that the library holds for the process's lifetime -- one per GPU, shared by
  * every call on that GPU -- and is written by small kernels whose arguments
- * carry the descriptors, on hip_stream, before the batched kernel: a call
- * allocates nothing and copies nothing from host memory.  Calls on one GPU
+ * carry the descriptors, on hip_stream, before the batched kernel (a call of
+ * at most 21 entries carries the table in the batched kernel's arguments and
+ * does not touch the array): a call allocates nothing and copies nothing from
+ * host memory.  Calls on one GPU
  * must not overlap: a call on another stream while an earlier one may still
  * run races on the shared table (calls on one stream are ordered by it).
  * Unlike fwrs_tick it does not order the tick against the contexts' own
@@ -392,10 +397,12 @@ int fwrs_tick_noalloc(const fwrs_frame* frames, int n, void* hip_stream);
 typedef struct fwrs_engine fwrs_engine;
 
 /* Creates an engine for up to `max_frames` (1 .. 4096) entries per tick on a
- * borrowed HIP stream.  With use_graph != 0 each tick is the replay of a HIP
- * graph -- the copy of the descriptor table, then the batched kernel -- built
- * once per ring slot and updated only when a tick's frames change size; the
- * stream must then not be capturing.
+ * borrowed HIP stream.  With use_graph != 0 each tick of more than 21 entries
+ * is the replay of a HIP graph -- the copy of the descriptor table, then the
+ * batched kernel -- built once per ring slot and kind of tick and updated only
+ * when a tick's frames change size; the stream must then not be capturing.
+ * Smaller ticks launch the kernel with the table in its arguments in either
+ * mode (a graph would only add a copy).
  * FWRS_E_ARG, FWRS_E_NOMEM, FWRS_E_HIP. */
 int fwrs_engine_create(void* hip_stream, int max_frames, int use_graph, fwrs_engine** out);
 

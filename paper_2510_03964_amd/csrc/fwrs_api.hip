@@ -822,6 +822,7 @@ struct fwrs_engine {
     std::vector<TileClass> classes;
     std::vector<int> ops;               // op of each frame of the tick being issued
     std::vector<int> work;              // the tick layout's scratch (TickWork)
+    fwrs::TickArgs args;                // the table of a tick small enough for the kernel's arguments
     TickSlot slot[kRing];
     hipEvent_t done_ev = nullptr;       // end of the latest tick, for contexts on other streams
     uint32_t ticks = 0;                 // ticks issued (odd ticks run in reverse order)
@@ -953,8 +954,11 @@ int engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n, hipStream_t str
     if (n == 0) return FWRS_OK;
     DeviceGuard g(e->device);
     if (!g.ok) return FWRS_E_HIP;
+    // A tick of at most kArgFrames frames carries its table in the kernel's
+    // arguments; a larger one copies it from the ring's pinned buffer.
+    const bool in_args = n <= fwrs::kArgFrames;
     TickSlot& sl = e->slot[e->ticks % kRing];
-    if (sl.pending) {
+    if (!in_args && sl.pending) {
         if (hipEventSynchronize(sl.done) != hipSuccess) return FWRS_E_HIP;
         sl.pending = false;
     }
@@ -962,8 +966,9 @@ int engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n, hipStream_t str
     // order, each frame's items in reverse), so a tick starts on the state the
     // previous one touched last, while it is still in the Infinity Cache.
     const bool reverse = (e->ticks & 1u) != 0u;
-    fwrs::TickHead* head = static_cast<fwrs::TickHead*>(sl.host);
-    FrameDesc* descs = reinterpret_cast<FrameDesc*>(static_cast<char*>(sl.host) + fwrs::kTickDescOffset);
+    fwrs::TickHead* head = in_args ? &e->args.head : static_cast<fwrs::TickHead*>(sl.host);
+    FrameDesc* descs = in_args ? e->args.descs
+                               : reinterpret_cast<FrameDesc*>(static_cast<char*>(sl.host) + fwrs::kTickDescOffset);
     int kind = fwrs::kTickAlone;
     const int lrc = layout_tick(frames, n, reverse, [e](const fwrs_ctx* x, int& tx, int& ty) { engine_tile(e, x, tx, ty); },
                                 TickWork(e->work.data(), (size_t)e->max_frames), head, descs, e->ops.data(), kind);
@@ -979,19 +984,21 @@ int engine_tick(fwrs_engine* e, const fwrs_frame* frames, int n, hipStream_t str
         }
     }
     const size_t bytes = fwrs::tick_table_bytes((size_t)n);
-    if (err == hipSuccess && e->use_graph) {
+    if (err == hipSuccess && in_args) {
+        err = fwrs::launch_tick_args(e->args, kind, stream);
+    } else if (err == hipSuccess && e->use_graph) {
         err = slot_graph(sl, kind, bytes, head->total);
         if (err == hipSuccess) err = hipGraphLaunch(sl.graph[kind].exec, stream);
     } else if (err == hipSuccess) {
         err = hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, stream);
         if (err == hipSuccess) err = fwrs::launch_tick(sl.dev, head->total, kind, stream);
     }
-    if (err == hipSuccess) err = hipEventRecord(sl.done, stream);
+    if (err == hipSuccess && !in_args) err = hipEventRecord(sl.done, stream);
     if (err != hipSuccess) {
         (void)hipGetLastError();
         return FWRS_E_HIP;
     }
-    sl.pending = true;
+    if (!in_args) sl.pending = true;
     e->ticks += 1u;
     for (int i = 0; i < n; ++i) advance(frames[i].ctx, e->ops[i], frames[i].out);
     // ... and its later work (and fwrs_destroy) waits for this tick
@@ -1163,18 +1170,35 @@ int fwrs_tick_noalloc(const fwrs_frame* frames, int n, void* hip_stream)
     if (scratch_table(dev, &table) != hipSuccess) return FWRS_E_HIP;
     // the tick's layout (as in fwrs_tick: every other call on a device runs backwards)
     const bool reverse = (g_scratch_ticks[dev] & 1u) != 0u;
-    int ops[kStaticTickFrames];
-    int work[kTickWorkInts * kStaticTickFrames];
-    FrameDesc descs[kStaticTickFrames];
-    fwrs::TickFill fill{};
-    int kind = fwrs::kTickAlone;
-    const int lrc = layout_tick(frames, n, reverse, [](const fwrs_ctx* x, int& tx, int& ty) {
+    auto ctx_tile = [](const fwrs_ctx* x, int& tx, int& ty) {
         tx = x->tile_x;
         ty = x->tile_y;
-    }, TickWork(work, kStaticTickFrames), &fill.head, descs, ops, kind);
+    };
+    int ops[kStaticTickFrames];
+    int work[kTickWorkInts * kStaticTickFrames];
+    int kind = fwrs::kTickAlone;
+    hipError_t err = hipSuccess;
+    if (n <= fwrs::kArgFrames) {
+        // the whole table in the kernel's arguments: the array is not needed
+        fwrs::TickArgs args;
+        const int lrc = layout_tick(frames, n, reverse, ctx_tile, TickWork(work, kStaticTickFrames), &args.head,
+                                    args.descs, ops, kind);
+        if (lrc != FWRS_OK) return lrc;
+        err = fwrs::launch_tick_args(args, kind, stream);
+        if (err != hipSuccess) {
+            (void)hipGetLastError();
+            return FWRS_E_HIP;
+        }
+        g_scratch_ticks[dev] += 1u;
+        for (int i = 0; i < n; ++i) advance(frames[i].ctx, ops[i], frames[i].out);
+        return FWRS_OK;
+    }
+    FrameDesc descs[kStaticTickFrames];
+    fwrs::TickFill fill{};
+    const int lrc = layout_tick(frames, n, reverse, ctx_tile, TickWork(work, kStaticTickFrames), &fill.head, descs,
+                                ops, kind);
     if (lrc != FWRS_OK) return lrc;
     // the descriptors, kFillFrames per fill launch, then the batched kernel
-    hipError_t err = hipSuccess;
     for (int at = 0; at < n && err == hipSuccess; at += fwrs::kFillFrames) {
         fill.at = (uint32_t)at;
         fill.count = (uint32_t)std::min(fwrs::kFillFrames, n - at);

@@ -49,6 +49,16 @@ hipError_t launch_tick(const void* table, uint32_t grid, int kind, hipStream_t s
 // Its entry points, for HIP graph kernel nodes: arguments (const TickHead*, const FrameDesc*).
 void* tick_kernel_entry(int kind);
 
+// A tick of at most kArgFrames frames carries its whole table in the kernel's
+// arguments: one launch, no copy.
+constexpr int kArgFrames = 21;
+struct TickArgs {
+    TickHead head;
+    FrameDesc descs[kArgFrames];
+};
+static_assert(sizeof(TickArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+hipError_t launch_tick_args(const TickArgs& a, int kind, hipStream_t stream);
+
 // One launch of the table-fill kernel: writes `count` descriptors (kernel
 // arguments) to table slots at .. at + count - 1, and the head if write_head.
 constexpr int kFillFrames = 20;

@@ -771,16 +771,16 @@ __device__ __forceinline__ void tick_group_item(const FrameDesc& d, const FrameD
     }
 }
 
-// G: what the tick holds (kTickAlone: no groups; kTickGroups: groups, none run
-// as kGroup with k = 8; kTickGroups8: some are).  A group holds its pixels'
-// whole records across its frames, which takes more registers than the
-// single-frame paths (at k = 8 far more), so each kind of tick runs the
-// instantiation with only the paths it needs, at the best occupancy they allow.
+// The tick of table (head, descs), block by block; G: what the tick holds
+// (kTickAlone: no groups; kTickGroups: groups, none run as kGroup with k = 8;
+// kTickGroups8: some are).  A group holds its pixels' whole records across
+// its frames, which takes more registers than the single-frame paths (at k = 8
+// far more), so each kind of tick runs the instantiation with only the paths
+// it needs, at the best occupancy they allow.
 template <int G>
-__global__ __launch_bounds__(kBlock) void tick_kernel(const TickHead* __restrict__ head,
-                                                      const FrameDesc* __restrict__ descs)
+__device__ __forceinline__ void tick_blocks(const TickHead& head, const FrameDesc* __restrict__ descs)
 {
-    const uint32_t n = head->n, total = head->total;
+    const uint32_t n = head.n, total = head.total;
     uint32_t f = 0u;
     for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
         if (item == blockIdx.x) {
@@ -804,6 +804,25 @@ __global__ __launch_bounds__(kBlock) void tick_kernel(const TickHead* __restrict
             if (d.stats) add_stats(d.stats, v);
         }
     }
+}
+
+// The table in device memory.
+template <int G>
+__global__ __launch_bounds__(kBlock) void tick_kernel(const TickHead* __restrict__ head,
+                                                      const FrameDesc* __restrict__ descs)
+{
+    tick_blocks<G>(*head, descs);
+}
+
+// The table carried in the kernel's arguments (a tick of at most kArgFrames
+// frames), read in place from the kernel-argument segment: indexing the
+// by-value parameter itself would copy it to private memory first.
+template <int G>
+__global__ __launch_bounds__(kBlock) void tick_args_kernel(const TickArgs a)
+{
+    (void)a;
+    const TickArgs* in = (const TickArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+    tick_blocks<G>(in->head, in->descs);
 }
 
 // Writes descriptors carried as kernel arguments into a tick table.
@@ -1457,6 +1476,19 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t stream
     size_t blocks = (n + kBlock - 1) / kBlock;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(fill_u32_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_tick_args(const TickArgs& a, int kind, hipStream_t stream)
+{
+    const uint32_t grid = a.head.total;
+    if (grid == 0u) return hipSuccess;
+    if (kind == kTickGroups8)
+        hipLaunchKernelGGL(tick_args_kernel<kTickGroups8>, dim3(grid), dim3(kBlock), 0, stream, a);
+    else if (kind == kTickGroups)
+        hipLaunchKernelGGL(tick_args_kernel<kTickGroups>, dim3(grid), dim3(kBlock), 0, stream, a);
+    else
+        hipLaunchKernelGGL(tick_args_kernel<kTickAlone>, dim3(grid), dim3(kBlock), 0, stream, a);
     return hipGetLastError();
 }
 

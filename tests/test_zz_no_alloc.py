@@ -1,7 +1,8 @@
 """fwrs_tick_noalloc (the batched call that allocates nothing) against fwrs_tick, through the C ABI.
 
-Two calls in a row on the same contexts' twins -- the second with fewer and smaller frames -- must
-leave every output and every state plane bit-identical to fwrs_tick's (the batched results are
+Two calls in a row on the same contexts' twins -- the second with fewer and smaller frames -- and a
+third small enough to travel in the kernel's arguments must leave every output and every state
+plane bit-identical to fwrs_tick's (the batched results are
 decided and copied values; the resolve is the same binary32 computation), and sizes beyond the
 fixed table are refused before any device work.
 """
@@ -84,8 +85,9 @@ def test_noalloc_tick_equals_fwrs_tick(dev):
         assert L.fwrs_tick(_frames(eb), len(eb), C.c_void_p(h)) == fwrs.OK
     torch.cuda.synchronize()
     _check_equal(a, b, oa, ob, "first call")
-    # call 2: a smaller input -- 5 of the contexts, the smallest frames
-    keep = [i for i in range(len(cases)) if specs[i].width <= 80][:5]
+    # call 2: a smaller input -- 24 of the contexts, the smallest frames (still more entries than a
+    # kernel's arguments hold, so the fixed table is used again, over the first call's contents)
+    keep = sorted(range(len(cases)), key=lambda i: (specs[i].pixels, i))[:24]
     for t in range(3, 5):
         fr = {i: srcs[i].frame(t) for i in keep}
         ea = [(a[i], *fr[i], oa[i]) for i in keep]
@@ -95,6 +97,14 @@ def test_noalloc_tick_equals_fwrs_tick(dev):
     torch.cuda.synchronize()
     _check_equal([a[i] for i in keep], [b[i] for i in keep], [oa[i] for i in keep], [ob[i] for i in keep],
                  "second call")
+    # call 3: 5 contexts, two frames of one of them (a table small enough for the kernel's arguments)
+    few = keep[:5]
+    ea = [(a[i], *srcs[i].frame(5), oa[i]) for i in few] + [(a[few[0]], *srcs[few[0]].frame(6), oa[few[0]])]
+    eb = [(b[i], *srcs[i].frame(5), ob[i]) for i in few] + [(b[few[0]], *srcs[few[0]].frame(6), ob[few[0]])]
+    assert L.fwrs_tick_noalloc(_frames(ea), len(ea), C.c_void_p(h)) == fwrs.OK
+    assert L.fwrs_tick(_frames(eb), len(eb), C.c_void_p(h)) == fwrs.OK
+    torch.cuda.synchronize()
+    _check_equal([a[i] for i in few], [b[i] for i in few], [oa[i] for i in few], [ob[i] for i in few], "third call")
     for r in a + b:
         r.close()
 
