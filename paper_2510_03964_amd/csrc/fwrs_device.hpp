@@ -306,19 +306,30 @@ __device__ __forceinline__ float3 fov_colour(const FovSrc& s, uint32_t x, uint32
 // Lab (D65 white), then the CIE94 difference with graphic-arts weights and the
 // reservoir sample as the reference; |dL| = min(1, dE94 / 100).
 // ---------------------------------------------------------------------------
-// Cube root of t > 0, correctly rounded to binary32.  An approximation y
-// without division comes first: the reciprocal cube root r from an exponent-bit
-// seed (bits(t^(-1/3)) ~ 4/3 * 127 * 2^23 - bits(t)/3), two Newton steps
-// r <- r (4 - t r^3) / 3, then y = t r^2 and one Newton step on y with r^2 for
-// 1 / y^2: y <- y - (y^3 - t) r^2 / 3 (1/3 is its binary32 rounding).  y is
-// within one ulp of the cube root, so the nearest binary32 is y or a
-// neighbour: the real cube root lies above the midpoint m between y and the
-// binary32 above it iff m^3 < t, and below the midpoint under y iff t < m^3.
-// A midpoint has 25 significant bits, so m^2 is exact in binary64 and m^3 is
-// exactly hi + lo with hi = m^2 m rounded and lo = fma(m^2, m, -hi); hi is
-// within a few ulps of t, so t - hi is exact and t - m^3 has the sign of
-// (t - hi) - lo.  That the result is the nearest binary32 for every t in
-// [(6/29)^3, 2^8) and for samples beyond is checked exhaustively on the host.
+// Cube root of t, correctly rounded to binary32 (t > 0 normal; zero, +inf and
+// NaN pass through).
+//
+// The estimate y0 = 2^(log2(t) / 3) comes from the device's base-2 logarithm
+// and exponential instructions (libm's on the host) and is within about 2^-19
+// of the cube root.  One Newton step in binary64 follows:
+// y1 = y0 + (t - y0^3) / (3 y0^2), with y0^2 exact, and the division taken as a
+// product with the binary32 reciprocal of 3 y0^2.  y1 is within about 2^-36 of
+// the cube root, so rounding it to binary32 gives the nearest binary32, unless
+// y1 lies within kCbrtGuard (2^-34 relative) of a midpoint between two
+// binary32 values.
+//
+// Those rare inputs take the exact decision in cube_root_nearest.  There
+// y = RN(y1) is within one ulp of the cube root.  The real cube root lies above
+// the midpoint m between y and the binary32 above it iff m^3 < t, and below the
+// midpoint under y iff t < m^3.  A midpoint has 25 significant bits, so m^2 is
+// exact in binary64 and m^3 is exactly hi + lo, with hi = m^2 m rounded and
+// lo = fma(m^2, m, -hi).  hi is within a few ulps of t, so t - hi is exact, and
+// t - m^3 has the sign of (t - hi) - lo.
+//
+// That the result equals the oracle's (the binary32 nearest to the real cube
+// root) is checked on every t in [(6/29)^3, 2^8) and on every 61st positive
+// normal binary32 beyond: on the GPU for the device code, and on the host for
+// the host build.
 __host__ __device__ __forceinline__ bool cube_below(double m, double t)     // m^3 < t, exactly
 {
     const double m2 = m * m;
@@ -327,29 +338,37 @@ __host__ __device__ __forceinline__ bool cube_below(double m, double t)     // m
     return (t - hi) > lo;
 }
 
-__host__ __device__ __forceinline__ float cube_root(float t)
+// The binary32 nearest to t^(1/3), given y within one ulp of it.
+__host__ __device__ __forceinline__ float cube_root_nearest(float t, float y)
 {
-    if (!(t < INFINITY)) return t;                   // +inf, NaN
-    float r = __builtin_bit_cast(float, 0x54A2FA8Cu - __builtin_bit_cast(uint32_t, t) / 3u);
-    const float third = 0x1.555556p-2f;
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const float r2 = r * r;
-        const float r3 = r2 * r;
-        const float d = 4.0f - t * r3;
-        r = (r * d) * third;
-    }
-    const float r2 = r * r;
-    const float y0 = t * r2;
-    const float y3 = (y0 * y0) * y0;
-    const float c = ((y3 - t) * r2) * third;
-    const float y = y0 - c;
     const uint32_t yb = __builtin_bit_cast(uint32_t, y);
     const float up = __builtin_bit_cast(float, yb + 1u);
     const float dn = __builtin_bit_cast(float, yb - 1u);
     const double td = (double)t;
     if (cube_below(0.5 * ((double)y + (double)up), td)) return up;
     if (!cube_below(0.5 * ((double)dn + (double)y), td)) return dn;
+    return y;
+}
+
+// Distance from a binary32 midpoint below which the exact decision is taken, in
+// units of 2^-52 of the binade (29 bits lie below binary32 precision): 2^-34.
+constexpr int32_t kCbrtGuard = 1 << 18;
+
+__host__ __device__ __forceinline__ float cube_root(float t)
+{
+    if (!(t < INFINITY) || t == 0.0f) return t;     // +inf, NaN, zero
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float y0 = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(t) * 0x1.555556p-2f);
+    const float r3 = __builtin_amdgcn_rcpf(3.0f * (y0 * y0));
+#else
+    const float y0 = exp2f(log2f(t) * 0x1.555556p-2f);
+    const float r3 = 1.0f / (3.0f * (y0 * y0));
+#endif
+    const double yd = (double)y0;
+    const double y1 = yd + ((double)t - (yd * yd) * yd) * (double)r3;
+    const float y = (float)y1;
+    const int32_t off = (int32_t)((uint32_t)__builtin_bit_cast(uint64_t, y1) & 0x1FFFFFFFu) - 0x10000000;
+    if (off > -kCbrtGuard && off < kCbrtGuard) return cube_root_nearest(t, y);
     return y;
 }
 

@@ -2,7 +2,10 @@
 their ranges (CPU only).
 
 The device header is compiled for the host (tests/pins/devmath_host.cpp), so the functions the
-gfx950 kernels inline are evaluated here on the CPU with the same IEEE operations:
+gfx950 kernels inline are evaluated here on the CPU with the same IEEE operations (the cube root's
+starting estimate excepted: the host build takes it from libm's log2 and exp2 where the device uses
+its own instructions, so this checks the correction and rounding that follow it; the device code
+itself is checked on the GPU by tests/test_gpu_devmath.py):
   - the cube root of Eq. 7's Lab conversion (Sec. 4.3) for every binary32 in the Lab curve's
     cube-root range [(6/29)^3, 2^8), and every 61st positive normal binary32 beyond;
   - log2 of the A-ES variate (Sec. 3.1) for all 2^24 variates;
