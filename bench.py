@@ -13,7 +13,7 @@ the resolve plane at frame 31 and copies unchanged pixels from it from frame 32 
 launches three kernels; the dominant one (frames 32-599) is the roofline's.
 
 Prints one JSON line: Gpixel-updates/s over the trace, ms per frame, the roofline of the dominant
-kernel (SURVEY 8(d) algorithmic bytes per pixel-update 41 + 16k + 20 r, r = slot replacements per
+kernel (algorithmic bytes per pixel-update of update + resolve, 41 + 16k + 20 r, r = slot replacements per
 pixel-update counted by the kernel, over its average launch time from HIP events on its stream;
 beside it the 33-byte variant, the kernel's measured HBM traffic from the committed counter
 summary of the same window, and the whole-trace and first-20-frame figures), and the CPU oracle
@@ -57,7 +57,7 @@ def log(msg: str) -> None:
 
 
 def bytes_per_update(k: int, rbar: float) -> float:
-    """Algorithmic HBM bytes per pixel-update of update + resolve (SURVEY 8(d)): colour in (12), level (1),
+    """Algorithmic HBM bytes per pixel-update of update + resolve: colour in (12), level (1),
     w_sum read and written (8), the per-pixel count read and written (8; kept here as the context's frame
     index), output (12), every slot's colour and weight read for the resolve (16 k), and colour + weight +
     index written per replaced slot (20 per take)."""
@@ -65,7 +65,7 @@ def bytes_per_update(k: int, rbar: float) -> float:
 
 
 def bytes_per_update_33(k: int, rbar: float) -> float:
-    """The same without the per-pixel count (8 bytes), which this build keeps once per context."""
+    """The same without the per-pixel count (8 bytes), which the library keeps once per context."""
     return 33.0 + 16.0 * k + 20.0 * rbar
 
 
@@ -579,7 +579,7 @@ def headline(dev, stream, spec, frames, steps: int, warmup: int, fps: int, tile)
             "traffic_frac": None if traffic is None else traffic / (t_cached / 1e3) / 1e9 / HBM_PEAK_GBPS,
             "kernel": f"{KERNEL_CACHED} (fused update + resolve, unchanged pixels from the resolve plane)",
             "frames": [PLANE_FROM, n], "launches": n - PLANE_FROM, "kernel_ms_avg": t_cached,
-            "bytes_per_pixel_update": B, "bytes_model": "41 + 16k + 20r (SURVEY 8(d))",
+            "bytes_per_pixel_update": B, "bytes_model": "41 + 16k + 20r (update + resolve, per-pixel count plane included)",
             "slot_takes_per_pixel_update": r_cached,
             "bytes_model_33": {"bytes_per_pixel_update": B33,
                                "frac": N * B33 / (t_cached / 1e3) / 1e9 / HBM_PEAK_GBPS,
@@ -604,7 +604,7 @@ def headline(dev, stream, spec, frames, steps: int, warmup: int, fps: int, tile)
                "bytes_per_pixel_update": bytes_per_update(k, r20),
                "frac": N * bytes_per_update(k, r20) / (t20 / 1e3) / 1e9 / HBM_PEAK_GBPS}
     log(f"trace: {total_ms / n:.4f} ms/frame; dominant kernel {t_cached * 1e3:.1f} us = {roof['frac']:.3f} of HBM "
-        f"(8(d) bytes), first 20 frames {t20 * 1e3:.1f} us")
+        f"(41 + 16k + 20r bytes), first 20 frames {t20 * 1e3:.1f} us")
     return {"total_ms": total_ms, "per": per, "roofline": roof, "trace": trace, "first_20_frames": first20,
             "changed": changed / updates}
 
@@ -634,7 +634,7 @@ def main() -> int:
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): every pixel stream is independent "
-              "and this build measures the single-GPU pass.", file=sys.stderr)
+              "and this benchmark measures the single-GPU pass.", file=sys.stderr)
         return 2
     if args.steps < 1 or args.warmup < 0:
         print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
