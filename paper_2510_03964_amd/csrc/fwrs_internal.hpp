@@ -37,8 +37,8 @@ constexpr size_t kTickDescOffset = 16;
 static_assert(sizeof(TickHead) == kTickDescOffset, "descriptors follow the head");
 inline size_t tick_table_bytes(size_t frames) { return kTickDescOffset + frames * sizeof(FrameDesc); }
 
-// The batched kernel on `grid` blocks (block b takes work items b, b + grid,
-// ... of the table's tick; the engine launches one block per item), in the
+// The batched kernel on `grid` blocks, one per work item of the table's tick
+// (grid = head.total; blocks past the last item do nothing), in the
 // instantiation for the kind of tick the table holds: no groups (no leader
 // with nf > 1), groups, or groups among which one with op kOpGroup and k = 8.
 constexpr int kTickAlone = 0;

@@ -699,24 +699,24 @@ __global__ __launch_bounds__(kBlock) void frame_kernel(FrameDesc d)
 
 // ---------------------------------------------------------------------------
 // Batched tick: one launch for all the frames of a tick, any number of them.
-// The frames' descriptors are a table in device memory (uniform data, read
-// with scalar loads).  The consecutive frames of one context in a tick form a
-// group, whose first frame (the leader) stands for it among the table's
-// leaders, in the order the tick visits them; the tick's 256-pixel work items
-// are numbered leader after leader, and a leader whose `rev` is set visits its
-// own items last first (the host reverses the group order and sets `rev` on
-// every other tick, so such a tick runs entirely backwards).  Block b takes
-// items b, b + G, b + 2G, ... (G = gridDim.x): the engine launches one block
-// per item, which measured faster than a persistent grid of resident blocks
-// looping over the items (the hardware's block dispatch balances the uneven
-// per-item cost of the pass better than a fixed stride), but any grid gives
-// the same results.  A block finds its first item's leader by binary search
-// over the leaders' first items and follows the leaders along with its
-// (increasing) items.  An item of a lone frame runs the single-frame per-pixel
-// code for the frame's slot count and op (kFused, kCached or kFill); an item
-// of a group runs pixel_group (op kGroup), or else (run-time slot counts,
-// per-slot modes) each of the group's frames in turn through the store, every
-// pixel in the same thread, so each frame reads what the one before wrote.
+// The frames' descriptors are a table in device memory or in the kernel's
+// arguments (uniform data, read with scalar loads).  The consecutive frames of
+// one context in a tick form a group, whose first frame (the leader) stands for
+// it among the table's leaders, in the order the tick visits them; the tick's
+// 256-pixel work items are numbered leader after leader, and a leader whose
+// `rev` is set visits its own items last first (the host reverses the group
+// order and sets `rev` on every other tick, so such a tick runs entirely
+// backwards).  The grid has one block per work item (blocks past the last item
+// exit): this measured faster than a persistent grid of resident blocks looping
+// over the items -- the hardware's block dispatch balances the uneven per-item
+// cost of the pass better than a fixed stride -- and without a loop over items
+// the kernel keeps fewer values live (one more wave per SIMD).  A block finds
+// its item's leader by binary search over the leaders' first items.  An item of
+// a lone frame runs the single-frame per-pixel code for the frame's slot count
+// and op (kFused, kCached or kFill); an item of a group runs pixel_group (op
+// kGroup), or else (run-time slot counts, per-slot modes) each of the group's
+// frames in turn through the store, every pixel in the same thread, so each
+// frame reads what the one before wrote.
 // ---------------------------------------------------------------------------
 template <int K, int OP, bool PER_SLOT = false>
 __device__ __forceinline__ uint32_t process_wave(const FrameDesc& d, uint32_t item, uint32_t wave)
@@ -780,29 +780,23 @@ __device__ __forceinline__ void tick_group_item(const FrameDesc& d, const FrameD
 template <int G>
 __device__ __forceinline__ void tick_blocks(const TickHead& head, const FrameDesc* __restrict__ descs)
 {
-    const uint32_t n = head.n, total = head.total;
-    uint32_t f = 0u;
-    for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
-        if (item == blockIdx.x) {
-            uint32_t hi = n - 1u;                        // last leader whose first item <= item
-            while (f < hi) {
-                const uint32_t mid = (f + hi + 1u) >> 1;
-                if (descs[mid].first <= item) f = mid;
-                else hi = mid - 1u;
-            }
-        } else {
-            while (f + 1u < n && descs[f + 1u].first <= item) ++f;
-        }
-        const FrameDesc& d = descs[f];
-        uint32_t local = item - d.first;
-        if (d.rev) local = d.items - 1u - local;
-        const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        if (G != kTickAlone && d.nf > 1u) {
-            tick_group_item<G>(d, descs, local, wave);
-        } else {
-            const uint32_t v = tick_item(d, local, wave);
-            if (d.stats) add_stats(d.stats, v);
-        }
+    const uint32_t item = blockIdx.x;
+    if (item >= head.total) return;
+    uint32_t f = 0u, hi = head.n - 1u;               // last leader whose first item <= item
+    while (f < hi) {
+        const uint32_t mid = (f + hi + 1u) >> 1;
+        if (descs[mid].first <= item) f = mid;
+        else hi = mid - 1u;
+    }
+    const FrameDesc& d = descs[f];
+    uint32_t local = item - d.first;
+    if (d.rev) local = d.items - 1u - local;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (G != kTickAlone && d.nf > 1u) {
+        tick_group_item<G>(d, descs, local, wave);
+    } else {
+        const uint32_t v = tick_item(d, local, wave);
+        if (d.stats) add_stats(d.stats, v);
     }
 }
 
