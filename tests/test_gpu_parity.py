@@ -651,6 +651,47 @@ def test_tick_groups_equal_plain_calls(dev, api):
         orcs[i].close()
 
 
+@pytest.mark.parametrize("api", ["tick", "noalloc"])
+def test_long_groups_equal_plain_calls(dev, api):
+    """Two contexts with 50 frames each in one tick (a group per context far longer than the serving
+    loop forms): k = 4 (the register path) and k = 3 (each frame through the store), from the empty
+    store through the resolve plane's switch; every frame's output, the state and the counters equal
+    one fwrs_push_frame_resolve per frame, bit for bit."""
+    nf = 50
+    stream = torch.cuda.current_stream()
+    cases = [(80, 48, 4, fwrs.BIAS_BERNOULLI, 20), (45, 30, 3, fwrs.BIAS_BERNOULLI, 0)]
+    tick_ctx, plain_ctx, frames, outs_t, outs_p = [], [], [], [], []
+    for i, (w, h, k, bias, res_from) in enumerate(cases):
+        s = synth.StreamSpec(w, h, k, nf, 0.1 * w, 0.25 * w, 2.0, 3, 4.0, stream_id=70 + i)
+        p, _ = _params(s, bias)
+        tick_ctx.append(fwrs.Reservoir(w, h, k, p, stream=stream))
+        plain_ctx.append(fwrs.Reservoir(w, h, k, p, stream=stream))
+        tick_ctx[-1].set_resolve_plane_from(res_from)
+        plain_ctx[-1].set_resolve_plane_from(res_from)
+        src = synth.FrameSource(s, device=dev, n_frames=nf)
+        frames.append([src.frame(t) for t in range(nf)])
+        outs_t.append(torch.full((nf, h, w, 3), -1.0, device=dev))
+        outs_p.append(torch.full((nf, h, w, 3), -2.0, device=dev))
+    # the two contexts' frames interleaved, each context's in order
+    batch = [(tick_ctx[i], *frames[i][t], outs_t[i][t]) for t in range(nf) for i in range(len(cases))]
+    if api == "tick":
+        fwrs.tick(batch, stream=stream)
+    else:
+        fwrs.tick_noalloc(batch, stream=stream)
+    for i in range(len(cases)):
+        for t in range(nf):
+            plain_ctx[i].step(*frames[i][t], outs_p[i][t])
+    torch.cuda.synchronize()
+    for i, case in enumerate(cases):
+        for t in range(nf):
+            assert torch.equal(outs_t[i][t], outs_p[i][t]), f"frame {t} case {case} ({api})"
+        assert tick_ctx[i].frame_index == nf
+        _compare_state(tick_ctx[i].download(), plain_ctx[i].download(), f"case {case} ({api})")
+        assert tick_ctx[i].stats() == plain_ctx[i].stats()
+        tick_ctx[i].close()
+        plain_ctx[i].close()
+
+
 @pytest.mark.parametrize("n,w,h", [(300, 24, 8), (48, 256, 256)])
 def test_tick_of_many_frames(dev, n, w, h):
     """Ticks of many frames: 300 one-item frames and 48 frames of 256 items each (12288 blocks in one
