@@ -76,6 +76,7 @@ def _bind(L):
                                         C.c_int, C.c_int]
     L.fwrs_oracle_advance.argtypes = [vp]
     L.fwrs_oracle_resolve.argtypes = [vp, C.POINTER(C.c_double)]
+    L.fwrs_oracle_resolve_rows.argtypes = [vp, C.POINTER(C.c_double), C.c_int, C.c_int]
     L.fwrs_oracle_frame_index.argtypes = [vp]
     L.fwrs_oracle_frame_index.restype = C.c_uint32
     L.fwrs_oracle_constants.argtypes = [vp, C.POINTER(C.c_float)]
@@ -210,6 +211,11 @@ class Oracle:
         out = np.empty((self.height, self.width, 3), dtype=np.float64)
         self._L.fwrs_oracle_resolve(self._h, _ptr(out, C.c_double))
         return out
+
+    def resolve_rows(self, out: np.ndarray, y0: int, y1: int) -> None:
+        """Rows [y0, y1) of the resolve into `out` ([H, W, 3] float64, C-contiguous)."""
+        assert out.shape == (self.height, self.width, 3) and out.dtype == np.float64 and out.flags.c_contiguous
+        self._L.fwrs_oracle_resolve_rows(self._h, _ptr(out, C.c_double), int(y0), int(y1))
 
     def state(self) -> State:
         H, W, k = self.height, self.width, self.k

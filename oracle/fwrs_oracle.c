@@ -817,11 +817,14 @@ void fwrs_oracle_depth(const fwrs_oracle* o, float* depth)
 uint64_t fwrs_oracle_flushes(const fwrs_oracle* o) { return o->flushes; }
 
 /* Weighted combination of the k slots (the k-slot resolve; at k = 1 it is the
- * paper's output R_out.x).  Binary64 from the stored binary32 values. */
-void fwrs_oracle_resolve(const fwrs_oracle* o, double* out)
+ * paper's output R_out.x).  Binary64 from the stored binary32 values; rows
+ * [y0, y1) of `out` ([H][W][3]) only. */
+void fwrs_oracle_resolve_rows(const fwrs_oracle* o, double* out, int y0, int y1)
 {
     const size_t n = (size_t)o->width * (size_t)o->height;
-    for (size_t p = 0; p < n; ++p) {
+    if (y0 < 0) y0 = 0;
+    if (y1 > o->height) y1 = o->height;
+    for (size_t p = (size_t)y0 * (size_t)o->width; p < (size_t)(y1 > y0 ? y1 : y0) * (size_t)o->width; ++p) {
         if (o->cnt[p] == 0) {
             out[3 * p + 0] = 0.0; out[3 * p + 1] = 0.0; out[3 * p + 2] = 0.0;
             continue;
@@ -836,6 +839,8 @@ void fwrs_oracle_resolve(const fwrs_oracle* o, double* out)
         }
     }
 }
+
+void fwrs_oracle_resolve(const fwrs_oracle* o, double* out) { fwrs_oracle_resolve_rows(o, out, 0, o->height); }
 
 /* ------------------------------------------------------------------------ */
 /* Accessors and vector helpers for the tests.                                */

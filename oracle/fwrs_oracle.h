@@ -67,6 +67,8 @@ void fwrs_oracle_push_rows(fwrs_oracle* o, const float* color, const uint8_t* le
                            int y1);
 void fwrs_oracle_advance(fwrs_oracle* o);
 void fwrs_oracle_resolve(const fwrs_oracle* o, double* out);
+/* The same for rows [y0, y1) of out only (independent rows: callers may run bands in parallel). */
+void fwrs_oracle_resolve_rows(const fwrs_oracle* o, double* out, int y0, int y1);
 uint32_t fwrs_oracle_frame_index(const fwrs_oracle* o);
 void fwrs_oracle_constants(const fwrs_oracle* o, float out[9]);
 void fwrs_oracle_state(const fwrs_oracle* o, float* wsum, uint32_t* cnt, float* wt, uint32_t* idx, float* col);

@@ -506,3 +506,32 @@ def test_zero_variate_bits_still_take_an_empty_slot(oracle_mod, rocrand_ref):
     idx, wsum = oracle_mod.trials(W, H, 4, p_, p % W, p // W, seed, 1, rgb, np.array([2], np.uint8),
                                   np.array([[5.0, 5.0]], np.float32))
     assert idx[0, j] == 0 and np.all(idx[0] == 0)
+
+
+def test_row_bands_in_parallel_equal_whole_frames(oracle_mod):
+    """Pixels are independent streams (Sec. 3.2, 4.1): updating and resolving a frame as row bands on
+    several threads (what bench.py's parallel CPU line does) leaves the state and the resolve exactly as
+    whole-frame calls do."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    spec = synth.StreamSpec(96, 67, 4, 8, 12.0, 30.0, 1.5, 3, 4.0)
+    src = synth.FrameSource(spec, device="cpu")
+    p = oracle_mod.default_params(spec.width, fovea_radius_px=spec.fovea_radius_px, seed=synth.PHILOX_SEED)
+    whole = oracle_mod.Oracle(spec.width, spec.height, spec.k, p)
+    bands = oracle_mod.Oracle(spec.width, spec.height, spec.k, p)
+    cuts = [0, 5, 23, 24, 50, 67]
+    out = np.empty((spec.height, spec.width, 3), np.float64)
+    with ThreadPoolExecutor(4) as pool:
+        for t in range(spec.frames):
+            c, lev, gx, gy = src.frame(t)
+            c, lev = c.numpy(), lev.numpy()
+            whole.push(c, lev, gx, gy)
+            list(pool.map(lambda b: bands.push_rows(c, lev, gx, gy, b[0], b[1]), zip(cuts[:-1], cuts[1:])))
+            bands.advance()
+            list(pool.map(lambda b: bands.resolve_rows(out, b[0], b[1]), zip(cuts[:-1], cuts[1:])))
+            np.testing.assert_array_equal(out, whole.resolve())
+    sa, sb = whole.state(), bands.state()
+    for name in ("wsum", "cnt", "wt", "idx", "col"):
+        np.testing.assert_array_equal(getattr(sa, name), getattr(sb, name), err_msg=name)
+    whole.close()
+    bands.close()
