@@ -2,19 +2,22 @@
 //
 // Store layout (per context, N pixels, k slots): a w_sum plane w_sum[N],
 // one record of k slots per pixel, rec[p * k + j] = {w, r, g, b} (16k bytes,
-// so at k = 4 a pixel's record is exactly one 64-byte sector), and the slots'
-// frame indices idx[p * k + j].  A slot replacement therefore dirties only the
-// sector of the pixel that replaced it, not one sector in each of k * 4
+// so at k = 4 a pixel's record is exactly one 64-byte sector), the slots'
+// frame indices idx[p * k + j], and the resolve plane res[N][3] (each pixel's
+// resolve as of its last change).  A slot replacement therefore dirties only
+// the sector of the pixel that replaced it, not one sector in each of k * 4
 // planes; reads of whole records stay contiguous across a wave.  Alg. 2's
 // candidate count m is the same for every pixel (each pixel receives exactly
 // one candidate per frame), so it is the context's frame count, not a plane.
 //
 // One thread per pixel; a block of 256 threads covers one work item laid out
 // as 1, 2 or 4 tiles of tile_x pixels by tile_y rows (the tile shape changes
-// the access pattern, never the results).  Every load a pixel needs is issued
-// before the arithmetic so that each wave has its whole footprint in flight
-// while the Philox rounds and the weight run.  The pass is bound by HBM
-// traffic; there is no contraction anywhere, so no matrix cores.
+// the access pattern, never the results).  A pixel's loads that do not depend
+// on its decision (level, w_sum, the resolve plane or the record) are issued
+// first and overlap the Philox rounds and the weight; the colour and, where
+// needed, the record of a pixel that takes the candidate follow the decision.
+// The pass is bound by HBM traffic; there is no contraction anywhere, so no
+// matrix cores.
 //
 // Per pixel and frame (Sec. 4.1-4.2 of the paper):
 //   w    = Eq. 4 weight from the eccentricity to the gaze (level 0 -> 1)
