@@ -692,6 +692,39 @@ def test_long_groups_equal_plain_calls(dev, api):
         plain_ctx[i].close()
 
 
+@pytest.mark.parametrize("k", [4, 8])
+def test_4k_group_equals_plain_calls(dev, k):
+    """A 4K context's frames 30-37 as one group of 8 (the launch the benchmark's groups section times),
+    after 30 plain frames and across the resolve plane's switch at frame 32, equal eight
+    fwrs_push_frame_resolve calls on a twin context, bit for bit: every frame's whole output and the
+    whole state."""
+    spec = synth.spec_4k(frames=600)
+    src = synth.FrameSource(spec, device=dev, n_frames=600)
+    stream = torch.cuda.current_stream()
+    p, _ = _params(spec)
+    a = fwrs.Reservoir(spec.width, spec.height, k, p, stream=stream)
+    b = fwrs.Reservoir(spec.width, spec.height, k, p, stream=stream)
+    tmp = torch.empty((spec.height, spec.width, 3), device=dev)
+    for t in range(30):
+        fr = src.frame(t)
+        a.step(*fr, tmp)
+        b.step(*fr, tmp)
+    frames = [src.frame(t) for t in range(30, 38)]
+    oa = torch.full((8, spec.height, spec.width, 3), -1.0, device=dev)
+    ob = torch.full((8, spec.height, spec.width, 3), -2.0, device=dev)
+    fwrs.tick([(a, *frames[i], oa[i]) for i in range(8)], stream=stream)
+    for i in range(8):
+        b.step(*frames[i], ob[i])
+    torch.cuda.synchronize()
+    for i in range(8):
+        assert torch.equal(oa[i], ob[i]), f"frame {30 + i} differs (k={k})"
+    assert a.frame_index == b.frame_index == 38
+    _compare_state(a.download(), b.download(), f"4K k={k} after the group")
+    assert a.stats() == b.stats()
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("n,w,h", [(300, 24, 8), (48, 256, 256)])
 def test_tick_of_many_frames(dev, n, w, h):
     """Ticks of many frames: 300 one-item frames and 48 frames of 256 items each (12288 blocks in one

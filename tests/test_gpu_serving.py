@@ -77,18 +77,24 @@ def test_small_budget_queues_sessions_on_the_gpu(dev):
     assert st.admitted + st.rejected == len(sessions)
 
 
-def test_full_size_sessions_alone_equal_in_the_mix(dev):
+@pytest.mark.parametrize("max_group", [1, 4])
+def test_full_size_sessions_alone_equal_in_the_mix(dev, max_group):
     """Sessions of the serving workload's sizes (1080p and 4K, k in {4, 8}) through batched ticks:
-    each one's output equals the same session run alone with plain launches."""
+    each one's output equals the same session run alone with plain launches.  max_group 4 with frame
+    rates above what the GPU serves: the ticks carry groups of a session's overdue frames."""
     sizes = ((1920, 1080), (3840, 2160))
-    sessions = serve.poisson_sessions(n=4, rate_per_s=40.0, seed=21, lifetime_s=(0.04, 0.08), sizes=sizes,
-                                      ks=(4, 8), fps=(90.0, 120.0))
+    fps = (90.0, 120.0) if max_group == 1 else (3000.0, 4000.0)
+    life = (0.04, 0.08) if max_group == 1 else (0.02, 0.04)
+    sessions = serve.poisson_sessions(n=4, rate_per_s=40.0, seed=21, lifetime_s=life, sizes=sizes,
+                                      ks=(4, 8), fps=fps)
     rings = _rings(dev, sizes, n=4)
     stream = torch.cuda.current_stream()
-    ex = serve.BatchedExecutor(rings, max_frames=8, stream=stream)
-    sched = serve.Scheduler(ex, budget_bytes=64 * 10**9, max_active=8)
+    ex = serve.BatchedExecutor(rings, max_frames=8 * max_group, stream=stream)
+    sched = serve.Scheduler(ex, budget_bytes=64 * 10**9, max_active=8, max_group=max_group)
     st = sched.run(sessions)
     assert st.frames > 0 and st.admitted == len(sessions)
+    if max_group > 1:
+        assert st.max_group > 1, "no tick carried several frames of a session"
     for s in sessions:
         n = sched.frames_done.get(s.sid, 0)
         assert n > 0
