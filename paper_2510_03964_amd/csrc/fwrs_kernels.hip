@@ -255,17 +255,23 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
 
     // 3. weight (Eq. 4), bias (Eq. 6) and the Alg. 2 decision per slot
     uint32_t tk = 0u;
-    float w = 0.f;
+    float w = 0.f, s = 0.f;
     if (kUpdates) {
         w = select_eq4(d.c, outside, e, lv);
         const float W1b = bias_shared(W1, w, d.bias, d.c.decay);
-        const float s = W1b + w;
+        s = W1b + w;
         tk = K ? decide_words<R>(words, W1b, s) : decide_any(d, p, W1b, s);
-        st<kNtWsumSt>(d.wsum + p, s);
     }
 
-    // 4. the new colour where some slot takes it, the records of the slots that
-    //    keep their sample where only now needed, then the replaced slots
+    // 4. the loads the decision calls for, all issued before any is waited for:
+    //    the records of the slots that keep their sample (where only now needed)
+    //    and the new colour, where some slot takes it; then the stores -- w_sum
+    //    and the replaced slots -- which thus delay none of these loads
+    if (K && (OP == kIncremental || OP == kCached) && tk && !empty) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (!((tk >> j) & 1u)) r[j] = ld4<kNtRecLd>(rec + j);
+    }
     float c0 = 0.f, c1 = 0.f, c2 = 0.f;
     if (tk) {
         if constexpr (FOV) {
@@ -279,12 +285,8 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
             c2 = ld<kNtColor>(color + 2);
         }
     }
+    if (kUpdates) st<kNtWsumSt>(d.wsum + p, s);
     const float4 fresh = make_float4(w, c0, c1, c2);
-    if (K && (OP == kIncremental || OP == kCached) && tk && !empty) {
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-            if (!((tk >> j) & 1u)) r[j] = ld4<kNtRecLd>(rec + j);
-    }
     if (K) {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
