@@ -41,6 +41,7 @@ TRACE_FRAMES = 600
 PLANE_FROM = 32
 COUNTERS = os.path.join(ROOT, "profiles", "fused_k4_4k_counters.json")
 INC_COUNTERS = os.path.join(ROOT, "profiles", "incremental_k4_4k_counters.json")
+EQ7_COUNTERS = os.path.join(ROOT, "profiles", "eq7_k4_4k_counters.json")
 VALU_COUNTERS = os.path.join(ROOT, "profiles", "fused_valu_4k_counters.json")
 KERNEL_PLAIN = "void fwrs::frame_kernel<4, 3, false>(fwrs::FrameDesc)"
 KERNEL_FILL = "void fwrs::frame_kernel<4, 9, false>(fwrs::FrameDesc)"
@@ -754,7 +755,8 @@ def main() -> int:
         f_B = bytes_per_update_eq7(spec.k, f_rbar)
         f_kern = float(f_per.mean())
         f_ach = spec.pixels * f_B / (f_kern / 1e3) / 1e9
-        vpp = valu_per_pixel("void fwrs::frame_kernel<4, 3, true>(fwrs::FrameDesc)")
+        e7_kernel = "void fwrs::frame_kernel<4, 3, true>(fwrs::FrameDesc)"
+        vpp = valu_per_pixel(e7_kernel)
         alu = None
         if vpp is not None:
             a_t = spec.pixels * vpp / (f_kern / 1e3) / 1e12
@@ -762,19 +764,21 @@ def main() -> int:
                    "frac": a_t / VALU_PEAK_TOPS, "valu_per_pixel": vpp,
                    "wave_insts_per_cu_clock": a_t * 1e12 / 64.0 / 256.0 / 2.4e9,
                    "note": "all VALU instructions (SQ_INSTS_VALU) against one non-packed wave64 instruction per CU "
-                           "and clock; a frac above 1 means the kernel's mix (integer, select, move and fp64 "
-                           "instructions beside fp32) issues faster than the single-operation microbenchmark: "
-                           "the pass runs at the VALU issue limit",
+                           "and clock",
                    "kernel": "fwrs::frame_kernel<4, 3, true> (Eq. 7)"}
         eq7 = {"entry": "fwrs_push_frame_resolve (FWRS_BIAS_FULL)", "frames": n_frames,
                "ms_per_frame": f_ms / n_frames,
                "value": spec.pixels * n_frames / (f_ms / 1e3) / 1e9, "unit": "Gpixel-updates/s",
                "ms_per_frame_p50": float(np.percentile(f_per, 50)),
                "ms_per_frame_p99": float(np.percentile(f_per, 99)),
-               "hbm": {"achieved": f_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": f_ach / HBM_PEAK_GBPS,
-                       "kernel_ms_avg": f_kern, "bytes_per_pixel_update": f_B,
-                       "slot_takes_per_pixel_update": f_rbar},
-               "roofline": alu}
+               "roofline": {"bound": "hbm", "achieved": f_ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                            "frac": f_ach / HBM_PEAK_GBPS,
+                            "traffic": traffic_from_counters(
+                                e7_kernel, spec.pixels, {"steps": K, "frames_per_step": fps, "frames": n_frames},
+                                EQ7_COUNTERS),
+                            "kernel_ms_avg": f_kern, "bytes_per_pixel_update": f_B,
+                            "slot_takes_per_pixel_update": f_rbar},
+               "valu": alu}
         log(f"eq7: {f_ms / n_frames:.4f} ms/frame")
 
     ablation = None if args.no_ablations else ablations(dev, stream, spec, frames, tile)

@@ -421,6 +421,25 @@ __host__ __device__ __forceinline__ float cie94(const float3& ref, const float3&
     return sqrtf((dL * dL + tC * tC) + dH2 / (SH * SH));
 }
 
+// A sample whose colour compares equal to the new pixel's, component by
+// component, has the same Lab triple: the inputs are the same binary32 values
+// up to the sign of a zero, and a zero component leaves the same Lab (a zero
+// product adds nothing to a non-zero sum, and a zero X, Y or Z lands on the
+// linear segment's 4/29).  CIE94 of a colour with itself is then exactly 0
+// (dL, dC, da, db and dH2 are 0, so is the root), and so is |dL|.  This needs
+// L* and the chroma finite, which components of magnitude below 2^24 ensure
+// (a* and b* stay below 2^40, their squares far from overflow); other colours,
+// and NaN, which compares unequal, take the full evaluation.
+__host__ __device__ __forceinline__ bool lab_bounded(float c0, float c1, float c2)
+{
+    return fabsf(c0) < 0x1p24f && fabsf(c1) < 0x1p24f && fabsf(c2) < 0x1p24f;
+}
+
+__host__ __device__ __forceinline__ bool same_colour(const float4& s, float c0, float c1, float c2)
+{
+    return s.y == c0 && s.z == c1 && s.w == c2;
+}
+
 // Eq. 7: (W1 (1 - |dL|)) (1 - w / (W1 + w)).
 __device__ __forceinline__ float bias_eq7(float W1, float w, float dl)
 {
@@ -428,6 +447,13 @@ __device__ __forceinline__ float bias_eq7(float W1, float w, float dl)
     const float q = w / total;
     const float survive = 1.0f - q;
     return (W1 * (1.0f - dl)) * survive;
+}
+
+// |dL| = min(1, dE94 / 100) of a sample of colour (r, g, b) against the new
+// pixel, given the new pixel's Lab.
+__device__ __forceinline__ float delta_l(float r, float g, float b, const float3& lab_new)
+{
+    return fminf(1.0f, div_const(cie94(rgb_to_lab(r, g, b), lab_new), 100.0f, 0x1.47ae14p-7f));
 }
 
 }  // namespace fwrs

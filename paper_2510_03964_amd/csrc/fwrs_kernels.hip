@@ -555,8 +555,18 @@ __device__ __forceinline__ uint32_t pixel_per_slot(const FrameDesc& d, uint32_t 
     const float dy = ((float)y + 0.5f) - d.gy;
     const float w = weight_eq4(d.c, dx * dx + dy * dy, lv);
     const bool aes = d.bias == kAes;
+    // Eq. 7: a slot whose sample has the new pixel's colour has |dL| = 0 exactly
+    // (same_colour), so its Lab and CIE94 are not evaluated, nor the new
+    // pixel's Lab when that holds for every slot.
+    const bool bounded = lab_bounded(c0, c1, c2);
+    uint32_t same = 0u;
+    if (K && !aes) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (bounded && same_colour(r[j], c0, c1, c2)) same |= 1u << j;
+    }
     float3 lab_new = make_float3(0.f, 0.f, 0.f);
-    if (!aes) lab_new = rgb_to_lab(c0, c1, c2);
+    if (!aes && (!K || same != (1u << R) - 1u)) lab_new = rgb_to_lab(c0, c1, c2);
     const float4 fresh = make_float4(w, c0, c1, c2);
 
     float S = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f;
@@ -577,7 +587,9 @@ __device__ __forceinline__ uint32_t pixel_per_slot(const FrameDesc& d, uint32_t 
             s = take ? kn : W1;
         } else {
             // Eq. 7 against this slot's sample, then the slot's Alg. 2 decision
-            const float dl = fminf(1.0f, div_const(cie94(rgb_to_lab(v.y, v.z, v.w), lab_new), 100.0f, 0x1.47ae14p-7f));
+            const bool same_j = K ? ((same >> j) & 1u) != 0u : bounded && same_colour(v, c0, c1, c2);
+            float dl = 0.0f;
+            if (!same_j) dl = delta_l(v.y, v.z, v.w, lab_new);
             const float W1b = bias_eq7(W1, w, dl);
             s = W1b + w;
             take = unit_variate(word) * s > W1b;
@@ -913,8 +925,17 @@ __device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_
     const float dy = ((float)y + 0.5f) - d.gy;
     const float w = weight_eq4(d.c, dx * dx + dy * dy, lv);
     const float4 fresh = make_float4(w, c0, c1, c2);
+    // Eq. 7: a slot whose sample has the new pixel's colour has |dL| = 0 exactly
+    // (same_colour); neither Lab is evaluated for it
+    const bool bounded = lab_bounded(c0, c1, c2);
+    uint32_t same = 0u;
+    if (K && PER_SLOT && !aes) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (bounded && same_colour(rv[j], c0, c1, c2)) same |= 1u << j;
+    }
     float3 lab_new = make_float3(0.f, 0.f, 0.f);
-    if (PER_SLOT && !aes) lab_new = rgb_to_lab(c0, c1, c2);
+    if (PER_SLOT && !aes && (!K || same != (1u << R) - 1u)) lab_new = rgb_to_lab(c0, c1, c2);
     const float W1b = PER_SLOT ? 0.f : bias_shared(W1, w, d.bias, d.c.decay);
     const float s = W1b + w;
 
@@ -953,7 +974,9 @@ __device__ __forceinline__ uint32_t pixel_reproject(const ReprojDesc& r, uint32_
             st<kNtWsumSt>(d.wsum + (size_t)p * (size_t)kk + j, take ? kn : Wj);
         } else {
             if (PER_SLOT) {
-                const float dl = fminf(1.0f, div_const(cie94(rgb_to_lab(v.y, v.z, v.w), lab_new), 100.0f, 0x1.47ae14p-7f));
+                const bool same_j = K ? ((same >> j) & 1u) != 0u : bounded && same_colour(v, c0, c1, c2);
+                float dl = 0.0f;
+                if (!same_j) dl = delta_l(v.y, v.z, v.w, lab_new);
                 W1j = bias_eq7(Wj, w, dl);
                 sj = W1j + w;
                 st<kNtWsumSt>(d.wsum + (size_t)p * (size_t)kk + j, sj);

@@ -30,6 +30,11 @@ float dev_de94(const float* ref, const float* x)
     return fwrs::cie94(make_float3(ref[0], ref[1], ref[2]), make_float3(x[0], x[1], x[2]));
 }
 
+int dev_lab_bounded(float r, float g, float b)
+{
+    return fwrs::lab_bounded(r, g, b) ? 1 : 0;
+}
+
 // Compares fwrs::cube_root with `reference` on every binary32 whose bit pattern
 // is in [lo, hi) with the given stride, on `threads` threads.  Returns the
 // number of inputs whose results differ bit for bit; *first is the bit pattern

@@ -9,7 +9,9 @@ itself is checked on the GPU by tests/test_gpu_devmath.py):
   - the cube root of Eq. 7's Lab conversion (Sec. 4.3) for every binary32 in the Lab curve's
     cube-root range [(6/29)^3, 2^8), and every 61st positive normal binary32 beyond;
   - log2 of the A-ES variate (Sec. 3.1) for all 2^24 variates;
-  - Lab and the CIE94 difference on random colours, standard-range and HDR.
+  - Lab and the CIE94 difference on random colours, standard-range and HDR;
+  - that a colour compared with an equal one (up to the sign of zeros) gives CIE94 exactly 0
+    within the bound under which Eq. 7's kernels skip that evaluation, and not always beyond it.
 The oracle's versions are the plain definitions (the nearest binary32 to the real cube root and
 to the real log2), pinned in test_oracle_eq7.py and test_oracle_ablations.py.
 """
@@ -41,6 +43,8 @@ def devmath(tmp_path_factory):
     L.dev_lab.argtypes = [C.c_float, C.c_float, C.c_float, C.POINTER(C.c_float)]
     L.dev_de94.restype = C.c_float
     L.dev_de94.argtypes = [C.POINTER(C.c_float), C.POINTER(C.c_float)]
+    L.dev_lab_bounded.restype = C.c_int
+    L.dev_lab_bounded.argtypes = [C.c_float, C.c_float, C.c_float]
     return L
 
 
@@ -92,3 +96,39 @@ def test_lab_and_cie94_equal_oracle(devmath, oracle_mod):
         rb[:] = b[i].tolist()
         got_de[i] = devmath.dev_de94(ra, rb)
     np.testing.assert_array_equal(got_de.view(np.uint32), want_de.view(np.uint32))
+
+
+def test_equal_colours_have_zero_cie94_within_the_bound(devmath):
+    """Eq. 7's kernels take |dL| = 0 without evaluating Lab and CIE94 when a sample's colour equals
+    the new pixel's component by component and every component is below 2^24 in magnitude.  Here
+    the device functions (host build) give the same: equal Lab triples, bit for bit, when zeros
+    change sign, and CIE94 exactly +0, on colours spread over every binade up to 2^24, signed zeros
+    and the components that maximise a* and b*.  Beyond the bound the chroma's squares can overflow
+    and CIE94 of a colour with itself be NaN (so |dL| = 1), which is why the bound exists."""
+    rng = np.random.default_rng(31)
+    n = 20000
+    mag = np.exp2(rng.uniform(-30.0, 24.0, size=(n, 3))).astype(np.float32)
+    mag = np.minimum(mag, np.float32(16777215.0))
+    col = np.where(rng.random((n, 3)) < 0.5, -mag, mag).astype(np.float32)
+    col[rng.random((n, 3)) < 0.15] = 0.0
+    B = np.float32(16777215.0)
+    extremes = np.array([[B, -B, 0.0], [-B, B, 0.0], [0.0, B, -B], [B, 0.0, -B], [-B, -B, B], [B, B, B],
+                         [-B, -B, -B], [0.0, 0.0, 0.0]], np.float32)
+    col = np.concatenate([col, extremes])
+    a = (C.c_float * 3)()
+    b = (C.c_float * 3)()
+    for c in col:
+        flipped = np.where(c == 0.0, np.where(np.signbit(c), np.float32(0.0), np.float32(-0.0)), c)
+        assert devmath.dev_lab_bounded(*map(float, c)) == 1
+        devmath.dev_lab(*map(float, c), a)
+        devmath.dev_lab(*map(float, flipped), b)
+        la = np.frombuffer(a, np.float32).copy()
+        lb = np.frombuffer(b, np.float32).copy()
+        assert np.all(np.isfinite(la)), c
+        np.testing.assert_array_equal(la.view(np.uint32), lb.view(np.uint32), err_msg=str(c))
+        d = np.float32(devmath.dev_de94(a, b))
+        assert d == 0.0 and not np.signbit(d), (c, d)
+    assert devmath.dev_lab_bounded(16777216.0, 0.0, 0.0) == 0
+    assert devmath.dev_lab_bounded(0.0, float("nan"), 0.0) == 0
+    devmath.dev_lab(1e30, -1e30, 0.5, a)
+    assert np.isnan(devmath.dev_de94(a, a))

@@ -14,6 +14,8 @@ import torch
 import oracle
 from paper_2510_03964_amd import fwrs, synth
 
+import edge_colours
+
 pytestmark = pytest.mark.gpu
 COLOR_TOL = 1e-5
 
@@ -862,6 +864,36 @@ def test_eq7_static_scene_equals_eq6(dev):
     assert torch.equal(outs[0], outs[1])
     np.testing.assert_array_equal(states[0].idx, states[1].idx)
     np.testing.assert_array_equal(states[0].wslot, states[1].wslot)
+
+
+@pytest.mark.parametrize("k", [4, 8, 3])
+def test_eq7_repeated_and_edge_colours(dev, k):
+    """Eq. 7 on colours that repeat across frames, drawn from edge values (signed zeros, a denormal,
+    2^24 and its neighbour below, +-3e7, +-1e30 whose Lab is not finite): samples equal to the new
+    pixel and unequal ones share waves, and whole waves hold only equal ones (the left half).
+    Every state plane bit-exact with the oracle each frame, through plain calls and ticks; the
+    resolve within 1e-5 of the oracle's, relative to the pixel's largest slot colour."""
+    w, h, n = 96, 40, 8
+    frames = edge_colours.palette_frames(w, h, n, dev, seed=10 + k)
+    spec = synth.StreamSpec(w, h, k, n, 8.0, 20.0, 1.0, 2, 3.0, stream_id=k)
+    p, q = _params(spec, fwrs.BIAS_FULL)
+    stream = torch.cuda.current_stream()
+    plain = fwrs.Reservoir(w, h, k, p, stream=stream)
+    ticked = fwrs.Reservoir(w, h, k, p, stream=stream)
+    orc = oracle.Oracle(w, h, k, q)
+    out = torch.empty((h, w, 3), device=dev)
+    out_t = torch.empty((h, w, 3), device=dev)
+    for t, (c, lev, gx, gy) in enumerate(frames):
+        plain.step(c, lev, gx, gy, out)
+        fwrs.tick([(ticked, c, lev, gx, gy, out_t)], stream=stream)
+        orc.push(c.cpu().numpy(), lev.cpu().numpy(), gx, gy)
+        torch.cuda.synchronize()
+        so = orc.state()
+        _compare_state(plain.download(), so, f"frame {t} k={k}")
+        _compare_state(ticked.download(), so, f"tick, frame {t} k={k}")
+        err = np.abs(out.cpu().numpy().astype(np.float64) - orc.resolve()).max(axis=2)
+        assert np.all(err <= COLOR_TOL * edge_colours.resolve_scale(so.col)), f"frame {t}"
+        assert torch.equal(out, out_t)
 
 
 def test_eq7_caller_arena_is_sized_by_mode(dev):

@@ -12,6 +12,8 @@ import torch
 import oracle
 from paper_2510_03964_amd import fwrs, synth
 
+import edge_colours
+
 pytestmark = pytest.mark.gpu
 COLOR_TOL = 1e-5
 TOL = 0.1
@@ -110,6 +112,24 @@ def test_integer_subpixel_and_invalid_motion(dev):
     motions = [None, None, (3.0, -2.0), (0.5, 0.0), (0.5 + 2 ** -10, 0.0), (-0.5, 0.0), (float("nan"), 0.0),
                None, (1e30, 1e30)]
     _run(dev, spec, 9, frames=_still_frames(dev, spec, 9, motions))
+
+
+@pytest.mark.parametrize("k", [4, 8, 3])
+def test_eq7_repeated_and_edge_colours(dev, k):
+    """Eq. 7 through the reprojecting pass with a still camera, on colours that repeat across frames
+    and edge values (signed zeros, a denormal, 2^24 and its neighbour below, +-3e7, +-1e30 whose Lab
+    is not finite); a sub-pixel pan on frame 4 moves every sample.  State planes bit-exact each
+    frame (the resolve of such colours is compared by the plain-pass test)."""
+    w, h, n = 96, 40, 8
+    still = edge_colours.palette_frames(w, h, n, dev, seed=20 + k)
+    frames = []
+    for t, (c, lev, gx, gy) in enumerate(still):
+        mv = torch.zeros((h, w, 2), device=dev)
+        if t == 4:
+            mv[..., 0] = 0.5
+        frames.append((c, lev, mv.contiguous(), torch.full((h, w), 5.0, device=dev), gx, gy))
+    spec = synth.StreamSpec(w, h, k, n, 8.0, 20.0, 1.0, 2, 3.0, stream_id=k)
+    _run(dev, spec, n, bias=fwrs.BIAS_FULL, frames=frames, resolve=False)
 
 
 def test_update_only_then_resolve(dev):
