@@ -289,12 +289,24 @@ __device__ __forceinline__ uint32_t pixel(const FrameDesc& d, uint32_t x, uint32
     const float4 fresh = make_float4(w, c0, c1, c2);
     if (K) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            if ((tk >> j) & 1u) {
-                r[j] = fresh;
+        for (int j = 0; j < R; ++j)
+            if ((tk >> j) & 1u) r[j] = fresh;
+        if constexpr (K >= 8) {
+            // Each lane's next replaced slot per store instruction: a wave issues
+            // as many as its pixels' most replacements instead of one per slot,
+            // nearly all lanes masked off (3% faster at k = 8, 6% slower at k = 4).
+            for (uint32_t m = tk; m != 0u; m &= m - 1u) {
+                const uint32_t j = (uint32_t)__builtin_ctz(m);
                 st4<kNtRecSt>(rec + j, fresh);
                 st<kNtIdxSt>(idx + j, d.t);
             }
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if ((tk >> j) & 1u) {
+                    st4<kNtRecSt>(rec + j, fresh);
+                    st<kNtIdxSt>(idx + j, d.t);
+                }
         }
     }
 
