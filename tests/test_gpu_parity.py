@@ -324,7 +324,8 @@ def test_stats_count_every_slot_replacement(dev):
     assert updates == spec.frames * spec.pixels
 
 
-@pytest.mark.parametrize("bias", [fwrs.BIAS_BERNOULLI, fwrs.BIAS_FULL])
+@pytest.mark.parametrize("bias", [fwrs.BIAS_BERNOULLI, fwrs.BIAS_FULL, fwrs.AES, fwrs.BIAS_MEMORYLESS,
+                                  fwrs.BIAS_NONE])
 def test_4k_bands_and_whole_frame_properties(dev, bias):
     """3840x2160, k = 4, in the launch configuration the benchmark times: bands of rows
     (through the gaze, the periphery and the image edges) against the oracle every few frames,
