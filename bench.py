@@ -399,6 +399,11 @@ def ablations(dev, stream, spec, frames, tile, sample_every: int = 10) -> dict:
         if tile:
             res.set_tile(*tile)
         total_ms, per = timed_run(res, frames, out, stream, res.step)
+        takes, _, updates = res.stats()
+        rbar = takes / updates
+        per_slot = mode in (fwrs.BIAS_FULL, fwrs.AES)
+        B = bytes_per_update_eq7(k, rbar) if per_slot else bytes_per_update(k, rbar)
+        gbps = N * B / (float(per.mean()) / 1e3) / 1e9
         res.reset()
         view = res.state_view()
         ws = view.wsum_slots
@@ -419,9 +424,15 @@ def ablations(dev, stream, spec, frames, tile, sample_every: int = 10) -> dict:
         del arena
         result[name] = {"bias_mode": mode, "ms_per_frame": total_ms / len(frames),
                         "kernel_ms_avg": float(per.mean()),
+                        "hbm": {"achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+                                "bytes_per_pixel_update": B, "slot_takes_per_pixel_update": rbar,
+                                "bytes_model": ("25 + 24k + 20r (per-slot sums, every record read)" if per_slot
+                                                else "41 + 16k + 20r (whole trace; counts the record reads that the resolve "
+                                                     "plane avoids from frame 32, so frac is an effective bandwidth and "
+                                                     "exceeds 1 where few pixels change)")},
                         "level0_retention_mean": float(np.mean(fracs)) if fracs else None,
                         "level0_retention_last": fracs[-1] if fracs else None}
-        log(f"ablation {name}: {total_ms / len(frames):.4f} ms/frame, level-0 retention "
+        log(f"ablation {name}: {total_ms / len(frames):.4f} ms/frame, {gbps / HBM_PEAK_GBPS:.3f} of HBM, level-0 retention "
             f"{result[name]['level0_retention_mean']:.4f}")
     result["definition"] = ("fraction of slots holding a weight-1 (level-0) sample over the pixels that were "
                             f"in the fovea earlier but are not now, sampled every {sample_every} frames")
