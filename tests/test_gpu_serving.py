@@ -35,7 +35,7 @@ def test_each_session_alone_equals_in_the_mix(dev, executor, max_group):
     of a session (one group in the batched executor), and the outputs are still those of the
     session run alone."""
     sizes = ((128, 64), (96, 48))
-    fps = (150.0, 240.0) if max_group == 1 else (6000.0, 9000.0)
+    fps = (150.0, 240.0) if max_group == 1 else (20000.0, 30000.0)
     sessions = serve.poisson_sessions(n=6, rate_per_s=20.0, seed=11, lifetime_s=(0.15, 0.4), sizes=sizes,
                                       ks=(2, 3, 4, 8), fps=fps)
     if max_group > 1:
